@@ -1,0 +1,174 @@
+/*
+ * C ABI of the MI355X (gfx950) MGRIT solver for the 2-D Riesz space-fractional
+ * diffusion equation discretised by linear finite elements in space and time
+ * (Yue, Shu, Xu, Bu, Pan: "Parallel-in-Time with Fully Finite Element Multigrid
+ * for 2-D Space-fractional Diffusion Equations", arXiv 1805.06688).
+ *
+ * Problem (eqs. 1.1-1.3): u_t = K_x d^{2b}u/d|x|^{2b} + K_y d^{2g}u/d|y|^{2g} + f on
+ * (a,b) x (c,d), u = 0 on the boundary, u(., 0) = psi_0, 1/2 < beta, gamma < 1.
+ * One time step (eq. chp-02-03):
+ *     [M_h + tau_n/2 A_h] U_n = F_n + [M_h - tau_n/2 A_h] U_{n-1},  A_h = K_x A_x + K_y A_y,
+ * with M_h, A_x, A_y the block matrices printed in Section 2.  The space-time
+ * system (eq. ode-03) is solved by MGRIT (Algorithm 3.1) with FCF- or
+ * F-relaxation; every spatial solve is conjugate gradients (Section 3.2).
+ *
+ * Layout of every grid array ("slice"): n_y rows of n_x doubles, x fastest
+ * (the paper's node order), n_x = Mx - 1, n_y = My - 1 interior nodes.
+ * Space-time arrays are [count][n_y][n_x], contiguous.
+ *
+ * Memory: `mem` = MGRIT_MEM_DEVICE means every array pointer is a device
+ * pointer valid on the handle's stream; MGRIT_MEM_HOST means host memory
+ * (copied in and out inside the call).  The caller owns every array; inputs are
+ * only read.  A handle owns its device memory and is not thread-safe; distinct
+ * handles are independent.  All work is ordered on the stream given at setup
+ * (NULL = the default stream); calls return after the stream has finished.
+ *
+ * Return codes: MGRIT_OK (0); negative = error, nothing written except where
+ * stated; positive = finished without meeting the tolerance, outputs written.
+ * mgrit_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef MGRIT_H
+#define MGRIT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MGRIT_OK          0
+#define MGRIT_EINVAL     (-1)   /* invalid argument (ranges below)                       */
+#define MGRIT_ENOMEM     (-2)   /* device or host allocation failed                      */
+#define MGRIT_EHIP       (-3)   /* a HIP runtime call failed                             */
+#define MGRIT_ENOCONV     1     /* max_iter reached; last iterate written, stats filled  */
+#define MGRIT_EDIVERGED   2     /* residual grew beyond divergence_factor x initial      */
+
+#define MGRIT_MEM_HOST    0
+#define MGRIT_MEM_DEVICE  1
+
+#define MGRIT_RELAX_F     0
+#define MGRIT_RELAX_FCF   1
+
+/* Coarse-level propagator (levels >= 1).  CN is eq. (equ-03-02): Crank-Nicolson
+ * with the coarse step.  BE: backward Euler with the coarse step.  CN2: two
+ * Crank-Nicolson half steps.  The choice changes the convergence rate only;
+ * the fixed point is sequential stepping in every case. */
+#define MGRIT_COARSE_CN   0
+#define MGRIT_COARSE_BE   1
+#define MGRIT_COARSE_CN2  2
+
+#define MGRIT_PREC_FP64   0   /* every operator application in FP64 (FP64 MFMA)        */
+
+typedef struct {
+    double beta, gamma;     /* fractional orders, 1/2 < beta, gamma < 1 (eq. 1.1)        */
+    double Kx, Ky;          /* diffusion coefficients, > 0                               */
+    double a, b, c, d;      /* domain (a,b) x (c,d), a < b, c < d                        */
+    int Mx, My;             /* mesh intervals per direction (h_x = (b-a)/Mx), >= 2       */
+    int Nt;                 /* number of time steps, >= 1                                */
+    const double* t;        /* host array of Nt+1 times, t[0] = 0 < t[1] < ... < t[Nt]   */
+} mgrit_problem;
+
+typedef struct {
+    int m;                  /* coarsening factor, >= 2                                   */
+    int max_levels;         /* levels including the finest, >= 2                         */
+    int relax;              /* MGRIT_RELAX_F or MGRIT_RELAX_FCF                          */
+    int coarse;             /* MGRIT_COARSE_*                                            */
+    int precision;          /* MGRIT_PREC_*                                              */
+    int max_iter;           /* MGRIT iterations, >= 1                                    */
+    double tol_abs;         /* stop when the discrete L2 C-point residual norm < tol_abs */
+    double cg_rtol;         /* CG stops when ||r||_2 <= cg_rtol ||b||_2                  */
+    int cg_maxit;           /* CG iteration cap per solve                                */
+    double divergence_factor; /* EDIVERGED when a norm exceeds this x the first (0: off) */
+} mgrit_options;
+
+typedef struct {
+    int iterations;             /* MGRIT iterations carried out                         */
+    int converged;              /* 1 when the tolerance was met                         */
+    int levels;                 /* levels in the hierarchy                              */
+    long long phi_applications; /* propagator applications (one per slice)              */
+    long long cg_iterations;    /* CG iterations summed over all slices                 */
+    double residual_history[64];/* level-0 residual norm per iteration (first 64)       */
+} mgrit_stats;
+
+typedef struct mgrit_handle mgrit_handle;
+
+/* Fill `opt` with defaults: m = 8, max_levels = 30, FCF, CN, FP64, max_iter = 100,
+ * tol_abs = 1e-9, cg_rtol = 1e-9 (the paper's tolerances, Section 3.2),
+ * cg_maxit = 10000, divergence_factor = 0. */
+void mgrit_default_options(mgrit_options* opt);
+
+/* Validate the problem, evaluate the Toeplitz generating sequences of Section 2
+ * (entries of A_1^rho and A_2^rho, evaluated in 113-bit floating point and
+ * rounded once to FP64) and the scales c_x, c_y, build the level hierarchy
+ * t^(l+1) = t^(l)[::m] (Section 3.1) and allocate device memory.
+ * `stream` is a hipStream_t or NULL.  Errors: EINVAL (beta or gamma outside
+ * (1/2,1), K <= 0, a >= b or c >= d, Mx or My < 2, Nt < 1, t not strictly
+ * increasing from 0, m < 2, max_levels < 2, unknown enum), ENOMEM, EHIP. */
+int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* stream,
+                mgrit_handle** out);
+
+/* Solve the space-time system (eq. ode-03) by MGRIT V-cycles (Algorithm 3.1).
+ * F: [Nt][n_y][n_x] load vectors F_1..F_Nt of eq. (chp-02-03) (NULL = zero load);
+ * psi0: [n_y][n_x] nodal initial values U_0; U_init: optional [Nt+1][n_y][n_x]
+ * initial iterate (NULL = zero; its slice 0 is ignored); U: [Nt+1][n_y][n_x]
+ * output, U[0] = psi0.  Returns OK, ENOCONV or EDIVERGED (U written in all
+ * three cases), or a negative error.  `st` may be NULL. */
+int mgrit_solve(mgrit_handle* h, const double* F, const double* psi0, const double* U_init,
+                double* U, int mem, mgrit_stats* st);
+
+/* Exactly `iterations` MGRIT iterations (relaxation, C-point residual, coarse
+ * solve, C-point correction) followed by a final F-relaxation, with no stop
+ * test: the iterate the algorithm has after that many steps.  Arguments as in
+ * mgrit_solve. */
+int mgrit_iterate(mgrit_handle* h, const double* F, const double* psi0, const double* U_init,
+                  int iterations, double* U, int mem, mgrit_stats* st);
+
+/* Sequential time stepping U_n = Phi_n(U_{n-1}), n = 1..Nt (eq. chp-02-03), the
+ * result MGRIT converges to.  Arguments as in mgrit_solve. */
+int mgrit_sequential(mgrit_handle* h, const double* F, const double* psi0, double* U, int mem,
+                     mgrit_stats* st);
+
+/* Batched propagator of one level (eqs. equ-03-01, equ-03-02):
+ *   level 0:  u_out[s] = [M + tau/2 A]^{-1} ([M - tau/2 A] u_in[s] + g[s])
+ *             with tau = t[k] - t[k-1], k = step[s] (g = load F_k, may be NULL);
+ *   level l:  u_out[s] = Psi^(l)_k u_in[s] + g[s] with the coarse propagator
+ *             of the options and the step of level l (g may be NULL).
+ * step: host array of nslices step indices, 1 <= k <= N_l.  u_in, g, u_out:
+ * [nslices][n_y][n_x]; u_out may not overlap u_in.  Each slice is solved by
+ * CG from the start vector u_in[s]. */
+int mgrit_propagate(mgrit_handle* h, int level, const int* step, int nslices,
+                    const double* u_in, const double* g, double* u_out, int mem);
+
+/* Operator application (the matrix-vector product inside every CG iteration):
+ *   out[s] = add[s] + sign * ( M_h v[s] + theta[s] A_h v[s] ),
+ * theta: host array of nslices values, sign = +1 or -1, add may be NULL.
+ * v, add, out: [nslices][n_y][n_x]; out may not overlap v. */
+int mgrit_apply(mgrit_handle* h, int nslices, const double* theta, double sign,
+                const double* v, const double* add, double* out, int mem);
+
+/* Copy the FP64 generating sequences the device uses, already multiplied by
+ * K c: seq_x = [t_x (n_x) | u_x (n_x) | w_x (n_x)], seq_y likewise with n_y,
+ * where t[l] is the distance-l entry of A_1, u[l] the entry (k, k+l) and w[l]
+ * the entry (k+l, k) of A_2 (w[0] repeats the diagonal); and the scalars
+ * c_x, c_y.  Host buffers of 3 n_x and 3 n_y doubles. */
+int mgrit_sequences(const mgrit_handle* h, double* seq_x, double* seq_y, double* cx, double* cy);
+
+/* Host-only helper (no GPU needed): the generating sequences of A_1^rho and A_2^rho
+ * (Section 2) for n interior nodes, each entry evaluated in IEEE binary128 and
+ * rounded once to FP64.  t[l]: entry of A_1 at distance l; u[l]: entry (k, k+l)
+ * of A_2; w[l]: entry (k+l, k) of A_2, l >= 1 (w[0] = u[0]).  Arrays of n doubles,
+ * caller-owned; 1/2 < rho <= 1 is not checked here. */
+void mgrit_toeplitz_sequences(double rho, int n, double* t, double* u, double* w);
+
+/* Host-only helper: h_par^(1-2 rho) h_perp / (2 cos(rho pi) Gamma(5 - 2 rho)), the
+ * scalar in front of the block stiffness matrix (c_x with h_par = h_x). */
+double mgrit_stiffness_scale(double rho, double h_par, double h_perp);
+
+/* Number of time points per level; writes up to `cap` values, returns the level count. */
+int mgrit_levels(const mgrit_handle* h, int* n_per_level, int cap);
+
+void mgrit_destroy(mgrit_handle* h);
+const char* mgrit_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGRIT_H */

@@ -1,0 +1,845 @@
+// Host driver of the MGRIT solver: the C ABI declared in include/mgrit.h.
+//
+// Algorithm 3.1 (MGRIT V-cycle) over the space-time system (eq. ode-03):
+// every relaxation sweep, C-point residual and coarsest solve is a *batch* of
+// independent propagator applications, one per coarse interval, handed to the
+// batched CG solver in one set of kernel launches (slices stacked along the
+// grid of workgroups).  Readings of the paper implemented here:
+//   * levels l = 0..L-1, level L-1 solved by sequential stepping; coarsening
+//     stops when the next level would hold fewer than two intervals;
+//   * C-points are the multiples of m; trailing F-points are F-relaxed only;
+//   * linear correction scheme with the injected residual in solution space,
+//     r_k = Phi_km(U_km-1) - U_km, zero start on coarse levels (step 3);
+//   * Remark 3.1: C-point-only correction on level 0; injection plus
+//     F-relaxation (the ideal interpolation) on coarser levels;
+//   * stop test after the level-0 relaxation on the discrete L2 norm
+//     sqrt(h_x h_y sum_k ||r_k||^2) (Section 3.2's "discrete L2 sense");
+//   * CG (Section 3.2) stops on ||r||_2 <= rtol ||b||_2 and starts from the
+//     propagated state; a zero right-hand side gives the zero vector.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/mgrit.h"
+#include "mgrit_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIPCHK(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (hipError_t)(expr);                                                            \
+        if (e_ != hipSuccess) return fail(MGRIT_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define CHK(expr)                   \
+    do {                            \
+        int rc_ = (expr);           \
+        if (rc_ != 0) return rc_;   \
+    } while (0)
+
+// A batch of propagator applications: one or two passes (two for the
+// two-half-step coarse propagator), descriptors resident on the device.
+struct Pass {
+    int S = 0;
+    std::vector<PropDesc> h;
+    PropDesc* d = nullptr;
+};
+
+struct Batch {
+    Pass pass[2];
+    int npass = 0;
+    int S() const { return pass[0].S; }
+};
+
+struct IndexPair {           // y[yi[s]] (+)= a x[xi[s]]
+    int S = 0;
+    int* yi = nullptr;
+    int* xi = nullptr;
+};
+
+struct Level {
+    int N = 0;                       // intervals
+    std::vector<int> fine;           // level-0 index of each point
+    std::vector<double> tau;         // tau[k], k = 1..N
+    double* U = nullptr;             // [N+1] slices (levels >= 1; level 0 uses the caller's array)
+    double* G = nullptr;             // [N+1] slices (levels >= 1)
+    std::vector<Batch> frelax;       // F-relaxation, one batch per F sub-step
+    Batch crelax;                    // C-relaxation
+    Batch resid;                     // residual propagation into the next level's G
+    std::vector<Batch> step_list;    // per-step batches of one slice (coarsest level / sequential)
+    IndexPair correct;               // U[km] += E[k]
+    IndexPair subtract;              // Gnext[k] -= U[km]
+    int* all_idx = nullptr;          // 0..N (zeroing)
+};
+
+}  // namespace
+
+struct mgrit_handle {
+    mgrit_problem prob;
+    mgrit_options opt;
+    std::vector<double> t;
+    hipStream_t stream = nullptr;
+    Geom geom;
+    Seqs seqs;
+    double* d_seq = nullptr;                 // T1x | A2x | T1y | A2y
+    std::vector<double> host_seq_x, host_seq_y;
+    double cx = 0, cy = 0;
+    std::vector<Level> lv;
+    int Smax = 0;
+    // CG workspace
+    double *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *tmp = nullptr;
+    double *pbb = nullptr, *prr[2] = {nullptr, nullptr}, *ppq = nullptr, *pnorm = nullptr;
+    double* bb = nullptr;
+    int* act[2] = {nullptr, nullptr};
+    int* iters = nullptr;
+    int* h_act = nullptr;                    // pinned
+    int* h_iters = nullptr;                  // pinned
+    double* h_norm = nullptr;                // pinned
+    long long phi_count = 0, cg_count = 0;
+    std::vector<void*> allocations;
+    // caller arrays of the current solve (level 0)
+    double* U0 = nullptr;
+    const double* F0 = nullptr;
+};
+
+namespace {
+
+int dmalloc(mgrit_handle* h, void** p, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail(MGRIT_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    h->allocations.push_back(*p);
+    return 0;
+}
+
+template <class T>
+int dalloc(mgrit_handle* h, T** p, size_t count) {
+    return dmalloc(h, (void**)p, count * sizeof(T));
+}
+
+int upload_pass(mgrit_handle* h, Pass& ps) {
+    ps.S = (int)ps.h.size();
+    if (ps.S == 0) return 0;
+    CHK(dalloc(h, &ps.d, ps.h.size()));
+    HIPCHK(hipMemcpy(ps.d, ps.h.data(), ps.h.size() * sizeof(PropDesc), hipMemcpyHostToDevice));
+    return 0;
+}
+
+int upload_pairs(mgrit_handle* h, IndexPair& ip, const std::vector<int>& y, const std::vector<int>& x) {
+    ip.S = (int)y.size();
+    if (ip.S == 0) return 0;
+    CHK(dalloc(h, &ip.yi, y.size()));
+    CHK(dalloc(h, &ip.xi, x.size()));
+    HIPCHK(hipMemcpy(ip.yi, y.data(), y.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ip.xi, x.data(), x.size() * sizeof(int), hipMemcpyHostToDevice));
+    return 0;
+}
+
+// Descriptor of one application of the level-l propagator from point k-1 to k,
+// reading slice `u`, writing slice `x`.  Returns one or two passes.
+void make_step(const mgrit_handle* h, int l, int k, int u, int x, int tmp_slot, Batch& b) {
+    const double tau = h->lv[l].tau[k];
+    PropDesc d;
+    d.u = u;
+    d.x = x;
+    d.f = -1;
+    d.g = -1;
+    if (l == 0) {
+        d.f = k - 1;                   // load F_k
+        d.theta_rhs = -0.5 * tau;
+        d.theta_lhs = 0.5 * tau;
+        b.pass[0].h.push_back(d);
+        b.npass = 1;
+        return;
+    }
+    d.g = k;                            // affine term G^(l)_k
+    if (h->opt.coarse == MGRIT_COARSE_BE) {
+        d.theta_rhs = 0.0;
+        d.theta_lhs = tau;
+        b.pass[0].h.push_back(d);
+        b.npass = 1;
+    } else if (h->opt.coarse == MGRIT_COARSE_CN2) {
+        PropDesc d1 = d, d2 = d;
+        d1.x = tmp_slot;
+        d1.g = -1;
+        d1.theta_rhs = -0.25 * tau;
+        d1.theta_lhs = 0.25 * tau;
+        d2.u = tmp_slot;
+        d2.theta_rhs = -0.25 * tau;
+        d2.theta_lhs = 0.25 * tau;
+        b.pass[0].h.push_back(d1);
+        b.pass[1].h.push_back(d2);
+        b.npass = 2;
+    } else {
+        d.theta_rhs = -0.5 * tau;
+        d.theta_lhs = 0.5 * tau;
+        b.pass[0].h.push_back(d);
+        b.npass = 1;
+    }
+}
+
+int upload_batch(mgrit_handle* h, Batch& b) {
+    for (int i = 0; i < b.npass; ++i) CHK(upload_pass(h, b.pass[i]));
+    return 0;
+}
+
+int build_levels(mgrit_handle* h) {
+    const int m = h->opt.m;
+    const int Nt = h->prob.Nt;
+    h->lv.clear();
+    Level l0;
+    l0.N = Nt;
+    l0.fine.resize(Nt + 1);
+    for (int i = 0; i <= Nt; ++i) l0.fine[i] = i;
+    h->lv.push_back(l0);
+    while ((int)h->lv.size() < h->opt.max_levels) {
+        const Level& pr = h->lv.back();
+        const int Nc = pr.N / m;
+        if (Nc < 2) break;
+        Level nl;
+        nl.N = Nc;
+        nl.fine.resize(Nc + 1);
+        for (int k = 0; k <= Nc; ++k) nl.fine[k] = pr.fine[k * m];
+        h->lv.push_back(nl);
+    }
+    if (h->lv.size() < 2) return fail(MGRIT_EINVAL, "time grid too short for one coarsening (Nt=%d, m=%d)", Nt, m);
+    for (Level& L : h->lv) {
+        L.tau.assign(L.N + 1, 0.0);
+        for (int k = 1; k <= L.N; ++k) L.tau[k] = h->t[L.fine[k]] - h->t[L.fine[k - 1]];
+    }
+    // batches
+    int smax = 1;
+    const int nl = (int)h->lv.size();
+    for (int l = 0; l < nl; ++l) {
+        Level& L = h->lv[l];
+        const bool coarsest = (l == nl - 1);
+        if (!coarsest) {
+            const int Nc = h->lv[l + 1].N;
+            L.frelax.assign(m - 1, Batch());
+            for (int j = 1; j < m; ++j) {
+                Batch& b = L.frelax[j - 1];
+                int slot = 0;
+                for (int c = 0; c + j <= L.N; c += m) make_step(h, l, c + j, c + j - 1, c + j, slot++, b);
+                smax = std::max(smax, (int)b.pass[0].h.size());
+            }
+            int slot = 0;
+            for (int k = 1; k <= Nc; ++k) make_step(h, l, k * m, k * m - 1, k * m, slot++, L.crelax);
+            slot = 0;
+            for (int k = 1; k <= Nc; ++k) make_step(h, l, k * m, k * m - 1, k, slot++, L.resid);
+            smax = std::max(smax, Nc);
+            std::vector<int> y, x;
+            for (int k = 0; k <= Nc; ++k) {
+                y.push_back(k * m);
+                x.push_back(k);
+            }
+            CHK(upload_pairs(h, L.correct, y, x));
+            std::vector<int> y2, x2;
+            for (int k = 1; k <= Nc; ++k) {
+                y2.push_back(k);
+                x2.push_back(k * m);
+            }
+            CHK(upload_pairs(h, L.subtract, y2, x2));
+        }
+        // single-step batches: for the coarsest level (E_k = Phi(E_k-1)) and for
+        // sequential stepping on level 0
+        if (coarsest || l == 0) {
+            L.step_list.assign(L.N, Batch());
+            for (int k = 1; k <= L.N; ++k) make_step(h, l, k, k - 1, k, 0, L.step_list[k - 1]);
+        }
+    }
+    h->Smax = smax;
+    for (int l = 0; l < nl; ++l) {
+        Level& L = h->lv[l];
+        for (Batch& b : L.frelax) CHK(upload_batch(h, b));
+        CHK(upload_batch(h, L.crelax));
+        CHK(upload_batch(h, L.resid));
+        if (!L.step_list.empty()) {
+            // one device array for all single-step descriptors (pass by pass)
+            const int np = L.step_list[0].npass;
+            for (int pi = 0; pi < np; ++pi) {
+                std::vector<PropDesc> all;
+                for (Batch& b : L.step_list) all.push_back(b.pass[pi].h[0]);
+                PropDesc* d = nullptr;
+                CHK(dalloc(h, &d, all.size()));
+                HIPCHK(hipMemcpy(d, all.data(), all.size() * sizeof(PropDesc), hipMemcpyHostToDevice));
+                for (size_t k = 0; k < L.step_list.size(); ++k) {
+                    L.step_list[k].pass[pi].S = 1;
+                    L.step_list[k].pass[pi].d = d + k;
+                }
+            }
+        }
+        std::vector<int> all(L.N + 1);
+        for (int i = 0; i <= L.N; ++i) all[i] = i;
+        CHK(dalloc(h, &L.all_idx, all.size()));
+        HIPCHK(hipMemcpy(L.all_idx, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice));
+        if (l > 0) {
+            CHK(dalloc(h, &L.U, (size_t)(L.N + 1) * h->geom.stride));
+            CHK(dalloc(h, &L.G, (size_t)(L.N + 1) * h->geom.stride));
+        }
+    }
+    return 0;
+}
+
+int build_sequences(mgrit_handle* h) {
+    const mgrit_problem& p = h->prob;
+    const int nx = p.Mx - 1, ny = p.My - 1;
+    const double hx = (p.b - p.a) / p.Mx, hy = (p.d - p.c) / p.My;
+    h->cx = mgrit_stiffness_scale(p.beta, hx, hy);
+    h->cy = mgrit_stiffness_scale(p.gamma, hy, hx);
+    h->host_seq_x.assign(3 * (size_t)nx, 0.0);
+    h->host_seq_y.assign(3 * (size_t)ny, 0.0);
+    mgrit_toeplitz_sequences(p.beta, nx, &h->host_seq_x[0], &h->host_seq_x[nx], &h->host_seq_x[2 * nx]);
+    mgrit_toeplitz_sequences(p.gamma, ny, &h->host_seq_y[0], &h->host_seq_y[ny], &h->host_seq_y[2 * ny]);
+    const double sx = p.Kx * h->cx, sy = p.Ky * h->cy;
+    for (double& v : h->host_seq_x) v *= sx;
+    for (double& v : h->host_seq_y) v *= sy;
+
+    Geom& g = h->geom;
+    const int offx = g.seq_off_x, offy = g.seq_off_y;
+    const size_t lx = 2 * (size_t)offx + 1, ly = 2 * (size_t)offy + 1;
+    std::vector<double> buf(2 * lx + 2 * ly, 0.0);
+    double* T1x = &buf[0];
+    double* A2x = T1x + lx;
+    double* T1y = A2x + lx;
+    double* A2y = T1y + ly;
+    const double* tx = &h->host_seq_x[0];
+    const double* ux = &h->host_seq_x[nx];
+    const double* wx = &h->host_seq_x[2 * nx];
+    for (int d = -(nx - 1); d <= nx - 1; ++d) {
+        T1x[offx + d] = tx[std::abs(d)];
+        A2x[offx + d] = d >= 0 ? ux[d] : wx[-d];
+    }
+    const double* ty = &h->host_seq_y[0];
+    const double* uy = &h->host_seq_y[ny];
+    const double* wy = &h->host_seq_y[2 * ny];
+    for (int d = -(ny - 1); d <= ny - 1; ++d) {
+        T1y[offy + d] = ty[std::abs(d)];
+        A2y[offy + d] = d >= 0 ? uy[d] : wy[-d];
+    }
+    CHK(dalloc(h, &h->d_seq, buf.size()));
+    HIPCHK(hipMemcpy(h->d_seq, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
+    h->seqs.T1x = h->d_seq;
+    h->seqs.A2x = h->d_seq + lx;
+    h->seqs.T1y = h->d_seq + 2 * lx;
+    h->seqs.A2y = h->d_seq + 2 * lx + ly;
+    return 0;
+}
+
+int alloc_workspace(mgrit_handle* h, int S) {
+    const size_t st = (size_t)h->geom.stride;
+    const size_t nt = (size_t)h->geom.ntiles;
+    CHK(dalloc(h, &h->b, S * st));
+    CHK(dalloc(h, &h->r, S * st));
+    CHK(dalloc(h, &h->p, S * st));
+    CHK(dalloc(h, &h->q, S * st));
+    if (h->opt.coarse == MGRIT_COARSE_CN2) CHK(dalloc(h, &h->tmp, S * st));
+    CHK(dalloc(h, &h->pbb, S * nt));
+    CHK(dalloc(h, &h->prr[0], S * nt));
+    CHK(dalloc(h, &h->prr[1], S * nt));
+    CHK(dalloc(h, &h->ppq, S * nt));
+    CHK(dalloc(h, &h->pnorm, S * nt));
+    CHK(dalloc(h, &h->bb, S));
+    CHK(dalloc(h, &h->act[0], S));
+    CHK(dalloc(h, &h->act[1], S));
+    CHK(dalloc(h, &h->iters, S));
+    HIPCHK(hipHostMalloc((void**)&h->h_act, S * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&h->h_iters, S * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&h->h_norm, S * nt * sizeof(double), hipHostMallocDefault));
+    return 0;
+}
+
+// Batched CG solve of one pass (S <= Smax slices).
+int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase, const double* fbase,
+             const double* gbase) {
+    const int S = ps.S;
+    if (S == 0) return 0;
+    if (S > h->Smax) return fail(MGRIT_EINVAL, "batch of %d slices exceeds workspace (%d)", S, h->Smax);
+    const Geom* g = &h->geom;
+    void* st = (void*)h->stream;
+    const double rtol2 = h->opt.cg_rtol * h->opt.cg_rtol;
+    HIPCHK(launch_rhs(g, &h->seqs, ps.d, S, ubase, fbase, h->b, h->pbb, st));
+    HIPCHK(launch_init_residual(g, &h->seqs, ps.d, S, ubase, h->b, h->r, h->prr[0], st));
+    HIPCHK(launch_cg_start(g, ps.d, S, ubase, xbase, h->r, h->p, h->pbb, h->prr[0], rtol2, h->bb, h->act[0], h->iters,
+                           st));
+    int cur = 0;
+    int it = 0;
+    const int maxit = h->opt.cg_maxit;
+    int chunk = 8;
+    while (true) {
+        HIPCHK(hipMemcpyAsync(h->h_act, h->act[cur], S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        bool any = false;
+        for (int s = 0; s < S; ++s) any |= h->h_act[s] != 0;
+        if (!any || it >= maxit) break;
+        for (int c = 0; c < chunk && it < maxit; ++c, ++it) {
+            const int nxt = cur ^ 1;
+            HIPCHK(launch_cg_apply(g, &h->seqs, ps.d, S, h->p, h->q, h->ppq, h->act[cur], st));
+            HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, h->prr[cur], h->ppq, h->prr[nxt],
+                                    h->act[cur], st));
+            HIPCHK(launch_cg_direction(g, S, h->r, h->p, h->prr[cur], h->prr[nxt], h->bb, rtol2, maxit, h->act[cur],
+                                       h->act[nxt], h->iters, st));
+            cur = nxt;
+        }
+        chunk = std::min(chunk * 2, 32);
+    }
+    HIPCHK(launch_add_g(g, ps.d, S, xbase, gbase, st));
+    HIPCHK(hipMemcpyAsync(h->h_iters, h->iters, S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int s = 0; s < S; ++s) h->cg_count += h->h_iters[s];
+    h->phi_count += S;
+    return 0;
+}
+
+// Bases of the level-l arrays.
+struct Bases {
+    double* U;
+    const double* F;
+    const double* G;
+};
+
+Bases bases(mgrit_handle* h, int l) {
+    if (l == 0) return Bases{h->U0, h->F0, nullptr};
+    return Bases{h->lv[l].U, nullptr, h->lv[l].G};
+}
+
+// Run a batch on level l with output array `xout` (the level's U unless given).
+int run_batch(mgrit_handle* h, int l, const Batch& b, double* xout = nullptr) {
+    Bases B = bases(h, l);
+    double* X = xout ? xout : B.U;
+    if (b.npass == 1) return run_pass(h, b.pass[0], B.U, X, B.F, B.G);
+    CHK(run_pass(h, b.pass[0], B.U, h->tmp, B.F, nullptr));
+    return run_pass(h, b.pass[1], h->tmp, X, B.F, B.G);
+}
+
+int f_relax(mgrit_handle* h, int l) {
+    for (const Batch& b : h->lv[l].frelax) CHK(run_batch(h, l, b));
+    return 0;
+}
+
+int relax(mgrit_handle* h, int l) {
+    CHK(f_relax(h, l));
+    if (h->opt.relax == MGRIT_RELAX_FCF) {
+        CHK(run_batch(h, l, h->lv[l].crelax));
+        CHK(f_relax(h, l));
+    }
+    return 0;
+}
+
+// G^(l+1)_k = Phi^(l)_km(U_km-1) - U_km; optionally the squared norm of the residual.
+int residual(mgrit_handle* h, int l, double* norm2) {
+    Level& L = h->lv[l];
+    Level& C = h->lv[l + 1];
+    CHK(run_batch(h, l, L.resid, C.G));
+    const Geom* g = &h->geom;
+    Bases B = bases(h, l);
+    HIPCHK(launch_zero_slices(g, 1, C.all_idx, C.G, (void*)h->stream));       // G_0 = 0
+    HIPCHK(launch_axpy_slices(g, L.subtract.S, L.subtract.yi, C.G, L.subtract.xi, B.U, -1.0,
+                              norm2 ? h->pnorm : nullptr, (void*)h->stream));
+    if (norm2) {
+        const size_t n = (size_t)L.subtract.S * g->ntiles;
+        HIPCHK(hipMemcpyAsync(h->h_norm, h->pnorm, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        double acc = 0.0;
+        for (size_t i = 0; i < n; ++i) acc += h->h_norm[i];
+        *norm2 = acc;
+    }
+    return 0;
+}
+
+int coarsest_solve(mgrit_handle* h, int l) {
+    Level& L = h->lv[l];
+    HIPCHK(launch_zero_slices(&h->geom, 1, L.all_idx, L.U, (void*)h->stream));   // E_0 = G_0 = 0
+    for (int k = 1; k <= L.N; ++k) CHK(run_batch(h, l, L.step_list[k - 1]));
+    return 0;
+}
+
+int cycle(mgrit_handle* h, int l) {
+    Level& L = h->lv[l];
+    if (l == (int)h->lv.size() - 1) return coarsest_solve(h, l);
+    CHK(relax(h, l));
+    CHK(residual(h, l, nullptr));
+    Level& C = h->lv[l + 1];
+    HIPCHK(launch_zero_slices(&h->geom, C.N + 1, C.all_idx, C.U, (void*)h->stream));
+    CHK(cycle(h, l + 1));
+    HIPCHK(launch_axpy_slices(&h->geom, L.correct.S, L.correct.yi, L.U, L.correct.xi, C.U, 1.0, nullptr,
+                              (void*)h->stream));
+    return f_relax(h, l);
+}
+
+// One level-0 correction after the residual has been restricted.
+int coarse_correct0(mgrit_handle* h) {
+    Level& L = h->lv[0];
+    Level& C = h->lv[1];
+    HIPCHK(launch_zero_slices(&h->geom, C.N + 1, C.all_idx, C.U, (void*)h->stream));
+    CHK(cycle(h, 1));
+    HIPCHK(launch_axpy_slices(&h->geom, L.correct.S, L.correct.yi, h->U0, L.correct.xi, C.U, 1.0, nullptr,
+                              (void*)h->stream));
+    return 0;
+}
+
+// Device staging of the caller's arrays for one call.
+struct Staging {
+    mgrit_handle* h;
+    std::vector<void*> owned;
+    ~Staging() {
+        for (void* p : owned) (void)hipFree(p);
+    }
+    int in(const double* src, size_t count, int mem, const double** out) {
+        if (!src) {
+            *out = nullptr;
+            return 0;
+        }
+        if (mem == MGRIT_MEM_DEVICE) {
+            *out = src;
+            return 0;
+        }
+        void* d = nullptr;
+        hipError_t e = hipMalloc(&d, count * sizeof(double));
+        if (e != hipSuccess) return fail(MGRIT_ENOMEM, "staging hipMalloc failed: %s", hipGetErrorString(e));
+        owned.push_back(d);
+        HIPCHK(hipMemcpyAsync(d, src, count * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        *out = (const double*)d;
+        return 0;
+    }
+    int outbuf(double* dst, size_t count, int mem, double** out) {
+        if (mem == MGRIT_MEM_DEVICE) {
+            *out = dst;
+            return 0;
+        }
+        void* d = nullptr;
+        hipError_t e = hipMalloc(&d, count * sizeof(double));
+        if (e != hipSuccess) return fail(MGRIT_ENOMEM, "staging hipMalloc failed: %s", hipGetErrorString(e));
+        owned.push_back(d);
+        *out = (double*)d;
+        return 0;
+    }
+};
+
+int check_mem(int mem) {
+    if (mem != MGRIT_MEM_HOST && mem != MGRIT_MEM_DEVICE) return fail(MGRIT_EINVAL, "mem must be HOST or DEVICE");
+    return 0;
+}
+
+void fill_stats(mgrit_handle* h, mgrit_stats* st, int iters, int conv, const std::vector<double>& hist) {
+    if (!st) return;
+    st->iterations = iters;
+    st->converged = conv;
+    st->levels = (int)h->lv.size();
+    st->phi_applications = h->phi_count;
+    st->cg_iterations = h->cg_count;
+    for (int i = 0; i < 64; ++i) st->residual_history[i] = i < (int)hist.size() ? hist[i] : 0.0;
+}
+
+// Common entry of solve / iterate: stage inputs, initialise U.
+int begin_solve(mgrit_handle* h, Staging& sg, const double* F, const double* psi0, const double* U_init, double* U,
+                int mem, double** dU) {
+    CHK(check_mem(mem));
+    if (!psi0 || !U) return fail(MGRIT_EINVAL, "psi0 and U must not be NULL");
+    const size_t st = (size_t)h->geom.stride;
+    const size_t nt1 = (size_t)h->prob.Nt + 1;
+    const double *dF, *dpsi, *dinit;
+    CHK(sg.in(F, (size_t)h->prob.Nt * st, mem, &dF));
+    CHK(sg.in(psi0, st, mem, &dpsi));
+    CHK(sg.in(U_init, nt1 * st, mem, &dinit));
+    CHK(sg.outbuf(U, nt1 * st, mem, dU));
+    if (dinit) {
+        if (dinit != *dU)
+            HIPCHK(hipMemcpyAsync(*dU + st, dinit + st, (nt1 - 1) * st * sizeof(double), hipMemcpyDeviceToDevice,
+                                  h->stream));
+    } else {
+        HIPCHK(hipMemsetAsync(*dU + st, 0, (nt1 - 1) * st * sizeof(double), h->stream));
+    }
+    HIPCHK(hipMemcpyAsync(*dU, dpsi, st * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    h->U0 = *dU;
+    h->F0 = dF;
+    h->phi_count = 0;
+    h->cg_count = 0;
+    return 0;
+}
+
+int end_solve(mgrit_handle* h, double* U, const double* dU, int mem) {
+    if (mem == MGRIT_MEM_HOST) {
+        const size_t n = ((size_t)h->prob.Nt + 1) * h->geom.stride;
+        HIPCHK(hipMemcpyAsync(U, dU, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->U0 = nullptr;
+    h->F0 = nullptr;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mgrit_default_options(mgrit_options* o) {
+    if (!o) return;
+    o->m = 8;
+    o->max_levels = 30;
+    o->relax = MGRIT_RELAX_FCF;
+    o->coarse = MGRIT_COARSE_CN;
+    o->precision = MGRIT_PREC_FP64;
+    o->max_iter = 100;
+    o->tol_abs = 1e-9;
+    o->cg_rtol = 1e-9;
+    o->cg_maxit = 10000;
+    o->divergence_factor = 0.0;
+}
+
+const char* mgrit_last_error(void) { return g_err; }
+
+int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* stream, mgrit_handle** out) {
+    if (!prob || !opt || !out) return fail(MGRIT_EINVAL, "NULL argument");
+    *out = nullptr;
+    const mgrit_problem& p = *prob;
+    if (!(p.beta > 0.5 && p.beta < 1.0) || !(p.gamma > 0.5 && p.gamma < 1.0))
+        return fail(MGRIT_EINVAL, "orders must satisfy 1/2 < beta, gamma < 1");
+    if (!(p.Kx > 0.0) || !(p.Ky > 0.0)) return fail(MGRIT_EINVAL, "K_x, K_y must be positive");
+    if (!(p.a < p.b) || !(p.c < p.d)) return fail(MGRIT_EINVAL, "domain must satisfy a < b, c < d");
+    if (p.Mx < 2 || p.My < 2) return fail(MGRIT_EINVAL, "Mx, My must be >= 2");
+    if (p.Nt < 1 || !p.t) return fail(MGRIT_EINVAL, "Nt >= 1 and a time grid are required");
+    if (p.t[0] != 0.0) return fail(MGRIT_EINVAL, "t[0] must be 0");
+    for (int i = 1; i <= p.Nt; ++i)
+        if (!(p.t[i] > p.t[i - 1])) return fail(MGRIT_EINVAL, "time grid must increase strictly (index %d)", i);
+    const mgrit_options& o = *opt;
+    if (o.m < 2) return fail(MGRIT_EINVAL, "m must be >= 2");
+    if (o.max_levels < 2) return fail(MGRIT_EINVAL, "max_levels must be >= 2");
+    if (o.relax != MGRIT_RELAX_F && o.relax != MGRIT_RELAX_FCF) return fail(MGRIT_EINVAL, "unknown relaxation");
+    if (o.coarse < MGRIT_COARSE_CN || o.coarse > MGRIT_COARSE_CN2)
+        return fail(MGRIT_EINVAL, "unknown coarse propagator");
+    if (o.precision != MGRIT_PREC_FP64) return fail(MGRIT_EINVAL, "unknown precision");
+    if (o.max_iter < 1 || o.cg_maxit < 1 || !(o.cg_rtol > 0.0) || !(o.tol_abs >= 0.0))
+        return fail(MGRIT_EINVAL, "bad iteration limits or tolerances");
+    const long long nx = p.Mx - 1, ny = p.My - 1;
+    if (nx * ny > (1LL << 30)) return fail(MGRIT_EINVAL, "grid too large");
+
+    mgrit_handle* h = new (std::nothrow) mgrit_handle();
+    if (!h) return fail(MGRIT_ENOMEM, "host allocation failed");
+    h->prob = p;
+    h->opt = o;
+    h->t.assign(p.t, p.t + p.Nt + 1);
+    h->prob.t = h->t.data();
+    h->stream = (hipStream_t)stream;
+    Geom& g = h->geom;
+    g.nx = (int)nx;
+    g.ny = (int)ny;
+    g.tiles_x = (g.nx + MGRIT_TILE - 1) / MGRIT_TILE;
+    g.tiles_y = (g.ny + MGRIT_TILE - 1) / MGRIT_TILE;
+    g.ntiles = g.tiles_x * g.tiles_y;
+    g.stride = nx * ny;
+    g.seq_off_x = g.tiles_x * MGRIT_TILE + MGRIT_TILE + MGRIT_KC;
+    g.seq_off_y = g.tiles_y * MGRIT_TILE + MGRIT_TILE + MGRIT_KC;
+    g.mass = ((p.b - p.a) / p.Mx) * ((p.d - p.c) / p.My) / 12.0;
+    int rc = build_sequences(h);
+    if (!rc) rc = build_levels(h);
+    if (!rc) rc = alloc_workspace(h, h->Smax);
+    if (rc) {
+        mgrit_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return MGRIT_OK;
+}
+
+void mgrit_destroy(mgrit_handle* h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    for (void* p : h->allocations) (void)hipFree(p);
+    if (h->h_act) (void)hipHostFree(h->h_act);
+    if (h->h_iters) (void)hipHostFree(h->h_iters);
+    if (h->h_norm) (void)hipHostFree(h->h_norm);
+    delete h;
+}
+
+int mgrit_solve(mgrit_handle* h, const double* F, const double* psi0, const double* U_init, double* U, int mem,
+                mgrit_stats* st) {
+    if (!h) return fail(MGRIT_EINVAL, "NULL handle");
+    Staging sg{h};
+    double* dU = nullptr;
+    CHK(begin_solve(h, sg, F, psi0, U_init, U, mem, &dU));
+    const double hxy = ((h->prob.b - h->prob.a) / h->prob.Mx) * ((h->prob.d - h->prob.c) / h->prob.My);
+    std::vector<double> hist;
+    int it = 0, conv = 0, diverged = 0;
+    while (it < h->opt.max_iter) {
+        CHK(relax(h, 0));
+        double n2 = 0.0;
+        CHK(residual(h, 0, &n2));
+        const double norm = std::sqrt(hxy * n2);
+        hist.push_back(norm);
+        if (norm < h->opt.tol_abs) {
+            conv = 1;
+            break;
+        }
+        if (h->opt.divergence_factor > 0.0 && norm > h->opt.divergence_factor * hist[0]) {
+            diverged = 1;
+            break;
+        }
+        ++it;
+        CHK(coarse_correct0(h));
+    }
+    if (!conv) CHK(f_relax(h, 0));
+    CHK(end_solve(h, U, dU, mem));
+    fill_stats(h, st, it, conv, hist);
+    if (diverged) return fail(MGRIT_EDIVERGED, "residual norm grew beyond the divergence guard");
+    if (!conv) return fail(MGRIT_ENOCONV, "no convergence in %d iterations", h->opt.max_iter);
+    return MGRIT_OK;
+}
+
+int mgrit_iterate(mgrit_handle* h, const double* F, const double* psi0, const double* U_init, int iterations,
+                  double* U, int mem, mgrit_stats* st) {
+    if (!h) return fail(MGRIT_EINVAL, "NULL handle");
+    if (iterations < 0) return fail(MGRIT_EINVAL, "iterations must be >= 0");
+    Staging sg{h};
+    double* dU = nullptr;
+    CHK(begin_solve(h, sg, F, psi0, U_init, U, mem, &dU));
+    std::vector<double> hist;
+    for (int i = 0; i < iterations; ++i) {
+        CHK(relax(h, 0));
+        CHK(residual(h, 0, nullptr));
+        CHK(coarse_correct0(h));
+    }
+    CHK(f_relax(h, 0));
+    CHK(end_solve(h, U, dU, mem));
+    fill_stats(h, st, iterations, 0, hist);
+    return MGRIT_OK;
+}
+
+int mgrit_sequential(mgrit_handle* h, const double* F, const double* psi0, double* U, int mem, mgrit_stats* st) {
+    if (!h) return fail(MGRIT_EINVAL, "NULL handle");
+    Staging sg{h};
+    double* dU = nullptr;
+    CHK(begin_solve(h, sg, F, psi0, nullptr, U, mem, &dU));
+    for (int k = 1; k <= h->prob.Nt; ++k) CHK(run_batch(h, 0, h->lv[0].step_list[k - 1]));
+    CHK(end_solve(h, U, dU, mem));
+    std::vector<double> hist;
+    fill_stats(h, st, 0, 1, hist);
+    return MGRIT_OK;
+}
+
+int mgrit_propagate(mgrit_handle* h, int level, const int* step, int nslices, const double* u_in, const double* g,
+                    double* u_out, int mem) {
+    if (!h) return fail(MGRIT_EINVAL, "NULL handle");
+    CHK(check_mem(mem));
+    if (level < 0 || level >= (int)h->lv.size()) return fail(MGRIT_EINVAL, "level out of range");
+    if (nslices < 0 || (nslices > 0 && (!step || !u_in || !u_out))) return fail(MGRIT_EINVAL, "bad slices");
+    if (nslices == 0) return MGRIT_OK;
+    for (int s = 0; s < nslices; ++s)
+        if (step[s] < 1 || step[s] > h->lv[level].N) return fail(MGRIT_EINVAL, "step index %d out of range", step[s]);
+    const size_t st = (size_t)h->geom.stride;
+    Staging sg{h};
+    const double *du, *dg;
+    double* dout;
+    CHK(sg.in(u_in, nslices * st, mem, &du));
+    CHK(sg.in(g, nslices * st, mem, &dg));
+    CHK(sg.outbuf(u_out, nslices * st, mem, &dout));
+    for (int s0 = 0; s0 < nslices; s0 += h->Smax) {
+        const int S = std::min(h->Smax, nslices - s0);
+        Batch b;
+        for (int s = 0; s < S; ++s) {
+            Batch one;
+            make_step(h, level, step[s0 + s], s, s, s, one);
+            for (int pi = 0; pi < one.npass; ++pi) {
+                PropDesc d = one.pass[pi].h[0];
+                if (level == 0) d.f = dg ? s : -1;
+                else if (pi == one.npass - 1) d.g = dg ? s : -1;
+                b.pass[pi].h.push_back(d);
+            }
+            b.npass = one.npass;
+        }
+        Staging descs{h};
+        for (int pi = 0; pi < b.npass; ++pi) {
+            Pass& ps = b.pass[pi];
+            ps.S = S;
+            void* d = nullptr;
+            hipError_t e = hipMalloc(&d, S * sizeof(PropDesc));
+            if (e != hipSuccess) return fail(MGRIT_ENOMEM, "descriptor allocation failed");
+            descs.owned.push_back(d);
+            ps.d = (PropDesc*)d;
+            HIPCHK(hipMemcpyAsync(ps.d, ps.h.data(), S * sizeof(PropDesc), hipMemcpyHostToDevice, h->stream));
+        }
+        const double* ub = du + s0 * st;
+        double* ob = dout + s0 * st;
+        const double* gb = dg ? dg + s0 * st : nullptr;
+        if (b.npass == 1) {
+            CHK(run_pass(h, b.pass[0], ub, ob, level == 0 ? gb : nullptr, level == 0 ? nullptr : gb));
+        } else {
+            CHK(run_pass(h, b.pass[0], ub, h->tmp, nullptr, nullptr));
+            CHK(run_pass(h, b.pass[1], h->tmp, ob, nullptr, gb));
+        }
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    if (mem == MGRIT_MEM_HOST)
+        HIPCHK(hipMemcpyAsync(u_out, dout, nslices * st * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return MGRIT_OK;
+}
+
+int mgrit_apply(mgrit_handle* h, int nslices, const double* theta, double sign, const double* v, const double* add,
+                double* out, int mem) {
+    if (!h) return fail(MGRIT_EINVAL, "NULL handle");
+    CHK(check_mem(mem));
+    if (nslices < 0 || (nslices > 0 && (!theta || !v || !out))) return fail(MGRIT_EINVAL, "bad slices");
+    if (sign != 1.0 && sign != -1.0) return fail(MGRIT_EINVAL, "sign must be +1 or -1");
+    if (nslices == 0) return MGRIT_OK;
+    const size_t st = (size_t)h->geom.stride;
+    Staging sg{h};
+    const double *dv, *da;
+    double* dout;
+    CHK(sg.in(v, nslices * st, mem, &dv));
+    CHK(sg.in(add, nslices * st, mem, &da));
+    CHK(sg.outbuf(out, nslices * st, mem, &dout));
+    std::vector<ApplyDesc> hd(nslices);
+    for (int s = 0; s < nslices; ++s) {
+        hd[s].v = s;
+        hd[s].out = s;
+        hd[s].add = da ? s : -1;
+        hd[s].pad_ = 0;
+        hd[s].theta = theta[s];
+    }
+    void* dd = nullptr;
+    hipError_t e = hipMalloc(&dd, nslices * sizeof(ApplyDesc));
+    if (e != hipSuccess) return fail(MGRIT_ENOMEM, "descriptor allocation failed");
+    sg.owned.push_back(dd);
+    HIPCHK(hipMemcpyAsync(dd, hd.data(), nslices * sizeof(ApplyDesc), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(launch_apply(&h->geom, &h->seqs, (const ApplyDesc*)dd, nslices, dv, dout, da, sign, 0, nullptr, nullptr,
+                        (void*)h->stream));
+    if (mem == MGRIT_MEM_HOST)
+        HIPCHK(hipMemcpyAsync(out, dout, nslices * st * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return MGRIT_OK;
+}
+
+int mgrit_sequences(const mgrit_handle* h, double* seq_x, double* seq_y, double* cx, double* cy) {
+    if (!h) return fail(MGRIT_EINVAL, "NULL handle");
+    if (seq_x) std::memcpy(seq_x, h->host_seq_x.data(), h->host_seq_x.size() * sizeof(double));
+    if (seq_y) std::memcpy(seq_y, h->host_seq_y.data(), h->host_seq_y.size() * sizeof(double));
+    if (cx) *cx = h->cx;
+    if (cy) *cy = h->cy;
+    return MGRIT_OK;
+}
+
+int mgrit_levels(const mgrit_handle* h, int* n_per_level, int cap) {
+    if (!h) return fail(MGRIT_EINVAL, "NULL handle");
+    const int L = (int)h->lv.size();
+    for (int l = 0; l < L && l < cap; ++l) n_per_level[l] = h->lv[l].N + 1;
+    return L;
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Internal interfaces between the host driver (mgrit_driver.cpp), the HIP
+// kernels (kernels.hip) and the host set-up (toeplitz_setup.cpp).
+#ifndef MGRIT_INTERNAL_H
+#define MGRIT_INTERNAL_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+// Output tile of the operator kernel and of every per-slice vector kernel:
+// TILE x TILE grid points (x rows, y columns).  Per-slice partial sums are
+// stored per tile, so reductions have a fixed order.
+#define MGRIT_TILE 64
+// k-chunk of the Toeplitz contractions staged through LDS.
+#define MGRIT_KC 32
+
+// One slice of a batched propagator call.  Indices refer to slices of the
+// base arrays passed beside the descriptor array (stride n_x * n_y doubles).
+typedef struct {
+    int u;            // input state slice (start vector of CG)
+    int x;            // output slice (the CG iterate)
+    int f;            // load slice added to the right-hand side, -1 = none
+    int g;            // slice added after the solve, -1 = none
+    double theta_rhs; // right-hand side M u + theta_rhs A u (+ F)
+    double theta_lhs; // system matrix M + theta_lhs A
+} PropDesc;
+
+// One slice of an operator application: out = add + sign (M v + theta A v).
+typedef struct {
+    int v;            // input slice
+    int out;          // output slice
+    int add;          // added slice, -1 = none
+    int pad_;
+    double theta;
+} ApplyDesc;
+
+// Geometry shared by every kernel.
+typedef struct {
+    int nx, ny;             // interior nodes
+    int tiles_x, tiles_y;   // ceil(n / TILE)
+    int ntiles;             // tiles per slice
+    long long stride;       // doubles per slice = nx * ny
+    int seq_off_x, seq_off_y; // index of distance 0 in the padded sequence arrays
+    double mass;            // h_x h_y / 12
+} Geom;
+
+// Padded generating sequences on the device, already multiplied by K c:
+// T1[d + off] = A_1 entry at distance |d|, A2[d + off] = A_2 entry (k, k+d)
+// for d >= 0 and (k-d, k) for d < 0; zero for |d| >= n.
+typedef struct {
+    const double* T1x;
+    const double* A2x;
+    const double* T1y;
+    const double* A2y;
+} Seqs;
+
+// Host set-up (toeplitz_setup.cpp).
+void mgrit_toeplitz_sequences(double rho, int n, double* t, double* u, double* w);
+double mgrit_stiffness_scale(double rho, double h_par, double h_perp);
+
+// Kernel launchers (kernels.hip).  All return a hipError_t as int.
+// dot_mode: 0 none, 1 partial[s*ntiles+tile] = sum v*out, 2 = sum out*out.
+int launch_apply(const Geom* g, const Seqs* sq, const ApplyDesc* desc, int S, const double* vbase,
+                 double* outbase, const double* addbase, double sign, int dot_mode, double* partial,
+                 const int* active, void* stream);
+// Right-hand side of a batched propagator: b[s] = M u + theta_rhs A u (+ F),
+// partial of ||b||^2.
+int launch_rhs(const Geom* g, const Seqs* sq, const PropDesc* desc, int S, const double* ubase,
+               const double* fbase, double* bws, double* partial_bb, void* stream);
+// r[s] = b[s] - (M u + theta_lhs A u), partial of ||r||^2 into partial_rr.
+int launch_init_residual(const Geom* g, const Seqs* sq, const PropDesc* desc, int S, const double* ubase,
+                         const double* bws, double* rws, double* partial_rr, void* stream);
+// x = u (or 0 when ||b|| = 0), p = r; active flags from ||r|| vs rtol ||b||.
+int launch_cg_start(const Geom* g, const PropDesc* desc, int S, const double* ubase, double* xbase,
+                    const double* rws, double* pws, const double* partial_bb, const double* partial_rr,
+                    double rtol2, double* bb, int* active, int* iters, void* stream);
+// q = B p for active slices, partial p.q.
+int launch_cg_apply(const Geom* g, const Seqs* sq, const PropDesc* desc, int S, const double* pws, double* qws,
+                    double* partial_pq, const int* active, void* stream);
+// x += alpha p, r -= alpha q; partial r.r into partial_rr_new.
+int launch_cg_update(const Geom* g, const PropDesc* desc, int S, double* xbase, double* rws, const double* pws,
+                     const double* qws, const double* partial_rr, const double* partial_pq,
+                     double* partial_rr_new, const int* active, void* stream);
+// p = r + beta p; next active flags and iteration counts.
+int launch_cg_direction(const Geom* g, int S, const double* rws, double* pws, const double* partial_rr,
+                        const double* partial_rr_new, const double* bb, double rtol2, int maxit,
+                        const int* active, int* active_next, int* iters, void* stream);
+// x[s] += G[s] for slices with g >= 0.
+int launch_add_g(const Geom* g, const PropDesc* desc, int S, double* xbase, const double* gbase, void* stream);
+// y[yi[s]] += a * x[xi[s]]; when partial != NULL, partial of ||y||^2 after the update.
+int launch_axpy_slices(const Geom* g, int S, const int* yi, double* ybase, const int* xi, const double* xbase,
+                       double a, double* partial, void* stream);
+// Fill slices of an array with zero.
+int launch_zero_slices(const Geom* g, int S, const int* idx, double* base, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

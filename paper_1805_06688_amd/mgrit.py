@@ -1,0 +1,268 @@
+"""Thin ctypes binding of libmgrit.so (the C ABI in include/mgrit.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Arrays are either torch tensors on the GPU (passed as device pointers, work
+ordered on the current torch stream) or numpy arrays (host memory, copied in
+and out by the library).  There is no CPU fallback: importing this module
+fails when the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmgrit.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, EDIVERGED = 0, -1, -2, -3, 1, 2
+MEM_HOST, MEM_DEVICE = 0, 1
+RELAX = {"F": 0, "FCF": 1}
+COARSE = {"cn": 0, "be": 1, "cn2": 2}
+PRECISION = {"fp64": 0}
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("gamma", ctypes.c_double), ("Kx", ctypes.c_double),
+                ("Ky", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double), ("c", ctypes.c_double),
+                ("d", ctypes.c_double), ("Mx", ctypes.c_int), ("My", ctypes.c_int), ("Nt", ctypes.c_int),
+                ("t", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("max_levels", ctypes.c_int), ("relax", ctypes.c_int),
+                ("coarse", ctypes.c_int), ("precision", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("tol_abs", ctypes.c_double), ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int),
+                ("divergence_factor", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("levels", ctypes.c_int),
+                ("phi_applications", ctypes.c_longlong), ("cg_iterations", ctypes.c_longlong),
+                ("residual_history", ctypes.c_double * 64)]
+
+    def history(self):
+        n = min(64, self.iterations + 1)
+        return [self.residual_history[i] for i in range(n)]
+
+
+SYMBOLS = ("mgrit_default_options", "mgrit_setup", "mgrit_solve", "mgrit_iterate", "mgrit_sequential",
+           "mgrit_propagate", "mgrit_apply", "mgrit_sequences", "mgrit_levels", "mgrit_destroy",
+           "mgrit_last_error", "mgrit_toeplitz_sequences", "mgrit_stiffness_scale")
+
+
+def load_library(path=_LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1805_06688_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, c_int, c_dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.mgrit_default_options.argtypes = [ctypes.POINTER(_Options)]
+    lib.mgrit_default_options.restype = None
+    lib.mgrit_setup.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Options), P, ctypes.POINTER(P)]
+    lib.mgrit_setup.restype = c_int
+    lib.mgrit_solve.argtypes = [P, P, P, P, P, c_int, ctypes.POINTER(Stats)]
+    lib.mgrit_solve.restype = c_int
+    lib.mgrit_iterate.argtypes = [P, P, P, P, c_int, P, c_int, ctypes.POINTER(Stats)]
+    lib.mgrit_iterate.restype = c_int
+    lib.mgrit_sequential.argtypes = [P, P, P, P, c_int, ctypes.POINTER(Stats)]
+    lib.mgrit_sequential.restype = c_int
+    lib.mgrit_propagate.argtypes = [P, c_int, ctypes.POINTER(c_int), c_int, P, P, P, c_int]
+    lib.mgrit_propagate.restype = c_int
+    lib.mgrit_apply.argtypes = [P, c_int, ctypes.POINTER(c_dbl), c_dbl, P, P, P, c_int]
+    lib.mgrit_apply.restype = c_int
+    lib.mgrit_sequences.argtypes = [P, ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl),
+                                    ctypes.POINTER(c_dbl)]
+    lib.mgrit_sequences.restype = c_int
+    lib.mgrit_levels.argtypes = [P, ctypes.POINTER(c_int), c_int]
+    lib.mgrit_levels.restype = c_int
+    lib.mgrit_destroy.argtypes = [P]
+    lib.mgrit_destroy.restype = None
+    lib.mgrit_toeplitz_sequences.argtypes = [c_dbl, c_int, ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl),
+                                             ctypes.POINTER(c_dbl)]
+    lib.mgrit_toeplitz_sequences.restype = None
+    lib.mgrit_stiffness_scale.argtypes = [c_dbl, c_dbl, c_dbl]
+    lib.mgrit_stiffness_scale.restype = c_dbl
+    lib.mgrit_last_error.argtypes = []
+    lib.mgrit_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = load_library()
+
+
+class MgritError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def _check(rc, allow=()):
+    if rc != OK and rc not in allow:
+        raise MgritError(rc, _lib.mgrit_last_error().decode())
+    return rc
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, mem, count):
+    """Raw pointer of an FP64 array with at least `count` elements in the expected memory space."""
+    if x is None:
+        return None
+    if _is_torch(x):
+        import torch
+        if mem != MEM_DEVICE or not x.is_cuda:
+            raise ValueError("mixing host and device arrays in one call")
+        if x.dtype != torch.float64 or not x.is_contiguous():
+            raise ValueError("device arrays must be contiguous float64 tensors")
+        if x.numel() < count:
+            raise ValueError(f"array has {x.numel()} elements, {count} needed")
+        return ctypes.c_void_p(x.data_ptr())
+    if mem != MEM_HOST:
+        raise ValueError("mixing host and device arrays in one call")
+    if x.dtype != np.float64 or not x.flags["C_CONTIGUOUS"]:
+        raise ValueError("host arrays must be C-contiguous float64")
+    if x.size < count:
+        raise ValueError(f"array has {x.size} elements, {count} needed")
+    return ctypes.c_void_p(x.ctypes.data)
+
+
+def _mem_of(x):
+    return MEM_DEVICE if _is_torch(x) else MEM_HOST
+
+
+def toeplitz_sequences(rho, n):
+    """Host-side generating sequences (t, u, w) of A_1^rho and A_2^rho, as the library builds them."""
+    t, u, w = np.empty(n), np.empty(n), np.empty(n)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _lib.mgrit_toeplitz_sequences(float(rho), int(n), t.ctypes.data_as(dp), u.ctypes.data_as(dp),
+                                  w.ctypes.data_as(dp))
+    return t, u, w
+
+
+def stiffness_scale(rho, h_par, h_perp):
+    return _lib.mgrit_stiffness_scale(float(rho), float(h_par), float(h_perp))
+
+
+def default_options():
+    o = _Options()
+    _lib.mgrit_default_options(ctypes.byref(o))
+    return o
+
+
+class Solver:
+    """One problem (eqs. 1.1-1.3 on a time grid) set up on the GPU."""
+
+    def __init__(self, beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0), m=8, max_levels=30,
+                 relax="FCF", coarse="cn", precision="fp64", max_iter=100, tol_abs=1e-9, cg_rtol=1e-9,
+                 cg_maxit=10000, divergence_factor=0.0, stream=None):
+        self._h = None
+        self._t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
+        p = _Problem(beta, gamma, Kx, Ky, domain[0], domain[1], domain[2], domain[3], int(Mx), int(My),
+                     len(self._t) - 1, self._t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        o = default_options()
+        o.m, o.max_levels, o.max_iter, o.cg_maxit = int(m), int(max_levels), int(max_iter), int(cg_maxit)
+        o.relax, o.coarse, o.precision = RELAX[relax], COARSE[coarse], PRECISION[precision]
+        o.tol_abs, o.cg_rtol, o.divergence_factor = float(tol_abs), float(cg_rtol), float(divergence_factor)
+        if stream is None:
+            stream = self._torch_stream()
+        h = ctypes.c_void_p()
+        _check(_lib.mgrit_setup(ctypes.byref(p), ctypes.byref(o), stream, ctypes.byref(h)))
+        self._h = h
+        self.nx, self.ny, self.Nt = int(Mx) - 1, int(My) - 1, len(self._t) - 1
+
+    @staticmethod
+    def _torch_stream():
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except Exception:
+            pass
+        return None
+
+    @property
+    def slice_size(self):
+        return self.nx * self.ny
+
+    def close(self):
+        if self._h is not None:
+            _lib.mgrit_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _out(self, like, count, out):
+        if out is not None:
+            return out
+        if _is_torch(like):
+            import torch
+            return torch.empty(count, dtype=torch.float64, device=like.device)
+        return np.empty(count, dtype=np.float64)
+
+    def _shape(self, arr, n):
+        return arr.reshape(n, self.ny, self.nx)
+
+    def solve(self, F, psi0, U_init=None, out=None, allow_noconv=True):
+        """MGRIT V-cycles to the tolerance.  Returns (U [Nt+1, ny, nx], Stats, return code)."""
+        return self._run(_lib.mgrit_solve, F, psi0, U_init, out, None, allow_noconv)
+
+    def iterate(self, F, psi0, iterations, U_init=None, out=None):
+        return self._run(_lib.mgrit_iterate, F, psi0, U_init, out, int(iterations), False)
+
+    def sequential(self, F, psi0, out=None):
+        return self._run(_lib.mgrit_sequential, F, psi0, None, out, None, False, seq=True)
+
+    def _run(self, fn, F, psi0, U_init, out, iterations, allow_noconv, seq=False):
+        mem = _mem_of(psi0)
+        n = self.slice_size
+        U = self._out(psi0, (self.Nt + 1) * n, out)
+        st = Stats()
+        args = [self._h, _ptr(F, mem, self.Nt * n), _ptr(psi0, mem, n)]
+        if not seq:
+            args.append(_ptr(U_init, mem, (self.Nt + 1) * n))
+        if iterations is not None:
+            args.append(iterations)
+        args += [_ptr(U, mem, (self.Nt + 1) * n), mem, ctypes.byref(st)]
+        rc = _check(fn(*args), allow=(ENOCONV, EDIVERGED) if allow_noconv else ())
+        return self._shape(U, self.Nt + 1), st, rc
+
+    def propagate(self, level, steps, u_in, g=None, out=None):
+        steps = np.ascontiguousarray(np.asarray(steps, dtype=np.int32))
+        S = len(steps)
+        mem = _mem_of(u_in)
+        n = self.slice_size
+        U = self._out(u_in, S * n, out)
+        _check(_lib.mgrit_propagate(self._h, int(level), steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), S,
+                                    _ptr(u_in, mem, S * n), _ptr(g, mem, S * n), _ptr(U, mem, S * n), mem))
+        return self._shape(U, S)
+
+    def apply(self, theta, v, sign=1.0, add=None, out=None):
+        theta = np.ascontiguousarray(np.atleast_1d(np.asarray(theta, dtype=np.float64)))
+        S = len(theta)
+        mem = _mem_of(v)
+        n = self.slice_size
+        U = self._out(v, S * n, out)
+        _check(_lib.mgrit_apply(self._h, S, theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(sign),
+                                _ptr(v, mem, S * n), _ptr(add, mem, S * n), _ptr(U, mem, S * n), mem))
+        return self._shape(U, S)
+
+    def sequences(self):
+        sx = np.empty(3 * self.nx)
+        sy = np.empty(3 * self.ny)
+        cx, cy = ctypes.c_double(), ctypes.c_double()
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(_lib.mgrit_sequences(self._h, sx.ctypes.data_as(dp), sy.ctypes.data_as(dp), ctypes.byref(cx),
+                                    ctypes.byref(cy)))
+        return sx, sy, cx.value, cy.value
+
+    def levels(self):
+        buf = (ctypes.c_int * 64)()
+        L = _lib.mgrit_levels(self._h, buf, 64)
+        return [buf[i] - 1 for i in range(L)]

@@ -1,0 +1,65 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+Only random numbers and time grids: no arithmetic of the method lives here,
+so the HIP path and the CPU oracle can both be fed from this module.
+
+Recipes (numpy PCG64, ``default_rng(seed)``):
+* load vectors F_n ~ N(0, 1) i.i.d. per interior node and step, shape [Nt, n_y, n_x];
+* initial values psi_0 ~ U[0, 1] per interior node, shape [n_y, n_x];
+* time grids: uniform t_n = n T / N; graded t_n = T (n / N)^2; piecewise-uniform
+  with N/4, N/2, N/4 equal steps on [0, s], [s, T-s], [T-s, T], s = 2 eps ln N
+  (Section 4.1).
+"""
+import math
+
+import numpy as np
+
+
+def uniform_grid(N, T=1.0):
+    return np.linspace(0.0, T, N + 1)
+
+
+def graded_grid(N, T=1.0):
+    return T * (np.arange(N + 1, dtype=np.float64) / N) ** 2
+
+
+def piecewise_uniform_grid(N, eps, T=1.0):
+    if N % 4:
+        raise ValueError("N must be a multiple of 4")
+    s = 2.0 * eps * math.log(N)
+    a = np.linspace(0.0, s, N // 4 + 1)
+    b = np.linspace(s, T - s, N // 2 + 1)
+    c = np.linspace(T - s, T, N // 4 + 1)
+    return np.concatenate([a, b[1:], c[1:]])
+
+
+def random_grid(N, seed, T=1.0):
+    rng = np.random.default_rng(seed)
+    inner = np.sort(rng.uniform(0.0, T, N - 1))
+    return np.concatenate([[0.0], inner, [T]])
+
+
+def random_inputs(seed, Nt, nx, ny):
+    """(F [Nt, ny, nx] ~ N(0,1), psi0 [ny, nx] ~ U[0,1]) from one seed."""
+    rng = np.random.default_rng(seed)
+    F = rng.standard_normal((Nt, ny, nx))
+    psi0 = rng.uniform(0.0, 1.0, (ny, nx))
+    return F, psi0
+
+
+def random_slices(seed, S, nx, ny):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((S, ny, nx))
+
+
+# The benchmark workload: 255 x 255 interior nodes, beta = 0.75, gamma = 0.85,
+# K_x = 2, K_y = 1, T = 1, 1024 uniform steps, V-cycle with m = 8; F ~ N(0,1),
+# psi_0 ~ U[0,1] from seed 2.
+FP64_VCYCLE_255 = dict(name="fp64-vcycle-255x255x1024", beta=0.75, gamma=0.85, Kx=2.0, Ky=1.0, Mx=256, My=256,
+                       Nt=1024, T=1.0, m=8, seed=2)
+
+# The small correctness workload: 31 x 31 nodes, beta = 0.7, gamma = 0.8, K = 1,
+# 64 uniform steps, two-level FCF with m = 4, manufactured solution
+# u = x^2 (1-x)^2 y^2 (1-y)^2 e^{-t}.
+FP64_TWOLEVEL_31 = dict(name="fp64-twolevel-31x31x64", beta=0.7, gamma=0.8, Kx=1.0, Ky=1.0, Mx=32, My=32, Nt=64,
+                        T=1.0, m=4, levels=2, amp=1.0)

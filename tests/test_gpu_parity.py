@@ -1,0 +1,241 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerance: relative l2 <= 1e-10 for FP64 results of solves (both sides run CG
+to rtol 1e-14; the remaining gap is the conditioning of B_n times rounding);
+<= 1e-13 (relative to the largest entry) for a single operator application.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fem, manufactured as mf, mgrit as omgrit, propagator
+from paper_1805_06688_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _mg():
+    from paper_1805_06688_amd import mgrit
+    return mgrit
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+GEOMS = [  # beta, gamma, Kx, Ky, Mx, My, domain
+    (0.7, 0.8, 1.0, 1.0, 32, 32, (0, 1, 0, 1)),          # one tile, padded
+    (0.75, 0.85, 2.0, 1.0, 96, 78, (0, 1, 0, 1)),        # 2 x 2 tiles, ragged both ways
+    (0.55, 0.95, 3.0, 7.5, 131, 65, (0, 2, -1, 1)),      # 3 x 2 tiles, ragged, non-unit domain
+    (0.95, 0.6, 0.5, 2.0, 65, 160, (0, 1, 0, 3)),        # exactly one tile + 1 in x
+]
+
+
+@pytest.mark.parametrize("geo", GEOMS)
+def test_apply_matches_oracle(geo):
+    beta, gamma, Kx, Ky, Mx, My, dom = geo
+    mg = _mg()
+    prob = fem.Problem(beta, gamma, Kx, Ky, Mx, My, *dom)
+    op = fem.Operator(prob)
+    S = 5
+    v = wl.random_slices(11, S, prob.nx, prob.ny)
+    add = wl.random_slices(12, S, prob.nx, prob.ny)
+    theta = np.array([0.0, 1e-3, 0.5, -0.25, 7.0])
+    with mg.Solver(beta, gamma, Kx, Ky, Mx, My, wl.uniform_grid(8), domain=dom, m=2) as s:
+        for sign, use_add in ((1.0, False), (-1.0, True)):
+            out = host(s.apply(theta, dev(v), sign=sign, add=dev(add) if use_add else None))
+            for k in range(S):
+                ref = sign * (op.apply_M(v[k]) + theta[k] * op.apply_A(v[k])) + (add[k] if use_add else 0.0)
+                assert np.abs(out[k] - ref).max() <= 1e-13 * np.abs(ref).max(), (k, sign)
+
+
+def test_apply_host_memory_and_empty():
+    mg = _mg()
+    prob = fem.Problem(0.7, 0.8, 1.0, 1.0, 40, 30)
+    op = fem.Operator(prob)
+    v = wl.random_slices(3, 2, prob.nx, prob.ny)
+    with mg.Solver(0.7, 0.8, 1.0, 1.0, 40, 30, wl.uniform_grid(4), m=2) as s:
+        out = s.apply([0.3, 0.0], v)                    # numpy in, numpy out
+        for k in range(2):
+            ref = op.apply_M(v[k]) + [0.3, 0.0][k] * op.apply_A(v[k])
+            assert np.abs(out[k] - ref).max() <= 1e-13 * np.abs(ref).max()
+        s.apply(np.zeros(0), np.zeros(0))                # zero slices is a no-op
+
+
+@pytest.mark.parametrize("geo", GEOMS[:3])
+def test_propagate_level0_matches_oracle(geo):
+    beta, gamma, Kx, Ky, Mx, My, dom = geo
+    mg = _mg()
+    prob = fem.Problem(beta, gamma, Kx, Ky, Mx, My, *dom)
+    op = fem.Operator(prob)
+    t = wl.random_grid(12, 5)
+    steps = [1, 4, 7, 12]
+    u = wl.random_slices(21, len(steps), prob.nx, prob.ny)
+    F = wl.random_slices(22, len(steps), prob.nx, prob.ny)
+    solver = propagator.CGSolver(op, 1e-14, 20000)
+    with mg.Solver(beta, gamma, Kx, Ky, Mx, My, t, domain=dom, m=2, cg_rtol=1e-14, cg_maxit=20000) as s:
+        out = host(s.propagate(0, steps, dev(u), dev(F)))
+    for i, k in enumerate(steps):
+        ref = propagator.cn_step(op, solver, t[k] - t[k - 1], u[i], F[i])
+        assert rel(out[i], ref) <= 1e-10, (i, k, rel(out[i], ref))
+
+
+@pytest.mark.parametrize("coarse", ["cn", "be", "cn2"])
+def test_propagate_coarse_level_matches_oracle(coarse):
+    mg = _mg()
+    beta, gamma, Kx, Ky, Mx, My = 0.75, 0.85, 2.0, 1.0, 70, 66
+    prob = fem.Problem(beta, gamma, Kx, Ky, Mx, My)
+    op = fem.Operator(prob)
+    t = wl.random_grid(32, 9)
+    m = 4
+    osolver = omgrit.MGRIT(op, t, m, max_levels=3, coarse=coarse, cg_rtol=1e-14)
+    steps = [1, 3, 8]
+    u = wl.random_slices(31, 3, prob.nx, prob.ny)
+    g = wl.random_slices(32, 3, prob.nx, prob.ny)
+    with mg.Solver(beta, gamma, Kx, Ky, Mx, My, t, m=m, max_levels=3, coarse=coarse, cg_rtol=1e-14) as s:
+        assert s.levels() == [32, 8, 2]
+        out = host(s.propagate(1, steps, dev(u), dev(g)))
+        out_nog = host(s.propagate(1, steps, dev(u)))
+    for i, k in enumerate(steps):
+        ref = osolver.psi(1, k, u[i])
+        assert rel(out_nog[i], ref) <= 1e-10
+        assert rel(out[i], ref + g[i]) <= 1e-10
+
+
+def _random_problem(seed, Nt, beta=0.7, gamma=0.8, Mx=40, My=34, Kx=1.0, Ky=1.0):
+    prob = fem.Problem(beta, gamma, Kx, Ky, Mx, My)
+    t = wl.random_grid(Nt, seed)
+    F, psi0 = wl.random_inputs(seed, Nt, prob.nx, prob.ny)
+    return prob, t, F, psi0
+
+
+def test_sequential_matches_oracle():
+    mg = _mg()
+    prob, t, F, psi0 = _random_problem(1, 20)
+    op = fem.Operator(prob)
+    ref = propagator.sequential(op, propagator.CGSolver(op, 1e-14), t, F, psi0)
+    with mg.Solver(prob.beta, prob.gamma, 1.0, 1.0, prob.Mx, prob.My, t, m=4, cg_rtol=1e-14) as s:
+        U, st, _ = s.sequential(dev(F), dev(psi0))
+        U = host(U)
+    assert rel(U, ref) <= 1e-10
+    assert st.phi_applications == 20
+
+
+CASES = [  # m, levels, relax, coarse, Nt
+    (4, 2, "FCF", "cn", 32),
+    (2, 4, "FCF", "be", 24),
+    (3, 3, "FCF", "cn2", 29),          # Nt not a multiple of m: trailing F-points
+    (4, 3, "F", "be", 37),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("iters", [1, 2, 3])
+def test_mgrit_iterates_match_oracle(case, iters):
+    """The iterate after k MGRIT iterations (plus final F-relaxation) equals the oracle's, step for step."""
+    m, levels, relax, coarse, Nt = case
+    mg = _mg()
+    prob, t, F, psi0 = _random_problem(7 + Nt, Nt)
+    op = fem.Operator(prob)
+    U0 = wl.random_slices(99, Nt + 1, prob.nx, prob.ny)
+    o = omgrit.MGRIT(op, t, m, max_levels=levels, relax=relax, coarse=coarse, cg_rtol=1e-14)
+    ref = o.iterate(F, psi0, iters, U0=U0)
+    with mg.Solver(prob.beta, prob.gamma, 1.0, 1.0, prob.Mx, prob.My, t, m=m, max_levels=levels, relax=relax,
+                   coarse=coarse, cg_rtol=1e-14) as s:
+        assert s.levels() == [lv.N for lv in o.levels]
+        U, st, _ = s.iterate(dev(F), dev(psi0), iters, U_init=dev(U0))
+        U = host(U)
+    assert rel(U, ref) <= 1e-10, rel(U, ref)
+
+
+@pytest.mark.parametrize("case", CASES[:3])
+def test_mgrit_solve_reaches_sequential(case):
+    m, levels, relax, coarse, Nt = case
+    mg = _mg()
+    prob, t, F, psi0 = _random_problem(3, Nt)
+    op = fem.Operator(prob)
+    ref = propagator.sequential(op, propagator.CGSolver(op, 1e-14), t, F, psi0)
+    o = omgrit.MGRIT(op, t, m, max_levels=levels, relax=relax, coarse=coarse, cg_rtol=1e-14)
+    _, oit, oconv, ohist = o.solve(F, psi0, tol=1e-9, max_iter=50, return_history=True)
+    with mg.Solver(prob.beta, prob.gamma, 1.0, 1.0, prob.Mx, prob.My, t, m=m, max_levels=levels, relax=relax,
+                   coarse=coarse, cg_rtol=1e-14, tol_abs=1e-9, max_iter=50) as s:
+        U, st, rc = s.solve(dev(F), dev(psi0))
+        U = host(U)
+    assert rc == 0 and st.converged == 1
+    assert st.iterations == oit
+    hist = st.history()
+    assert np.allclose(hist, ohist[: len(hist)], rtol=1e-6, atol=1e-12)
+    assert rel(U, ref) <= 1e-10
+
+
+def test_manufactured_two_level_workload():
+    """31 x 31 nodes, beta 0.7, gamma 0.8, K = 1, 64 uniform steps, two-level FCF m = 4,
+    u = x^2(1-x)^2 y^2(1-y)^2 e^{-t}: MGRIT equals sequential stepping and the L2 error is O(h^2)."""
+    mg = _mg()
+    W = wl.FP64_TWOLEVEL_31
+    M = W["Mx"]
+    prob = fem.Problem(W["beta"], W["gamma"], W["Kx"], W["Ky"], M, M)
+    op = fem.Operator(prob)
+    t = wl.uniform_grid(W["Nt"])
+    F = mf.load_vectors(t, W["beta"], W["gamma"], W["Kx"], W["Ky"], M, amp=W["amp"])
+    psi0 = mf.nodal_psi0(M, amp=W["amp"])
+    ref = propagator.sequential(op, propagator.CGSolver(op, 1e-14), t, F, psi0)
+    with mg.Solver(W["beta"], W["gamma"], W["Kx"], W["Ky"], M, M, t, m=W["m"], max_levels=W["levels"],
+                   cg_rtol=1e-14, tol_abs=1e-13, max_iter=40) as s:
+        U, st, rc = s.solve(dev(F), dev(psi0))
+        U = host(U)
+    assert rc == 0
+    assert st.iterations <= math.ceil(16 / 2)          # finite termination bound for two levels
+    assert rel(U, ref) <= 1e-10
+    err = mf.l2_error(U[-1], 1.0, M, amp=W["amp"])
+    assert err < 2e-5
+
+
+def test_zero_data_gives_zero_and_noconv_code():
+    mg = _mg()
+    prob, t, F, psi0 = _random_problem(4, 16)
+    with mg.Solver(prob.beta, prob.gamma, 1.0, 1.0, prob.Mx, prob.My, t, m=4, cg_rtol=1e-14, max_iter=1,
+                   tol_abs=0.0) as s:
+        U, st, rc = s.solve(dev(np.zeros_like(F)), dev(np.zeros_like(psi0)))
+        assert not torch.any(U != 0)
+        U, st, rc = s.solve(dev(F), dev(psi0))
+        assert rc == mg.ENOCONV and st.converged == 0 and st.iterations == 1
+
+
+def test_full_size_apply_and_step_sampled():
+    """Benchmark geometry (255 x 255, beta 0.75, gamma 0.85, K = (2, 1)): operator and one step on sampled slices."""
+    mg = _mg()
+    W = wl.FP64_VCYCLE_255
+    prob = fem.Problem(W["beta"], W["gamma"], W["Kx"], W["Ky"], W["Mx"], W["My"])
+    op = fem.Operator(prob)
+    t = wl.uniform_grid(W["Nt"])
+    u = wl.random_slices(5, 3, prob.nx, prob.ny)
+    F = wl.random_slices(6, 3, prob.nx, prob.ny)
+    with mg.Solver(W["beta"], W["gamma"], W["Kx"], W["Ky"], W["Mx"], W["My"], t, m=W["m"], cg_rtol=1e-14) as s:
+        theta = np.array([0.5 / 1024, 4.0 / 1024, 0.0])
+        out = host(s.apply(theta, dev(u)))
+        steps = [1, 500, 1024]
+        prop = host(s.propagate(0, steps, dev(u), dev(F)))
+    for k in range(3):
+        ref = op.apply_M(u[k]) + theta[k] * op.apply_A(u[k])
+        assert np.abs(out[k] - ref).max() <= 1e-13 * np.abs(ref).max()
+    solver = propagator.CGSolver(op, 1e-14, 20000)
+    ref = propagator.cn_step(op, solver, t[1] - t[0], u[0], F[0])
+    assert rel(prop[0], ref) <= 1e-10
