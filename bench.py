@@ -1,0 +1,154 @@
+"""Benchmark: FP64 multilevel MGRIT V-cycle on one MI355X.
+
+Workload: 255 x 255 interior nodes, beta = 0.75, gamma = 0.85, K_x = 2, K_y = 1,
+T = 1, 1024 uniform steps, coarsening m = 8 (levels 1024 -> 128 -> 16 -> 2),
+F ~ N(0,1) per node and step and psi_0 ~ U[0,1] from seed 2, all FP64 and
+resident on the GPU before timing.  One step = one full MGRIT solve to the
+stop test; the result is checked against FP64 sequential stepping on the GPU
+(CG to rtol 1e-13) and must agree to relative l2 <= 1e-8.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+Prints one JSON line.  The operator kernel (the CG matrix-vector product) is
+timed with HIP events inside the library over the timed region; its algorithmic
+work is the six dense Toeplitz products, 6 n_x^2 n_y + 6 n_x n_y^2 flops per
+slice application.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "space-time DOF/s at 1e-8 rel. error vs FP64 sequential"
+FP64_PEAK_TFLOPS = 78.6          # MI355X dense FP64 (matrix and vector)
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_prop_apply2_fp64_vcycle_255_traffic.json")
+
+
+def cpu_baseline(W, t, F, psi0, steps, cg_rtol):
+    """The CPU oracle as it stands: sequential stepping over the first `steps` steps."""
+    import numpy as np
+    from oracle import fem, propagator
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    prob = fem.Problem(W["beta"], W["gamma"], W["Kx"], W["Ky"], W["Mx"], W["My"])
+    op = fem.Operator(prob)
+    solver = propagator.CGSolver(op, cg_rtol, 100000)
+    t0 = time.perf_counter()
+    propagator.sequential(op, solver, t[: steps + 1], F[:steps], psi0)
+    dt = time.perf_counter() - t0
+    return {"value": prob.nx * prob.ny * steps / dt, "unit": "DOF/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"sequential time stepping (the result MGRIT converges to) over the first {steps} of "
+                      f"{len(t) - 1} steps, CG rtol {cg_rtol:g}, numpy FP64 on the host; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--coarse", default="opt")
+    ap.add_argument("--cg-rtol", type=float, default=1e-10)
+    ap.add_argument("--tol-rel", type=float, default=1e-9)
+    ap.add_argument("--cpu-steps", type=int, default=48)
+    ap.add_argument("--precond", default="fd")
+    ap.add_argument("--skip-reference", action="store_true",
+                    help="time MGRIT only (no sequential reference, no accuracy check): for profiler runs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1805_06688_amd import mgrit, workloads as wl
+
+    W = wl.FP64_VCYCLE_255
+    nx, ny, Nt = W["Mx"] - 1, W["My"] - 1, W["Nt"]
+    t = wl.uniform_grid(Nt, W["T"])
+    F, psi0 = wl.random_inputs(W["seed"], Nt, nx, ny)
+    torch.cuda.set_device(0)
+    Fd = torch.from_numpy(F).cuda()
+    pd = torch.from_numpy(psi0).cuda()
+    common = (W["beta"], W["gamma"], W["Kx"], W["Ky"], W["Mx"], W["My"], t)
+
+    Uref, seq_s, seq_err = None, None, None
+    if not args.skip_reference:
+        # FP64 sequential reference (outside the timed region)
+        with mgrit.Solver(*common, m=W["m"], cg_rtol=1e-13, cg_maxit=100000, precond=args.precond) as ref:
+            Uref, _, _ = ref.sequential(Fd, pd)
+        torch.cuda.synchronize()
+        # sequential stepping at the benchmark CG tolerance, for comparison
+        with mgrit.Solver(*common, m=W["m"], cg_rtol=args.cg_rtol, cg_maxit=100000, precond=args.precond) as sq:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Useq, _, _ = sq.sequential(Fd, pd)
+            torch.cuda.synchronize()
+            seq_s = time.perf_counter() - t0
+        seq_err = float(torch.linalg.norm(Useq - Uref) / torch.linalg.norm(Uref))
+        del Useq
+
+    s = mgrit.Solver(*common, m=W["m"], coarse=args.coarse, cg_rtol=args.cg_rtol, cg_maxit=100000,
+                     tol_abs=0.0, tol_rel=args.tol_rel, max_iter=40, precond=args.precond)
+    U = torch.empty((Nt + 1) * nx * ny, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        s.solve(Fd, pd, out=U)
+    torch.cuda.synchronize()
+    s.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st, rc = s.solve(Fd, pd, out=U)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    apply_ms, launches, slice_applies = s.profile_read()
+    s.profile(False)
+    levels = s.levels()
+    err = None if Uref is None else float(torch.linalg.norm(U.view(Nt + 1, ny, nx) - Uref) / torch.linalg.norm(Uref))
+    s.close()
+
+    dof = nx * ny * Nt
+    per_step = elapsed / args.steps
+    flops_per_apply = 6.0 * nx * nx * ny + 6.0 * nx * ny * ny
+    achieved = flops_per_apply * slice_applies / (apply_ms * 1e-3) / 1e12 if apply_ms > 0 else None
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            traffic = json.load(fh).get("bytes_per_launch")
+    roofline = {"bound": "mfma", "kernel": "k_prop_apply<2> (CG operator, FP64 MFMA)",
+                "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS if achieved else None, "traffic": traffic,
+                "avg_launch_ms": apply_ms / launches if launches else None,
+                "launches": launches, "slice_applies_per_launch": slice_applies / launches if launches else None,
+                "flops_per_slice_apply": flops_per_apply}
+    out = {"metric": METRIC, "value": dof / per_step, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": per_step * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": W["name"], "nx": nx, "ny": ny, "Nt": Nt, "beta": W["beta"], "gamma": W["gamma"],
+                      "Kx": W["Kx"], "Ky": W["Ky"], "m": W["m"], "levels": levels, "relax": "FCF",
+                      "coarse": args.coarse, "precond": args.precond, "cg_rtol": args.cg_rtol,
+                      "tol_rel": args.tol_rel,
+                      "mgrit_iterations": st.iterations, "phi_per_solve": st.phi_applications,
+                      "cg_iterations_per_solve": st.cg_iterations, "rel_l2_err_vs_fp64_sequential": err,
+                      "sequential_dof_per_s": dof / seq_s if seq_s else None, "sequential_rel_l2_err": seq_err,
+                      "parallelism": "time (MGRIT), one GPU"},
+           "roofline": roofline}
+    if not args.no_cpu and not args.skip_reference:
+        out["cpu_baseline"] = cpu_baseline(W, t, F, psi0, args.cpu_steps, args.cg_rtol)
+    print(json.dumps(out), flush=True)
+    if args.skip_reference:
+        return
+    if not (err <= 1e-8 and rc == 0):
+        print(f"accuracy target missed: rel_l2_err={err:.3e} rc={rc}", file=sys.stderr)
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()

@@ -49,13 +49,25 @@ extern "C" {
 
 /* Coarse-level propagator (levels >= 1).  CN is eq. (equ-03-02): Crank-Nicolson
  * with the coarse step.  BE: backward Euler with the coarse step.  CN2: two
- * Crank-Nicolson half steps.  The choice changes the convergence rate only;
- * the fixed point is sequential stepping in every case. */
+ * Crank-Nicolson half steps.  OPT: two Crank-Nicolson steps of lengths
+ * 2 tau~/a1 and 2 tau~/a2, a1,2 = c/4 +- sqrt(c^2/16 - c), c = 4 tau~ sum 1/tau_n
+ * over the level-0 steps inside the coarse step; per mode of eq. (equ-03-05) it
+ * agrees with the product of the fine propagators to first order in tau~ sigma
+ * and in the stiff limit (needs an even m).  The choice changes the
+ * convergence rate only; the fixed point is sequential stepping in every case. */
 #define MGRIT_COARSE_CN   0
 #define MGRIT_COARSE_BE   1
 #define MGRIT_COARSE_CN2  2
+#define MGRIT_COARSE_OPT  3
 
 #define MGRIT_PREC_FP64   0   /* every operator application in FP64 (FP64 MFMA)        */
+
+/* Preconditioner of the spatial CG solves (Section 3.2 uses none).  FD: exact
+ * inverse of the tensor-product (bilinear-element) discretisation of the same
+ * operator, applied by fast diagonalisation (see mgrit_fd_eigen); it changes
+ * the iteration count only, not the solution the solver converges to. */
+#define MGRIT_PRECOND_NONE 0
+#define MGRIT_PRECOND_FD   1
 
 typedef struct {
     double beta, gamma;     /* fractional orders, 1/2 < beta, gamma < 1 (eq. 1.1)        */
@@ -74,8 +86,10 @@ typedef struct {
     int precision;          /* MGRIT_PREC_*                                              */
     int max_iter;           /* MGRIT iterations, >= 1                                    */
     double tol_abs;         /* stop when the discrete L2 C-point residual norm < tol_abs */
+    double tol_rel;         /* ... or < tol_rel x the norm of the first iteration (0: off)  */
     double cg_rtol;         /* CG stops when ||r||_2 <= cg_rtol ||b||_2                  */
     int cg_maxit;           /* CG iteration cap per solve                                */
+    int precond;            /* MGRIT_PRECOND_*                                           */
     double divergence_factor; /* EDIVERGED when a norm exceeds this x the first (0: off) */
 } mgrit_options;
 
@@ -91,8 +105,8 @@ typedef struct {
 typedef struct mgrit_handle mgrit_handle;
 
 /* Fill `opt` with defaults: m = 8, max_levels = 30, FCF, CN, FP64, max_iter = 100,
- * tol_abs = 1e-9, cg_rtol = 1e-9 (the paper's tolerances, Section 3.2),
- * cg_maxit = 10000, divergence_factor = 0. */
+ * tol_abs = 1e-9, tol_rel = 0, cg_rtol = 1e-9 (the paper's tolerances, Section 3.2),
+ * cg_maxit = 10000, precond = NONE, divergence_factor = 0. */
 void mgrit_default_options(mgrit_options* opt);
 
 /* Validate the problem, evaluate the Toeplitz generating sequences of Section 2
@@ -101,7 +115,8 @@ void mgrit_default_options(mgrit_options* opt);
  * t^(l+1) = t^(l)[::m] (Section 3.1) and allocate device memory.
  * `stream` is a hipStream_t or NULL.  Errors: EINVAL (beta or gamma outside
  * (1/2,1), K <= 0, a >= b or c >= d, Mx or My < 2, Nt < 1, t not strictly
- * increasing from 0, m < 2, max_levels < 2, unknown enum), ENOMEM, EHIP. */
+ * increasing from 0, m < 2, max_levels < 2, unknown enum, OPT with odd m),
+ * ENOMEM, EHIP. */
 int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* stream,
                 mgrit_handle** out);
 
@@ -161,6 +176,28 @@ void mgrit_toeplitz_sequences(double rho, int n, double* t, double* u, double* w
 /* Host-only helper: h_par^(1-2 rho) h_perp / (2 cos(rho pi) Gamma(5 - 2 rho)), the
  * scalar in front of the block stiffness matrix (c_x with h_par = h_x). */
 double mgrit_stiffness_scale(double rho, double h_par, double h_perp);
+
+/* Host-only helpers of the preconditioner (no GPU needed).  The spatial solves
+ * may be preconditioned by the exact inverse of the tensor-product (bilinear
+ * element) discretisation of the same operator,
+ *   P = M_y (x) M_x + theta (M_y (x) K_x + K_y (x) M_x),
+ * built from 1-D linear-element matrices M = h/6 tridiag(1, 4, 1) and
+ * K[i][j] = K_rho h^(1-2rho) / (2 cos(rho pi) Gamma(4-2rho)) g(|i-j|),
+ * g(l) = |l-2|^p - 4|l-1|^p + 6|l|^p - 4|l+1|^p + |l+2|^p, p = 3 - 2 rho.
+ * mgrit_fd_stiffness_entry returns K[i][i+l] (binary128 evaluation, rounded).
+ * mgrit_fd_eigen solves K v = lambda M v for n nodes: V (n x n, row-major,
+ * column i = eigenvector i, normalised so that V^T M V = I) and lambda (n).
+ * Returns 0, or a negative value when the eigen-iteration fails. */
+double mgrit_fd_stiffness_entry(double rho, double h, double K, int l);
+int mgrit_fd_eigen(double rho, int n, double h, double K, double* V, double* lambda);
+
+/* Instrumentation.  While enabled, a pair of HIP events on the handle's stream
+ * brackets every launch of the CG operator kernel (q = (M_h + theta A_h) p, the
+ * dominant kernel); enabling resets the counters.  mgrit_profile_read returns
+ * the summed kernel time in ms, the number of launches and the number of
+ * slice applications they performed (the sum of CG iterations over slices). */
+int mgrit_profile_enable(mgrit_handle* h, int on);
+int mgrit_profile_read(const mgrit_handle* h, double* apply_ms, long long* launches, long long* slice_applies);
 
 /* Number of time points per level; writes up to `cap` values, returns the level count. */
 int mgrit_levels(const mgrit_handle* h, int* n_per_level, int cap);

@@ -28,16 +28,42 @@ Readings (where the paper is silent or ambiguous):
   correction is followed by a final F-relaxation;
 * coarse propagator: "cn" is eq. (equ-03-02).  Also available: "be"
   (backward Euler with the coarse step), "cn2" (two Crank-Nicolson half
-  steps) and "ideal" (the product of the fine propagators over the coarse
-  step, i.e. the exact Schur complement).  The choice changes the
-  convergence speed, never the fixed point, which is sequential stepping.
+  steps), "ideal" (the product of the fine propagators over the coarse
+  step, i.e. the exact Schur complement) and "opt", a product of two
+  Crank-Nicolson steps whose lengths are chosen so that, mode by mode
+  (eq. equ-03-05), it agrees with the ideal propagator to first order in
+  tau~ sigma and in the stiff limit tau~ sigma -> infinity (see
+  opt_factors).  The choice changes the convergence speed, never the fixed
+  point, which is sequential stepping.
 """
 import numpy as np
 
 from .propagator import CGSolver
 
 
-COARSE_KINDS = ("cn", "be", "cn2", "ideal")
+COARSE_KINDS = ("cn", "be", "cn2", "ideal", "opt")
+
+
+def opt_factors(taus):
+    """Step lengths of the two Crank-Nicolson factors of the "opt" coarse propagator.
+
+    taus: the level-0 steps tau_n inside one coarse step (an even number of them),
+    tau~ = sum tau_n.  Per mode (eq. equ-03-05, y = tau~ sigma) the ideal coarse
+    propagator is prod_n (2 - tau_n sigma)/(2 + tau_n sigma), which behaves as
+    1 - y for small y and as 1 - c/y with c = 4 tau~ sum_n 1/tau_n for large y.
+    A product (a1 - y)/(a1 + y) * (a2 - y)/(a2 + y) behaves as 1 - 2 y (1/a1 + 1/a2)
+    and 1 - 2 (a1 + a2)/y, so a1 + a2 = c/2 and 1/a1 + 1/a2 = 1/2: a1, a2 are the
+    roots of s^2 - (c/2) s + c = 0 (real since c >= 16).  The factor (a - y)/(a + y)
+    is a Crank-Nicolson step of length 2 tau~ / a.  Returns (short step, long step).
+    """
+    taus = np.asarray(taus, dtype=np.float64)
+    if len(taus) % 2:
+        raise ValueError("the opt coarse propagator needs an even number of fine steps")
+    T = float(taus.sum())
+    c = 4.0 * T * float(np.sum(1.0 / taus))
+    d = np.sqrt(c * c / 16.0 - c)
+    a1, a2 = c / 4.0 + d, c / 4.0 - d
+    return 2.0 * T / a1, 2.0 * T / a2
 
 
 class _Level:
@@ -58,6 +84,8 @@ class MGRIT:
             raise ValueError("unknown coarse propagator")
         if max_levels < 2:
             raise ValueError("need at least two levels")
+        if coarse == "opt" and m % 2:
+            raise ValueError("the opt coarse propagator needs an even coarsening factor")
         self.op = op
         self.t = np.asarray(t, dtype=np.float64)
         self.m, self.relax_kind, self.coarse = m, relax, coarse
@@ -93,6 +121,10 @@ class MGRIT:
         if self.coarse == "cn2":
             v = self._cn(0.5 * tau, u)
             return self._cn(0.5 * tau, v)
+        if self.coarse == "opt":
+            short, long_ = opt_factors(np.diff(self.t[i0:i1 + 1]))
+            v = self._cn(short, u)
+            return self._cn(long_, v)
         v = u                                  # "ideal": fine steps i0+1 .. i1
         for n in range(i0 + 1, i1 + 1):
             v = self._cn(self.t[n] - self.t[n - 1], v)

@@ -32,6 +32,9 @@ def build(verbose=True):
     o = os.path.join(OUT_DIR, "toeplitz_setup.o")
     _run(["g++", "-O2", "-fPIC", "-std=gnu++17", "-I", CSRC, "-c", os.path.join(CSRC, "toeplitz_setup.cpp"), "-o", o])
     objs.append(o)
+    o = os.path.join(OUT_DIR, "fd_setup.o")
+    _run(["g++", "-O3", "-fPIC", "-std=gnu++17", "-I", CSRC, "-c", os.path.join(CSRC, "fd_setup.cpp"), "-o", o])
+    objs.append(o)
     o = os.path.join(OUT_DIR, "kernels.o")
     _run([HIPCC] + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "kernels.hip"), "-o", o])
     objs.append(o)

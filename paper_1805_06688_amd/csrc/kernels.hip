@@ -277,7 +277,7 @@ __device__ __forceinline__ void chunk_range(const Geom& g, int tile, long long& 
 }
 
 __global__ __launch_bounds__(NT) void k_cg_start(Geom g, const PropDesc* __restrict__ desc, int S,
-                                                 const double* ubase, double* xbase, const double* rws, double* pws,
+                                                 const double* ubase, double* xbase, const double* zws, double* pws,
                                                  const double* partial_bb, const double* partial_rr, double rtol2,
                                                  double* bb, int* active, int* iters) {
     int s, tile;
@@ -288,14 +288,14 @@ __global__ __launch_bounds__(NT) void k_cg_start(Geom g, const PropDesc* __restr
     const double r2 = slice_sum(partial_rr, s, g.ntiles);
     const double* u = ubase + d.u * g.stride;
     double* x = xbase + d.x * g.stride;
-    const double* r = rws + (long long)s * g.stride;
+    const double* z = zws + (long long)s * g.stride;
     double* p = pws + (long long)s * g.stride;
     long long lo, hi;
     chunk_range(g, tile, lo, hi);
     const bool zero = !(b2 > 0.0);
     for (long long e = lo + threadIdx.x; e < hi; e += NT) {
         x[e] = zero ? 0.0 : u[e];
-        p[e] = r[e];
+        p[e] = z[e];
     }
     if (tile == 0 && threadIdx.x == 0) {
         bb[s] = b2;
@@ -304,17 +304,18 @@ __global__ __launch_bounds__(NT) void k_cg_start(Geom g, const PropDesc* __restr
     }
 }
 
+// alpha = rho / (p.q) with rho = r.z (z = r without preconditioner)
 __global__ __launch_bounds__(NT) void k_cg_update(Geom g, const PropDesc* __restrict__ desc, int S, double* xbase,
                                                   double* rws, const double* pws, const double* qws,
-                                                  const double* partial_rr, const double* partial_pq,
+                                                  const double* partial_rho, const double* partial_pq,
                                                   double* partial_rr_new, const int* active) {
     int s, tile;
     decode_block(g.ntiles, S, s, tile);
     if (s < 0 || !active[s]) return;
     __shared__ double red[4];
-    const double rr = slice_sum(partial_rr, s, g.ntiles);
+    const double rho = slice_sum(partial_rho, s, g.ntiles);
     const double pq = slice_sum(partial_pq, s, g.ntiles);
-    const double alpha = rr / pq;
+    const double alpha = rho / pq;
     double* x = xbase + desc[s].x * g.stride;
     const long long so = (long long)s * g.stride;
     double* r = rws + so;
@@ -333,10 +334,11 @@ __global__ __launch_bounds__(NT) void k_cg_update(Geom g, const PropDesc* __rest
     if (threadIdx.x == 0) partial_rr_new[(long long)s * g.ntiles + tile] = acc;
 }
 
-__global__ __launch_bounds__(NT) void k_cg_direction(Geom g, int S, const double* rws, double* pws,
-                                                     const double* partial_rr, const double* partial_rr_new,
-                                                     const double* bb, double rtol2, int maxit, const int* active,
-                                                     int* active_next, int* iters) {
+// p = z + beta p, beta = rho_new / rho; convergence on ||r||^2 <= rtol^2 ||b||^2
+__global__ __launch_bounds__(NT) void k_cg_direction(Geom g, int S, const double* zws, double* pws,
+                                                     const double* partial_rho, const double* partial_rho_new,
+                                                     const double* partial_rr_new, const double* bb, double rtol2,
+                                                     int maxit, const int* active, int* active_next, int* iters) {
     int s, tile;
     decode_block(g.ntiles, S, s, tile);
     if (s < 0) return;
@@ -344,19 +346,131 @@ __global__ __launch_bounds__(NT) void k_cg_direction(Geom g, int S, const double
         if (tile == 0 && threadIdx.x == 0) active_next[s] = 0;
         return;
     }
-    const double rr = slice_sum(partial_rr, s, g.ntiles);
-    const double rrn = slice_sum(partial_rr_new, s, g.ntiles);
-    const double beta = rrn / rr;
+    const double rho = slice_sum(partial_rho, s, g.ntiles);
+    const double rhon = slice_sum(partial_rho_new, s, g.ntiles);
+    const double beta = rhon / rho;
     const long long so = (long long)s * g.stride;
-    const double* r = rws + so;
+    const double* z = zws + so;
     double* p = pws + so;
     long long lo, hi;
     chunk_range(g, tile, lo, hi);
-    for (long long e = lo + threadIdx.x; e < hi; e += NT) p[e] = r[e] + beta * p[e];
+    for (long long e = lo + threadIdx.x; e < hi; e += NT) p[e] = z[e] + beta * p[e];
     if (tile == 0 && threadIdx.x == 0) {
+        const double rrn = slice_sum(partial_rr_new, s, g.ntiles);
         const int it = iters[s] + 1;
         iters[s] = it;
         active_next[s] = (rrn > rtol2 * bb[s] && it < maxit) ? 1 : 0;
+    }
+}
+
+// ---- fast-diagonalisation preconditioner: batched dense FP64 products ----
+// LEFT:  Y[s] = A X[s]   (contraction over x), A given transposed: AT[k][i] = A[i][k]
+// RIGHT: Y[s] = X[s] B   (contraction over y), B[k][j] row-major
+// EPI 0: store; 1: scale by 1 / (1 + theta_s (lx[i] + ly[j])); 2: store and partial dot with r
+constexpr int GAS = 80;                        // LDS stride of [k][i] tiles
+constexpr int GBS = KC + 2;                    // LDS stride of [j][k] tiles
+constexpr int FD_LDS = (2 * KC * GAS > EPI) ? 2 * KC * GAS : EPI;
+template <bool LEFT, int EPI>
+__global__ __launch_bounds__(NT) void k_fd_gemm(Geom g, int S, const double* __restrict__ mat,
+                                                const double* __restrict__ xin, double* __restrict__ yout,
+                                                const PropDesc* __restrict__ desc, const double* __restrict__ lx,
+                                                const double* __restrict__ ly, const double* __restrict__ rws,
+                                                double* partial, const int* active) {
+    int s, tile;
+    decode_block(g.ntiles, S, s, tile);
+    if (s < 0) return;
+    if (active && !active[s]) return;
+    __shared__ double lds[FD_LDS];
+    __shared__ double red[4];
+    const int nx = g.nx, ny = g.ny;
+    const int ti = tile % g.tiles_x, tj = tile / g.tiles_x;
+    const int i0 = ti * T, j0 = tj * T;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int wi = wave & 1, wj = wave >> 1;
+    const long long so = (long long)s * g.stride;
+    const double* X = xin + so;
+    const int K = LEFT ? nx : ny;
+    double* At = lds;                 // [k][i], stride GAS
+    double* Bt = lds + KC * GAS;      // LEFT: [j][k] stride GBS; RIGHT: [k][j] stride GAS
+
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    for (int k0 = 0; k0 < K; k0 += KC) {
+        for (int idx = tid; idx < KC * T; idx += NT) {
+            const int kk = idx / T, ii = idx - kk * T;
+            const int k = k0 + kk;
+            if (LEFT) {
+                const int i = i0 + ii;        // A[i][k] = AT[k][i]
+                At[kk * GAS + ii] = (k < nx && i < nx) ? mat[(long long)k * nx + i] : 0.0;
+            } else {
+                const int i = i0 + ii;        // A = X[i][k] = X[i + nx k]
+                At[kk * GAS + ii] = (k < ny && i < nx) ? X[(long long)k * nx + i] : 0.0;
+            }
+        }
+        for (int idx = tid; idx < KC * T; idx += NT) {
+            if (LEFT) {                       // B = X[k][j] = X[k + nx j] -> [j][k]
+                const int jj = idx / KC, kk = idx - jj * KC;
+                const int k = k0 + kk, j = j0 + jj;
+                Bt[jj * GBS + kk] = (k < nx && j < ny) ? X[(long long)j * nx + k] : 0.0;
+            } else {                          // B = mat[k][j] -> [k][j]
+                const int kk = idx / T, jj = idx - kk * T;
+                const int k = k0 + kk, j = j0 + jj;
+                Bt[kk * GAS + jj] = (k < ny && j < ny) ? mat[(long long)k * ny + j] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < KC; ks += 4) {
+            const int kk = ks + lk;
+            double a[2], b[2];
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                a[f] = At[kk * GAS + wi * 32 + f * 16 + lr];
+                const int jl = wj * 32 + f * 16 + lr;
+                b[f] = LEFT ? Bt[jl * GBS + kk] : Bt[kk * GAS + jl];
+            }
+#pragma unroll
+            for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+                for (int fj = 0; fj < 2; ++fj)
+                    acc[fi][fj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[fi], b[fj], acc[fi][fj], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    double* epi = lds;
+#pragma unroll
+    for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+        for (int fj = 0; fj < 2; ++fj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int il = wi * 32 + fi * 16 + lk + 4 * r;
+                const int jl = wj * 32 + fj * 16 + lr;
+                epi[jl * (T + 1) + il] = acc[fi][fj][r];
+            }
+    __syncthreads();
+    double* Y = yout + so;
+    const double theta = EPI == 1 ? desc[s].theta_lhs : 0.0;
+    double dot = 0.0;
+    for (int idx = tid; idx < T * T; idx += NT) {
+        const int jl = idx / T, il = idx - jl * T;
+        const int i = i0 + il, j = j0 + jl;
+        if (i >= nx || j >= ny) continue;
+        const long long o = (long long)j * nx + i;
+        double v = epi[jl * (T + 1) + il];
+        if (EPI == 1) v /= 1.0 + theta * (lx[i] + ly[j]);
+        Y[o] = v;
+        if (EPI == 2) dot += v * rws[so + o];
+    }
+    if (EPI == 2) {
+        dot = block_sum(dot, red);
+        if (threadIdx.x == 0) partial[(long long)s * g.ntiles + tile] = dot;
     }
 }
 
@@ -436,11 +550,11 @@ int launch_init_residual(const Geom* g, const Seqs* sq, const PropDesc* desc, in
 }
 
 int launch_cg_start(const Geom* g, const PropDesc* desc, int S, const double* ubase, double* xbase,
-                    const double* rws, double* pws, const double* partial_bb, const double* partial_rr,
+                    const double* zws, double* pws, const double* partial_bb, const double* partial_rr,
                     double rtol2, double* bb, int* active, int* iters, void* stream) {
     if (S <= 0) return 0;
     hipLaunchKernelGGL(k_cg_start, dim3(grid_blocks(g->ntiles, S)), dim3(NT), 0, (hipStream_t)stream, *g, desc, S,
-                       ubase, xbase, rws, pws, partial_bb, partial_rr, rtol2, bb, active, iters);
+                       ubase, xbase, zws, pws, partial_bb, partial_rr, rtol2, bb, active, iters);
     return (int)hipGetLastError();
 }
 
@@ -453,20 +567,38 @@ int launch_cg_apply(const Geom* g, const Seqs* sq, const PropDesc* desc, int S, 
 }
 
 int launch_cg_update(const Geom* g, const PropDesc* desc, int S, double* xbase, double* rws, const double* pws,
-                     const double* qws, const double* partial_rr, const double* partial_pq,
+                     const double* qws, const double* partial_rho, const double* partial_pq,
                      double* partial_rr_new, const int* active, void* stream) {
     if (S <= 0) return 0;
     hipLaunchKernelGGL(k_cg_update, dim3(grid_blocks(g->ntiles, S)), dim3(NT), 0, (hipStream_t)stream, *g, desc, S,
-                       xbase, rws, pws, qws, partial_rr, partial_pq, partial_rr_new, active);
+                       xbase, rws, pws, qws, partial_rho, partial_pq, partial_rr_new, active);
     return (int)hipGetLastError();
 }
 
-int launch_cg_direction(const Geom* g, int S, const double* rws, double* pws, const double* partial_rr,
-                        const double* partial_rr_new, const double* bb, double rtol2, int maxit,
-                        const int* active, int* active_next, int* iters, void* stream) {
+int launch_cg_direction(const Geom* g, int S, const double* zws, double* pws, const double* partial_rho,
+                        const double* partial_rho_new, const double* partial_rr_new, const double* bb, double rtol2,
+                        int maxit, const int* active, int* active_next, int* iters, void* stream) {
     if (S <= 0) return 0;
-    hipLaunchKernelGGL(k_cg_direction, dim3(grid_blocks(g->ntiles, S)), dim3(NT), 0, (hipStream_t)stream, *g, S, rws,
-                       pws, partial_rr, partial_rr_new, bb, rtol2, maxit, active, active_next, iters);
+    hipLaunchKernelGGL(k_cg_direction, dim3(grid_blocks(g->ntiles, S)), dim3(NT), 0, (hipStream_t)stream, *g, S, zws,
+                       pws, partial_rho, partial_rho_new, partial_rr_new, bb, rtol2, maxit, active, active_next,
+                       iters);
+    return (int)hipGetLastError();
+}
+
+int launch_fd_apply(const Geom* g, const FdMats* fd, const PropDesc* desc, int S, const double* rws, double* zws,
+                    double* t1, double* t2, double* partial_rz, const int* active, void* stream) {
+    if (S <= 0) return 0;
+    const dim3 grid(grid_blocks(g->ntiles, S)), blk(NT);
+    hipStream_t st = (hipStream_t)stream;
+    // t1 = Vx^T r ; t2 = (t1 Vy) / (1 + theta (lx + ly)) ; t1 = Vx t2 ; z = t1 Vy^T (+ r.z)
+    hipLaunchKernelGGL((k_fd_gemm<true, 0>), grid, blk, 0, st, *g, S, fd->Vx, rws, t1, desc, fd->lx, fd->ly,
+                       (const double*)nullptr, (double*)nullptr, active);
+    hipLaunchKernelGGL((k_fd_gemm<false, 1>), grid, blk, 0, st, *g, S, fd->Vy, (const double*)t1, t2, desc, fd->lx,
+                       fd->ly, (const double*)nullptr, (double*)nullptr, active);
+    hipLaunchKernelGGL((k_fd_gemm<true, 0>), grid, blk, 0, st, *g, S, fd->VxT, (const double*)t2, t1, desc, fd->lx,
+                       fd->ly, (const double*)nullptr, (double*)nullptr, active);
+    hipLaunchKernelGGL((k_fd_gemm<false, 2>), grid, blk, 0, st, *g, S, fd->VyT, (const double*)t1, zws, desc, fd->lx,
+                       fd->ly, rws, partial_rz, active);
     return (int)hipGetLastError();
 }
 

@@ -104,7 +104,10 @@ struct mgrit_handle {
     int Smax = 0;
     // CG workspace
     double *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *tmp = nullptr;
+    double *z = nullptr, *t1 = nullptr, *t2 = nullptr;      // preconditioner workspace
+    FdMats fd;
     double *pbb = nullptr, *prr[2] = {nullptr, nullptr}, *ppq = nullptr, *pnorm = nullptr;
+    double* prz[2] = {nullptr, nullptr};
     double* bb = nullptr;
     int* act[2] = {nullptr, nullptr};
     int* iters = nullptr;
@@ -113,6 +116,12 @@ struct mgrit_handle {
     double* h_norm = nullptr;                // pinned
     long long phi_count = 0, cg_count = 0;
     std::vector<void*> allocations;
+    // instrumentation of the CG operator kernel
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;
+    size_t prof_used = 0;
+    double prof_ms = 0.0;
+    long long prof_launches = 0, prof_slices = 0;
     // caller arrays of the current solve (level 0)
     double* U0 = nullptr;
     const double* F0 = nullptr;
@@ -174,15 +183,28 @@ void make_step(const mgrit_handle* h, int l, int k, int u, int x, int tmp_slot, 
         d.theta_lhs = tau;
         b.pass[0].h.push_back(d);
         b.npass = 1;
-    } else if (h->opt.coarse == MGRIT_COARSE_CN2) {
+    } else if (h->opt.coarse == MGRIT_COARSE_CN2 || h->opt.coarse == MGRIT_COARSE_OPT) {
+        double s1 = 0.5 * tau, s2 = 0.5 * tau;   // two half steps
+        if (h->opt.coarse == MGRIT_COARSE_OPT) {
+            // Match the product of the level-0 Crank-Nicolson factors inside
+            // this coarse step at small and at large tau~ sigma.
+            const int i0 = h->lv[l].fine[k - 1], i1 = h->lv[l].fine[k];
+            double inv = 0.0;
+            for (int n = i0 + 1; n <= i1; ++n) inv += 1.0 / (h->t[n] - h->t[n - 1]);
+            const double c = 4.0 * tau * inv;
+            const double dd = std::sqrt(c * c / 16.0 - c);
+            const double a1 = c / 4.0 + dd, a2 = c / 4.0 - dd;
+            s1 = 2.0 * tau / a1;   // short step first
+            s2 = 2.0 * tau / a2;
+        }
         PropDesc d1 = d, d2 = d;
         d1.x = tmp_slot;
         d1.g = -1;
-        d1.theta_rhs = -0.25 * tau;
-        d1.theta_lhs = 0.25 * tau;
+        d1.theta_rhs = -0.5 * s1;
+        d1.theta_lhs = 0.5 * s1;
         d2.u = tmp_slot;
-        d2.theta_rhs = -0.25 * tau;
-        d2.theta_lhs = 0.25 * tau;
+        d2.theta_rhs = -0.5 * s2;
+        d2.theta_lhs = 0.5 * s2;
         b.pass[0].h.push_back(d1);
         b.pass[1].h.push_back(d2);
         b.npass = 2;
@@ -341,6 +363,39 @@ int build_sequences(mgrit_handle* h) {
     return 0;
 }
 
+// Eigen-decompositions of the 1-D (K, M) pairs of the preconditioner.
+int build_fd(mgrit_handle* h) {
+    const mgrit_problem& p = h->prob;
+    const int nx = p.Mx - 1, ny = p.My - 1;
+    const double hx = (p.b - p.a) / p.Mx, hy = (p.d - p.c) / p.My;
+    std::vector<double> Vx((size_t)nx * nx), lx(nx), Vy((size_t)ny * ny), ly(ny);
+    if (mgrit_fd_eigen(p.beta, nx, hx, p.Kx, Vx.data(), lx.data()) != 0 ||
+        mgrit_fd_eigen(p.gamma, ny, hy, p.Ky, Vy.data(), ly.data()) != 0)
+        return fail(MGRIT_EINVAL, "eigen-decomposition of the preconditioner failed");
+    std::vector<double> VxT(Vx.size()), VyT(Vy.size());
+    for (int i = 0; i < nx; ++i)
+        for (int k = 0; k < nx; ++k) VxT[(size_t)i * nx + k] = Vx[(size_t)k * nx + i];
+    for (int i = 0; i < ny; ++i)
+        for (int k = 0; k < ny; ++k) VyT[(size_t)i * ny + k] = Vy[(size_t)k * ny + i];
+    double* d = nullptr;
+    const size_t total = 2 * Vx.size() + 2 * Vy.size() + nx + ny;
+    CHK(dalloc(h, &d, total));
+    size_t o = 0;
+    auto put = [&](const std::vector<double>& v, const double** dst) -> int {
+        HIPCHK(hipMemcpy(d + o, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+        *dst = d + o;
+        o += v.size();
+        return 0;
+    };
+    CHK(put(Vx, &h->fd.Vx));
+    CHK(put(VxT, &h->fd.VxT));
+    CHK(put(Vy, &h->fd.Vy));
+    CHK(put(VyT, &h->fd.VyT));
+    CHK(put(lx, &h->fd.lx));
+    CHK(put(ly, &h->fd.ly));
+    return 0;
+}
+
 int alloc_workspace(mgrit_handle* h, int S) {
     const size_t st = (size_t)h->geom.stride;
     const size_t nt = (size_t)h->geom.ntiles;
@@ -348,7 +403,14 @@ int alloc_workspace(mgrit_handle* h, int S) {
     CHK(dalloc(h, &h->r, S * st));
     CHK(dalloc(h, &h->p, S * st));
     CHK(dalloc(h, &h->q, S * st));
-    if (h->opt.coarse == MGRIT_COARSE_CN2) CHK(dalloc(h, &h->tmp, S * st));
+    if (h->opt.coarse == MGRIT_COARSE_CN2 || h->opt.coarse == MGRIT_COARSE_OPT) CHK(dalloc(h, &h->tmp, S * st));
+    if (h->opt.precond == MGRIT_PRECOND_FD) {
+        CHK(dalloc(h, &h->z, S * st));
+        CHK(dalloc(h, &h->t1, S * st));
+        CHK(dalloc(h, &h->t2, S * st));
+        CHK(dalloc(h, &h->prz[0], S * nt));
+        CHK(dalloc(h, &h->prz[1], S * nt));
+    }
     CHK(dalloc(h, &h->pbb, S * nt));
     CHK(dalloc(h, &h->prr[0], S * nt));
     CHK(dalloc(h, &h->prr[1], S * nt));
@@ -364,6 +426,28 @@ int alloc_workspace(mgrit_handle* h, int S) {
     return 0;
 }
 
+int prof_record(mgrit_handle* h) {
+    if (h->prof_used == h->prof_ev.size()) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        h->prof_ev.push_back(e);
+    }
+    HIPCHK(hipEventRecord(h->prof_ev[h->prof_used++], h->stream));
+    return 0;
+}
+
+// Accumulate the recorded event pairs (the stream has been synchronised).
+int prof_drain(mgrit_handle* h) {
+    for (size_t i = 0; i + 1 < h->prof_used; i += 2) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->prof_ev[i], h->prof_ev[i + 1]));
+        h->prof_ms += ms;
+        h->prof_launches += 1;
+    }
+    h->prof_used = 0;
+    return 0;
+}
+
 // Batched CG solve of one pass (S <= Smax slices).
 int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase, const double* fbase,
              const double* gbase) {
@@ -373,27 +457,36 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     const Geom* g = &h->geom;
     void* st = (void*)h->stream;
     const double rtol2 = h->opt.cg_rtol * h->opt.cg_rtol;
+    const bool pc = h->opt.precond == MGRIT_PRECOND_FD;
     HIPCHK(launch_rhs(g, &h->seqs, ps.d, S, ubase, fbase, h->b, h->pbb, st));
     HIPCHK(launch_init_residual(g, &h->seqs, ps.d, S, ubase, h->b, h->r, h->prr[0], st));
-    HIPCHK(launch_cg_start(g, ps.d, S, ubase, xbase, h->r, h->p, h->pbb, h->prr[0], rtol2, h->bb, h->act[0], h->iters,
-                           st));
+    if (pc) HIPCHK(launch_fd_apply(g, &h->fd, ps.d, S, h->r, h->z, h->t1, h->t2, h->prz[0], nullptr, st));
+    double* zws = pc ? h->z : h->r;
+    double** prho = pc ? h->prz : h->prr;        // rho = r.z (r.r without preconditioner)
+    HIPCHK(launch_cg_start(g, ps.d, S, ubase, xbase, zws, h->p, h->pbb, h->prr[0], rtol2, h->bb, h->act[0],
+                           h->iters, st));
     int cur = 0;
     int it = 0;
     const int maxit = h->opt.cg_maxit;
-    int chunk = 8;
+    int chunk = pc ? 4 : 8;
     while (true) {
         HIPCHK(hipMemcpyAsync(h->h_act, h->act[cur], S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
+        if (h->prof_on) CHK(prof_drain(h));
         bool any = false;
         for (int s = 0; s < S; ++s) any |= h->h_act[s] != 0;
         if (!any || it >= maxit) break;
         for (int c = 0; c < chunk && it < maxit; ++c, ++it) {
             const int nxt = cur ^ 1;
+            if (h->prof_on) CHK(prof_record(h));
             HIPCHK(launch_cg_apply(g, &h->seqs, ps.d, S, h->p, h->q, h->ppq, h->act[cur], st));
-            HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, h->prr[cur], h->ppq, h->prr[nxt],
+            if (h->prof_on) CHK(prof_record(h));
+            HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, prho[cur], h->ppq, h->prr[nxt],
                                     h->act[cur], st));
-            HIPCHK(launch_cg_direction(g, S, h->r, h->p, h->prr[cur], h->prr[nxt], h->bb, rtol2, maxit, h->act[cur],
-                                       h->act[nxt], h->iters, st));
+            if (pc)
+                HIPCHK(launch_fd_apply(g, &h->fd, ps.d, S, h->r, h->z, h->t1, h->t2, h->prz[nxt], h->act[cur], st));
+            HIPCHK(launch_cg_direction(g, S, zws, h->p, prho[cur], prho[nxt], h->prr[nxt], h->bb, rtol2, maxit,
+                                       h->act[cur], h->act[nxt], h->iters, st));
             cur = nxt;
         }
         chunk = std::min(chunk * 2, 32);
@@ -401,7 +494,10 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     HIPCHK(launch_add_g(g, ps.d, S, xbase, gbase, st));
     HIPCHK(hipMemcpyAsync(h->h_iters, h->iters, S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    for (int s = 0; s < S; ++s) h->cg_count += h->h_iters[s];
+    long long its = 0;
+    for (int s = 0; s < S; ++s) its += h->h_iters[s];
+    h->cg_count += its;
+    if (h->prof_on) h->prof_slices += its;
     h->phi_count += S;
     return 0;
 }
@@ -597,8 +693,10 @@ void mgrit_default_options(mgrit_options* o) {
     o->precision = MGRIT_PREC_FP64;
     o->max_iter = 100;
     o->tol_abs = 1e-9;
+    o->tol_rel = 0.0;
     o->cg_rtol = 1e-9;
     o->cg_maxit = 10000;
+    o->precond = MGRIT_PRECOND_NONE;
     o->divergence_factor = 0.0;
 }
 
@@ -621,10 +719,14 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
     if (o.m < 2) return fail(MGRIT_EINVAL, "m must be >= 2");
     if (o.max_levels < 2) return fail(MGRIT_EINVAL, "max_levels must be >= 2");
     if (o.relax != MGRIT_RELAX_F && o.relax != MGRIT_RELAX_FCF) return fail(MGRIT_EINVAL, "unknown relaxation");
-    if (o.coarse < MGRIT_COARSE_CN || o.coarse > MGRIT_COARSE_CN2)
+    if (o.coarse < MGRIT_COARSE_CN || o.coarse > MGRIT_COARSE_OPT)
         return fail(MGRIT_EINVAL, "unknown coarse propagator");
+    if (o.coarse == MGRIT_COARSE_OPT && (o.m % 2))
+        return fail(MGRIT_EINVAL, "the OPT coarse propagator needs an even coarsening factor");
     if (o.precision != MGRIT_PREC_FP64) return fail(MGRIT_EINVAL, "unknown precision");
-    if (o.max_iter < 1 || o.cg_maxit < 1 || !(o.cg_rtol > 0.0) || !(o.tol_abs >= 0.0))
+    if (o.precond != MGRIT_PRECOND_NONE && o.precond != MGRIT_PRECOND_FD)
+        return fail(MGRIT_EINVAL, "unknown preconditioner");
+    if (o.max_iter < 1 || o.cg_maxit < 1 || !(o.cg_rtol > 0.0) || !(o.tol_abs >= 0.0) || !(o.tol_rel >= 0.0))
         return fail(MGRIT_EINVAL, "bad iteration limits or tolerances");
     const long long nx = p.Mx - 1, ny = p.My - 1;
     if (nx * ny > (1LL << 30)) return fail(MGRIT_EINVAL, "grid too large");
@@ -647,6 +749,7 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
     g.seq_off_y = g.tiles_y * MGRIT_TILE + MGRIT_TILE + MGRIT_KC;
     g.mass = ((p.b - p.a) / p.Mx) * ((p.d - p.c) / p.My) / 12.0;
     int rc = build_sequences(h);
+    if (!rc && o.precond == MGRIT_PRECOND_FD) rc = build_fd(h);
     if (!rc) rc = build_levels(h);
     if (!rc) rc = alloc_workspace(h, h->Smax);
     if (rc) {
@@ -662,6 +765,7 @@ void mgrit_destroy(mgrit_handle* h) {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
     for (void* p : h->allocations) (void)hipFree(p);
+    for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
     if (h->h_act) (void)hipHostFree(h->h_act);
     if (h->h_iters) (void)hipHostFree(h->h_iters);
     if (h->h_norm) (void)hipHostFree(h->h_norm);
@@ -683,7 +787,7 @@ int mgrit_solve(mgrit_handle* h, const double* F, const double* psi0, const doub
         CHK(residual(h, 0, &n2));
         const double norm = std::sqrt(hxy * n2);
         hist.push_back(norm);
-        if (norm < h->opt.tol_abs) {
+        if (norm < h->opt.tol_abs || norm < h->opt.tol_rel * hist[0]) {
             conv = 1;
             break;
         }
@@ -832,6 +936,25 @@ int mgrit_sequences(const mgrit_handle* h, double* seq_x, double* seq_y, double*
     if (seq_y) std::memcpy(seq_y, h->host_seq_y.data(), h->host_seq_y.size() * sizeof(double));
     if (cx) *cx = h->cx;
     if (cy) *cy = h->cy;
+    return MGRIT_OK;
+}
+
+int mgrit_profile_enable(mgrit_handle* h, int on) {
+    if (!h) return fail(MGRIT_EINVAL, "NULL handle");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->prof_on = on != 0;
+    h->prof_used = 0;
+    h->prof_ms = 0.0;
+    h->prof_launches = 0;
+    h->prof_slices = 0;
+    return MGRIT_OK;
+}
+
+int mgrit_profile_read(const mgrit_handle* h, double* apply_ms, long long* launches, long long* slice_applies) {
+    if (!h) return fail(MGRIT_EINVAL, "NULL handle");
+    if (apply_ms) *apply_ms = h->prof_ms;
+    if (launches) *launches = h->prof_launches;
+    if (slice_applies) *slice_applies = h->prof_slices;
     return MGRIT_OK;
 }
 

@@ -56,9 +56,24 @@ typedef struct {
     const double* A2y;
 } Seqs;
 
+// Device matrices of the fast-diagonalisation preconditioner (row-major):
+// Vx[k][i] = component k of eigenvector i (x), VxT its transpose, likewise y;
+// lx, ly the generalised eigenvalues.
+typedef struct {
+    const double* Vx;
+    const double* VxT;
+    const double* Vy;
+    const double* VyT;
+    const double* lx;
+    const double* ly;
+} FdMats;
+
 // Host set-up (toeplitz_setup.cpp).
 void mgrit_toeplitz_sequences(double rho, int n, double* t, double* u, double* w);
 double mgrit_stiffness_scale(double rho, double h_par, double h_perp);
+// Fast-diagonalisation preconditioner set-up (fd_setup.cpp).
+double mgrit_fd_stiffness_entry(double rho, double h, double K, int l);
+int mgrit_fd_eigen(double rho, int n, double h, double K, double* V, double* lambda);
 
 // Kernel launchers (kernels.hip).  All return a hipError_t as int.
 // dot_mode: 0 none, 1 partial[s*ntiles+tile] = sum v*out, 2 = sum out*out.
@@ -72,21 +87,24 @@ int launch_rhs(const Geom* g, const Seqs* sq, const PropDesc* desc, int S, const
 // r[s] = b[s] - (M u + theta_lhs A u), partial of ||r||^2 into partial_rr.
 int launch_init_residual(const Geom* g, const Seqs* sq, const PropDesc* desc, int S, const double* ubase,
                          const double* bws, double* rws, double* partial_rr, void* stream);
-// x = u (or 0 when ||b|| = 0), p = r; active flags from ||r|| vs rtol ||b||.
+// x = u (or 0 when ||b|| = 0), p = z; active flags from ||r|| vs rtol ||b||.
 int launch_cg_start(const Geom* g, const PropDesc* desc, int S, const double* ubase, double* xbase,
-                    const double* rws, double* pws, const double* partial_bb, const double* partial_rr,
+                    const double* zws, double* pws, const double* partial_bb, const double* partial_rr,
                     double rtol2, double* bb, int* active, int* iters, void* stream);
 // q = B p for active slices, partial p.q.
 int launch_cg_apply(const Geom* g, const Seqs* sq, const PropDesc* desc, int S, const double* pws, double* qws,
                     double* partial_pq, const int* active, void* stream);
-// x += alpha p, r -= alpha q; partial r.r into partial_rr_new.
+// alpha = rho / p.q; x += alpha p, r -= alpha q; partial r.r into partial_rr_new.
 int launch_cg_update(const Geom* g, const PropDesc* desc, int S, double* xbase, double* rws, const double* pws,
-                     const double* qws, const double* partial_rr, const double* partial_pq,
+                     const double* qws, const double* partial_rho, const double* partial_pq,
                      double* partial_rr_new, const int* active, void* stream);
-// p = r + beta p; next active flags and iteration counts.
-int launch_cg_direction(const Geom* g, int S, const double* rws, double* pws, const double* partial_rr,
-                        const double* partial_rr_new, const double* bb, double rtol2, int maxit,
-                        const int* active, int* active_next, int* iters, void* stream);
+// p = z + (rho_new / rho) p; next active flags (from ||r||^2) and iteration counts.
+int launch_cg_direction(const Geom* g, int S, const double* zws, double* pws, const double* partial_rho,
+                        const double* partial_rho_new, const double* partial_rr_new, const double* bb, double rtol2,
+                        int maxit, const int* active, int* active_next, int* iters, void* stream);
+// z = P^{-1} r (four batched dense products), partial r.z; active may be NULL.
+int launch_fd_apply(const Geom* g, const FdMats* fd, const PropDesc* desc, int S, const double* rws, double* zws,
+                    double* t1, double* t2, double* partial_rz, const int* active, void* stream);
 // x[s] += G[s] for slices with g >= 0.
 int launch_add_g(const Geom* g, const PropDesc* desc, int S, double* xbase, const double* gbase, void* stream);
 // y[yi[s]] += a * x[xi[s]]; when partial != NULL, partial of ||y||^2 after the update.

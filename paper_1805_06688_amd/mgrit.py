@@ -16,8 +16,9 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmgrit.s
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, EDIVERGED = 0, -1, -2, -3, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 RELAX = {"F": 0, "FCF": 1}
-COARSE = {"cn": 0, "be": 1, "cn2": 2}
+COARSE = {"cn": 0, "be": 1, "cn2": 2, "opt": 3}
 PRECISION = {"fp64": 0}
+PRECOND = {"none": 0, "fd": 1}
 
 
 class _Problem(ctypes.Structure):
@@ -30,7 +31,8 @@ class _Problem(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("max_levels", ctypes.c_int), ("relax", ctypes.c_int),
                 ("coarse", ctypes.c_int), ("precision", ctypes.c_int), ("max_iter", ctypes.c_int),
-                ("tol_abs", ctypes.c_double), ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int),
+                ("tol_abs", ctypes.c_double), ("tol_rel", ctypes.c_double), ("cg_rtol", ctypes.c_double),
+                ("cg_maxit", ctypes.c_int), ("precond", ctypes.c_int),
                 ("divergence_factor", ctypes.c_double)]
 
 
@@ -46,7 +48,8 @@ class Stats(ctypes.Structure):
 
 SYMBOLS = ("mgrit_default_options", "mgrit_setup", "mgrit_solve", "mgrit_iterate", "mgrit_sequential",
            "mgrit_propagate", "mgrit_apply", "mgrit_sequences", "mgrit_levels", "mgrit_destroy",
-           "mgrit_last_error", "mgrit_toeplitz_sequences", "mgrit_stiffness_scale")
+           "mgrit_last_error", "mgrit_toeplitz_sequences", "mgrit_stiffness_scale", "mgrit_profile_enable",
+           "mgrit_profile_read", "mgrit_fd_stiffness_entry", "mgrit_fd_eigen")
 
 
 def load_library(path=_LIB_PATH):
@@ -80,6 +83,15 @@ def load_library(path=_LIB_PATH):
     lib.mgrit_toeplitz_sequences.restype = None
     lib.mgrit_stiffness_scale.argtypes = [c_dbl, c_dbl, c_dbl]
     lib.mgrit_stiffness_scale.restype = c_dbl
+    lib.mgrit_profile_enable.argtypes = [P, c_int]
+    lib.mgrit_profile_enable.restype = c_int
+    lib.mgrit_profile_read.argtypes = [P, ctypes.POINTER(c_dbl), ctypes.POINTER(ctypes.c_longlong),
+                                       ctypes.POINTER(ctypes.c_longlong)]
+    lib.mgrit_profile_read.restype = c_int
+    lib.mgrit_fd_stiffness_entry.argtypes = [c_dbl, c_dbl, c_dbl, c_int]
+    lib.mgrit_fd_stiffness_entry.restype = c_dbl
+    lib.mgrit_fd_eigen.argtypes = [c_dbl, c_int, c_dbl, c_dbl, ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl)]
+    lib.mgrit_fd_eigen.restype = c_int
     lib.mgrit_last_error.argtypes = []
     lib.mgrit_last_error.restype = ctypes.c_char_p
     return lib
@@ -143,6 +155,21 @@ def stiffness_scale(rho, h_par, h_perp):
     return _lib.mgrit_stiffness_scale(float(rho), float(h_par), float(h_perp))
 
 
+def fd_stiffness_entry(rho, h, K, l):
+    return _lib.mgrit_fd_stiffness_entry(float(rho), float(h), float(K), int(l))
+
+
+def fd_eigen(rho, n, h, K):
+    """Generalised eigenpairs of the 1-D (K, M) pair of the preconditioner: (V [n, n], lambda [n])."""
+    V = np.empty((n, n))
+    lam = np.empty(n)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = _lib.mgrit_fd_eigen(float(rho), int(n), float(h), float(K), V.ctypes.data_as(dp), lam.ctypes.data_as(dp))
+    if rc != 0:
+        raise MgritError(rc, "eigen-iteration failed")
+    return V, lam
+
+
 def default_options():
     o = _Options()
     _lib.mgrit_default_options(ctypes.byref(o))
@@ -153,8 +180,8 @@ class Solver:
     """One problem (eqs. 1.1-1.3 on a time grid) set up on the GPU."""
 
     def __init__(self, beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0), m=8, max_levels=30,
-                 relax="FCF", coarse="cn", precision="fp64", max_iter=100, tol_abs=1e-9, cg_rtol=1e-9,
-                 cg_maxit=10000, divergence_factor=0.0, stream=None):
+                 relax="FCF", coarse="cn", precision="fp64", max_iter=100, tol_abs=1e-9, tol_rel=0.0, cg_rtol=1e-9,
+                 cg_maxit=10000, precond="none", divergence_factor=0.0, stream=None):
         self._h = None
         self._t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
         p = _Problem(beta, gamma, Kx, Ky, domain[0], domain[1], domain[2], domain[3], int(Mx), int(My),
@@ -162,7 +189,9 @@ class Solver:
         o = default_options()
         o.m, o.max_levels, o.max_iter, o.cg_maxit = int(m), int(max_levels), int(max_iter), int(cg_maxit)
         o.relax, o.coarse, o.precision = RELAX[relax], COARSE[coarse], PRECISION[precision]
-        o.tol_abs, o.cg_rtol, o.divergence_factor = float(tol_abs), float(cg_rtol), float(divergence_factor)
+        o.precond = PRECOND[precond]
+        o.tol_abs, o.tol_rel = float(tol_abs), float(tol_rel)
+        o.cg_rtol, o.divergence_factor = float(cg_rtol), float(divergence_factor)
         if stream is None:
             stream = self._torch_stream()
         h = ctypes.c_void_p()
@@ -261,6 +290,14 @@ class Solver:
         _check(_lib.mgrit_sequences(self._h, sx.ctypes.data_as(dp), sy.ctypes.data_as(dp), ctypes.byref(cx),
                                     ctypes.byref(cy)))
         return sx, sy, cx.value, cy.value
+
+    def profile(self, on=True):
+        _check(_lib.mgrit_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        ms, n, sl = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_longlong()
+        _check(_lib.mgrit_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(sl)))
+        return ms.value, n.value, sl.value
 
     def levels(self):
         buf = (ctypes.c_int * 64)()

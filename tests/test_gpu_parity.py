@@ -97,7 +97,7 @@ def test_propagate_level0_matches_oracle(geo):
         assert rel(out[i], ref) <= 1e-10, (i, k, rel(out[i], ref))
 
 
-@pytest.mark.parametrize("coarse", ["cn", "be", "cn2"])
+@pytest.mark.parametrize("coarse", ["cn", "be", "cn2", "opt"])
 def test_propagate_coarse_level_matches_oracle(coarse):
     mg = _mg()
     beta, gamma, Kx, Ky, Mx, My = 0.75, 0.85, 2.0, 1.0, 70, 66
@@ -143,6 +143,7 @@ CASES = [  # m, levels, relax, coarse, Nt
     (2, 4, "FCF", "be", 24),
     (3, 3, "FCF", "cn2", 29),          # Nt not a multiple of m: trailing F-points
     (4, 3, "F", "be", 37),
+    (4, 3, "FCF", "opt", 34),
 ]
 
 
@@ -165,7 +166,7 @@ def test_mgrit_iterates_match_oracle(case, iters):
     assert rel(U, ref) <= 1e-10, rel(U, ref)
 
 
-@pytest.mark.parametrize("case", CASES[:3])
+@pytest.mark.parametrize("case", CASES[:3] + CASES[4:])
 def test_mgrit_solve_reaches_sequential(case):
     m, levels, relax, coarse, Nt = case
     mg = _mg()
@@ -239,3 +240,43 @@ def test_full_size_apply_and_step_sampled():
     solver = propagator.CGSolver(op, 1e-14, 20000)
     ref = propagator.cn_step(op, solver, t[1] - t[0], u[0], F[0])
     assert rel(prop[0], ref) <= 1e-10
+
+
+@pytest.mark.parametrize("level,coarse", [(0, "cn"), (1, "opt"), (1, "be")])
+def test_preconditioned_propagate_matches_oracle(level, coarse):
+    """PCG with the fast-diagonalisation preconditioner converges to the same propagator as plain CG."""
+    mg = _mg()
+    beta, gamma, Kx, Ky, Mx, My = 0.65, 0.9, 2.0, 0.5, 97, 70
+    prob = fem.Problem(beta, gamma, Kx, Ky, Mx, My)
+    op = fem.Operator(prob)
+    t = wl.random_grid(24, 13)
+    o = omgrit.MGRIT(op, t, 4, max_levels=3, coarse=coarse, cg_rtol=1e-14)
+    steps = [1, 2, 5] if level else [1, 9, 24]
+    u = wl.random_slices(41, 3, prob.nx, prob.ny)
+    g = wl.random_slices(42, 3, prob.nx, prob.ny)
+    with mg.Solver(beta, gamma, Kx, Ky, Mx, My, t, m=4, max_levels=3, coarse=coarse, cg_rtol=1e-14,
+                   precond="fd") as s:
+        out = host(s.propagate(level, steps, dev(u), dev(g)))
+    solver = propagator.CGSolver(op, 1e-14, 20000)
+    for i, k in enumerate(steps):
+        if level == 0:
+            ref = propagator.cn_step(op, solver, t[k] - t[k - 1], u[i], g[i])
+        else:
+            ref = o.psi(1, k, u[i]) + g[i]
+        assert rel(out[i], ref) <= 1e-10, (i, rel(out[i], ref))
+
+
+@pytest.mark.parametrize("iters", [1, 3])
+def test_preconditioned_mgrit_iterates_match_oracle(iters):
+    mg = _mg()
+    prob, t, F, psi0 = _random_problem(5, 40, beta=0.75, gamma=0.85, Mx=70, My=66, Kx=2.0, Ky=1.0)
+    op = fem.Operator(prob)
+    U0 = wl.random_slices(98, 41, prob.nx, prob.ny)
+    o = omgrit.MGRIT(op, t, 4, max_levels=3, coarse="opt", cg_rtol=1e-14)
+    ref = o.iterate(F, psi0, iters, U0=U0)
+    with mg.Solver(prob.beta, prob.gamma, 2.0, 1.0, prob.Mx, prob.My, t, m=4, max_levels=3, coarse="opt",
+                   cg_rtol=1e-14, precond="fd") as s:
+        U, st, _ = s.iterate(dev(F), dev(psi0), iters, U_init=dev(U0))
+        U = host(U)
+    assert rel(U, ref) <= 1e-10
+    assert st.cg_iterations / st.phi_applications < 30

@@ -65,3 +65,27 @@ def test_setup_rejects_invalid_arguments(kw, code):
     with pytest.raises(mg.MgritError) as ei:
         mg.Solver(**args)
     assert ei.value.code == code
+
+
+@pytest.mark.parametrize("rho,n,h,K", [(0.75, 255, 1 / 256, 2.0), (0.55, 63, 0.1, 1.0), (0.95, 40, 0.025, 7.5),
+                                       (0.8, 1, 0.5, 1.0), (0.8, 2, 0.3, 1.0)])
+def test_fd_eigen_matches_scipy(rho, n, h, K):
+    """Preconditioner set-up: generalised eigenpairs of the 1-D (K, M) pair equal scipy's eigh."""
+    import math
+    import scipy.linalg as sl
+    mg = _lib()
+    import mpmath
+    V, lam = mg.fd_eigen(rho, n, h, K)
+    with mpmath.workdps(40):           # the fourth difference cancels: evaluate it in 40 digits
+        p = 3 - 2 * mpmath.mpf(rho)
+        g = lambda l: mpmath.mpf(0) if l == 0 else mpmath.power(abs(l), p)
+        scale = K * h ** (1 - 2 * rho) / (2 * math.cos(rho * math.pi) * math.gamma(4 - 2 * rho))
+        col = [scale * float(g(l - 2) - 4 * g(l - 1) + 6 * g(l) - 4 * g(l + 1) + g(l + 2)) for l in range(n)]
+    Kd = np.array([[col[abs(i - j)] for j in range(n)] for i in range(n)])
+    M = h / 6 * (4 * np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1))
+    ref = sl.eigh(Kd, M, eigvals_only=True)
+    assert np.allclose(np.sort(lam), ref, rtol=1e-11, atol=1e-12 * ref.max())
+    assert np.abs(V.T @ M @ V - np.eye(n)).max() < 1e-12
+    assert np.abs(V.T @ Kd @ V - np.diag(lam)).max() < 1e-11 * np.abs(lam).max()
+    for l in range(min(n, 5)):
+        assert mg.fd_stiffness_entry(rho, h, K, l) == pytest.approx(Kd[0, l], rel=1e-12)

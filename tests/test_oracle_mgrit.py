@@ -22,10 +22,14 @@ def _setup(N=32, seed=0, grid="random", beta=0.7, gamma=0.8, Mx=10, My=9):
     return p, op, t, F, psi0, ch, Useq
 
 
-@pytest.mark.parametrize("coarse", ["cn", "be", "cn2"])
+@pytest.mark.parametrize("coarse", ["cn", "be", "cn2", "opt"])
 @pytest.mark.parametrize("m,levels", [(4, 2), (2, 5), (3, 3)])
 def test_mgrit_reaches_sequential(coarse, m, levels):
     """The fixed point of MGRIT is sequential stepping, whatever the coarse propagator."""
+    if coarse == "opt" and m % 2:
+        with pytest.raises(ValueError):
+            mgrit.MGRIT(fem.Operator(fem.Problem(0.7, 0.8, 1, 1, 5, 5)), np.linspace(0, 1, 10), m, coarse="opt")
+        return
     p, op, t, F, psi0, ch, Useq = _setup(N=31)
     mg = mgrit.MGRIT(op, t, m, max_levels=levels, coarse=coarse, solver=ch)
     U, it, conv = mg.solve(F, psi0, tol=1e-10, max_iter=60)
@@ -124,3 +128,42 @@ def test_cg_inside_mgrit():
     mg = mgrit.MGRIT(op, t, 4, max_levels=3, coarse="be", cg_rtol=1e-14)
     U, it, conv = mg.solve(F, psi0, tol=1e-9, max_iter=60)
     assert conv and np.linalg.norm(U - Useq) <= 1e-11 * np.linalg.norm(Useq)
+
+
+def test_opt_factors_reproduce_two_fine_steps():
+    """With two fine steps per coarse step the opt factors are exactly those two steps (any lengths)."""
+    for taus in ([0.25, 0.25], [0.1, 0.37], [0.9, 0.05]):
+        short, long_ = mgrit.opt_factors(taus)
+        assert math.isclose(short, min(taus), rel_tol=1e-12) and math.isclose(long_, max(taus), rel_tol=1e-12)
+
+
+def test_opt_m2_two_level_exact_in_one_iteration():
+    p, op, t, F, psi0, ch, Useq = _setup(N=30)
+    mg = mgrit.MGRIT(op, t, 2, max_levels=2, coarse="opt", solver=ch)
+    U = mg.iterate(F, psi0, 1)
+    assert np.abs(U - Useq).max() <= 1e-12 * np.abs(Useq).max()
+
+
+@pytest.mark.parametrize("M", [4, 8, 64])
+def test_opt_factor_matches_ideal_asymptotics(M):
+    """Per mode: R(y) = prod CN factors equals the ideal ((2 - y/M)/(2 + y/M))^M to O(y^2) at 0 and to O(1/y^2)
+    at infinity (uniform fine steps)."""
+    short, long_ = mgrit.opt_factors(np.full(M, 1.0 / M))
+    R = lambda y: (2 - short * y) / (2 + short * y) * (2 - long_ * y) / (2 + long_ * y)
+    ideal = lambda y: ((2 - y / M) / (2 + y / M)) ** M
+    for y in (1e-3, 1e-4):
+        assert abs(R(y) - ideal(y)) < 2 * y * y
+    for y in (1e6, 1e7):
+        assert abs(R(y) - ideal(y)) * y < 1e-2 * 4 * M * M
+    assert abs(R(1e9) - 1) * 1e9 == pytest.approx(4 * M * M, rel=1e-3)
+
+
+def test_opt_converges_fast_on_stiff_problem():
+    """tau sigma_max ~ 80: the paper's coarse propagator barely contracts, opt by more than 50x per iteration."""
+    p, op, t, F, psi0, ch, Useq = _setup(N=64, grid="uniform", Mx=32, My=32, beta=0.75, gamma=0.85)
+    errs = {}
+    for coarse in ("cn", "opt"):
+        mg = mgrit.MGRIT(op, t, 8, max_levels=2, coarse=coarse, solver=ch)
+        errs[coarse] = [np.linalg.norm(mg.iterate(F, psi0, k) - Useq) / np.linalg.norm(Useq) for k in (1, 2)]
+    assert errs["cn"][1] > 0.5 * errs["cn"][0]          # the paper's coarse step barely contracts here
+    assert errs["opt"][1] < errs["opt"][0] / 50 and errs["opt"][0] < 1e-2
