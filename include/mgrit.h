@@ -66,8 +66,12 @@ extern "C" {
  * inverse of the tensor-product (bilinear-element) discretisation of the same
  * operator, applied by fast diagonalisation (see mgrit_fd_eigen); it changes
  * the iteration count only, not the solution the solver converges to. */
-#define MGRIT_PRECOND_NONE 0
-#define MGRIT_PRECOND_FD   1
+#define MGRIT_PRECOND_NONE    0
+#define MGRIT_PRECOND_FD      1
+/* FD_BF16: the same preconditioner with its four dense products in BF16 on the
+ * matrix cores (FP32 accumulation); the operator, residuals and iterates stay
+ * FP64, so the solution is the FP64 one. */
+#define MGRIT_PRECOND_FD_BF16 2
 
 typedef struct {
     double beta, gamma;     /* fractional orders, 1/2 < beta, gamma < 1 (eq. 1.1)        */
@@ -90,6 +94,9 @@ typedef struct {
     double cg_rtol;         /* CG stops when ||r||_2 <= cg_rtol ||b||_2                  */
     int cg_maxit;           /* CG iteration cap per solve                                */
     int precond;            /* MGRIT_PRECOND_*                                           */
+    double cg_rtol_adapt;   /* > 0: inexact early iterations (mgrit_solve only): CG rtol  */
+                            /* of iteration k = clamp(cg_rtol_adapt x ||r_k-1|| / ||r_0||, */
+                            /* cg_rtol, 1e-4), ||r|| the level-0 residual norms; 0: off   */
     double divergence_factor; /* EDIVERGED when a norm exceeds this x the first (0: off) */
 } mgrit_options;
 
@@ -106,7 +113,7 @@ typedef struct mgrit_handle mgrit_handle;
 
 /* Fill `opt` with defaults: m = 8, max_levels = 30, FCF, CN, FP64, max_iter = 100,
  * tol_abs = 1e-9, tol_rel = 0, cg_rtol = 1e-9 (the paper's tolerances, Section 3.2),
- * cg_maxit = 10000, precond = NONE, divergence_factor = 0. */
+ * cg_maxit = 10000, precond = NONE, cg_rtol_adapt = 0, divergence_factor = 0. */
 void mgrit_default_options(mgrit_options* opt);
 
 /* Validate the problem, evaluate the Toeplitz generating sequences of Section 2

@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -105,7 +106,9 @@ struct mgrit_handle {
     // CG workspace
     double *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *tmp = nullptr;
     double *z = nullptr, *t1 = nullptr, *t2 = nullptr;      // preconditioner workspace
+    void *tb1 = nullptr, *tb2 = nullptr;                    // BF16 preconditioner workspace
     FdMats fd;
+    FdMatsB fdb;
     double *pbb = nullptr, *prr[2] = {nullptr, nullptr}, *ppq = nullptr, *pnorm = nullptr;
     double* prz[2] = {nullptr, nullptr};
     double* bb = nullptr;
@@ -116,6 +119,9 @@ struct mgrit_handle {
     double* h_norm = nullptr;                // pinned
     long long phi_count = 0, cg_count = 0;
     std::vector<void*> allocations;
+    double cur_rtol = 0.0;          // CG tolerance of the current MGRIT iteration
+    int force_tile = -1;            // tuning override (MGRIT_FORCE_TILE=0|1)
+    long long tile_threshold = 512; // 64-tiles when S * tiles64 >= this (MGRIT_TILE_THRESHOLD)
     // instrumentation of the CG operator kernel
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;
@@ -363,6 +369,15 @@ int build_sequences(mgrit_handle* h) {
     return 0;
 }
 
+// FP64 -> BF16 bit pattern, round to nearest even (finite inputs).
+unsigned short to_bf16(double v) {
+    const float f = (float)v;
+    unsigned int u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
 // Eigen-decompositions of the 1-D (K, M) pairs of the preconditioner.
 int build_fd(mgrit_handle* h) {
     const mgrit_problem& p = h->prob;
@@ -393,23 +408,66 @@ int build_fd(mgrit_handle* h) {
     CHK(put(VyT, &h->fd.VyT));
     CHK(put(lx, &h->fd.lx));
     CHK(put(ly, &h->fd.ly));
+    if (h->opt.precond != MGRIT_PRECOND_FD_BF16) return 0;
+    // zero-padded BF16 copies: A operands of the products over x are row-major
+    // [i][k] (VxT for Vx^T X, Vx for Vx X); B^T operands of the products over y
+    // are row-major [j][k] (VyT for X Vy, Vy for X Vy^T)
+    const int npx = h->geom.tiles_x[0] * 64, npy = h->geom.tiles_y[0] * 64;
+    std::vector<unsigned short> bx1((size_t)npx * npx, 0), bx2((size_t)npx * npx, 0);
+    std::vector<unsigned short> by1((size_t)npy * npy, 0), by2((size_t)npy * npy, 0);
+    for (int i = 0; i < nx; ++i)
+        for (int k = 0; k < nx; ++k) {
+            bx1[(size_t)i * npx + k] = to_bf16(Vx[(size_t)k * nx + i]);    // (Vx^T)[i][k]
+            bx2[(size_t)i * npx + k] = to_bf16(Vx[(size_t)i * nx + k]);    // Vx[i][k]
+        }
+    for (int j = 0; j < ny; ++j)
+        for (int k = 0; k < ny; ++k) {
+            by1[(size_t)j * npy + k] = to_bf16(Vy[(size_t)k * ny + j]);    // B = Vy: B^T[j][k] = Vy[k][j]
+            by2[(size_t)j * npy + k] = to_bf16(Vy[(size_t)j * ny + k]);    // B = Vy^T: B^T[j][k] = Vy[j][k]
+        }
+    std::vector<float> lxf(npx, 0.f), lyf(npy, 0.f);
+    for (int i = 0; i < nx; ++i) lxf[i] = (float)lx[i];
+    for (int j = 0; j < ny; ++j) lyf[j] = (float)ly[j];
+    unsigned short* b = nullptr;
+    CHK(dalloc(h, &b, bx1.size() * 2 + by1.size() * 2));
+    HIPCHK(hipMemcpy(b, bx1.data(), bx1.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b + bx1.size(), bx2.data(), bx2.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b + 2 * bx1.size(), by1.data(), by1.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b + 2 * bx1.size() + by1.size(), by2.data(), by2.size() * 2, hipMemcpyHostToDevice));
+    h->fdb.VxT = b;
+    h->fdb.Vx = b + bx1.size();
+    h->fdb.VyT = b + 2 * bx1.size();
+    h->fdb.Vy = b + 2 * bx1.size() + by1.size();
+    float* f = nullptr;
+    CHK(dalloc(h, &f, (size_t)npx + npy));
+    HIPCHK(hipMemcpy(f, lxf.data(), npx * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(f + npx, lyf.data(), npy * sizeof(float), hipMemcpyHostToDevice));
+    h->fdb.lx = f;
+    h->fdb.ly = f + npx;
     return 0;
 }
 
 int alloc_workspace(mgrit_handle* h, int S) {
     const size_t st = (size_t)h->geom.stride;
-    const size_t nt = (size_t)h->geom.ntiles;
+    const size_t nt = (size_t)h->geom.pmax;
     CHK(dalloc(h, &h->b, S * st));
     CHK(dalloc(h, &h->r, S * st));
     CHK(dalloc(h, &h->p, S * st));
     CHK(dalloc(h, &h->q, S * st));
     if (h->opt.coarse == MGRIT_COARSE_CN2 || h->opt.coarse == MGRIT_COARSE_OPT) CHK(dalloc(h, &h->tmp, S * st));
-    if (h->opt.precond == MGRIT_PRECOND_FD) {
+    if (h->opt.precond != MGRIT_PRECOND_NONE) {
         CHK(dalloc(h, &h->z, S * st));
-        CHK(dalloc(h, &h->t1, S * st));
-        CHK(dalloc(h, &h->t2, S * st));
         CHK(dalloc(h, &h->prz[0], S * nt));
         CHK(dalloc(h, &h->prz[1], S * nt));
+    }
+    if (h->opt.precond == MGRIT_PRECOND_FD) {
+        CHK(dalloc(h, &h->t1, S * st));
+        CHK(dalloc(h, &h->t2, S * st));
+    }
+    if (h->opt.precond == MGRIT_PRECOND_FD_BF16) {
+        const size_t pb = (size_t)h->geom.tiles_x[0] * 64 * h->geom.tiles_y[0] * 64 * sizeof(unsigned short);
+        CHK(dmalloc(h, &h->tb1, S * pb));
+        CHK(dmalloc(h, &h->tb2, S * pb));
     }
     CHK(dalloc(h, &h->pbb, S * nt));
     CHK(dalloc(h, &h->prr[0], S * nt));
@@ -448,6 +506,13 @@ int prof_drain(mgrit_handle* h) {
     return 0;
 }
 
+// Operator tile edge for a batch of S slices: 64 when the batch fills the
+// chip with such tiles, else 32.
+int tile_variant(const mgrit_handle* h, int S) {
+    if (h->force_tile >= 0) return h->force_tile;
+    return (long long)S * h->geom.ntiles[0] >= h->tile_threshold ? 0 : 1;
+}
+
 // Batched CG solve of one pass (S <= Smax slices).
 int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase, const double* fbase,
              const double* gbase) {
@@ -456,17 +521,29 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     if (S > h->Smax) return fail(MGRIT_EINVAL, "batch of %d slices exceeds workspace (%d)", S, h->Smax);
     const Geom* g = &h->geom;
     void* st = (void*)h->stream;
-    const double rtol2 = h->opt.cg_rtol * h->opt.cg_rtol;
-    const bool pc = h->opt.precond == MGRIT_PRECOND_FD;
-    HIPCHK(launch_rhs(g, &h->seqs, ps.d, S, ubase, fbase, h->b, h->pbb, st));
-    HIPCHK(launch_init_residual(g, &h->seqs, ps.d, S, ubase, h->b, h->r, h->prr[0], st));
-    if (pc) HIPCHK(launch_fd_apply(g, &h->fd, ps.d, S, h->r, h->z, h->t1, h->t2, h->prz[0], nullptr, st));
+    const double rtol = h->cur_rtol > 0.0 ? h->cur_rtol : h->opt.cg_rtol;
+    const double rtol2 = rtol * rtol;
+    const int pk = h->opt.precond;
+    const bool pc = pk != MGRIT_PRECOND_NONE;
+    const int tv = tile_variant(h, S);
+    const int nt = g->ntiles[tv], nc = g->nchunk;
+    const int nrz = pk == MGRIT_PRECOND_FD_BF16 ? g->ntiles[0] : nt;   // r.z partials per slice
+    auto precondition = [&](double* prz_out, const int* act) -> int {
+        if (pk == MGRIT_PRECOND_FD)
+            return launch_fd_apply(g, &h->fd, tv, ps.d, S, h->r, h->z, h->t1, h->t2, prz_out, act, st);
+        return launch_fdb_apply(g, &h->fdb, ps.d, S, h->r, h->z, h->tb1, h->tb2, prz_out, act, st);
+    };
+    HIPCHK(launch_rhs(g, &h->seqs, tv, ps.d, S, ubase, fbase, h->b, h->pbb, st));
+    HIPCHK(launch_init_residual(g, &h->seqs, tv, ps.d, S, ubase, h->b, h->r, h->prr[0], st));
+    if (pc) HIPCHK(precondition(h->prz[0], nullptr));
     double* zws = pc ? h->z : h->r;
     double** prho = pc ? h->prz : h->prr;        // rho = r.z (r.r without preconditioner)
-    HIPCHK(launch_cg_start(g, ps.d, S, ubase, xbase, zws, h->p, h->pbb, h->prr[0], rtol2, h->bb, h->act[0],
+    HIPCHK(launch_cg_start(g, ps.d, S, ubase, xbase, zws, h->p, h->pbb, nt, h->prr[0], nt, rtol2, h->bb, h->act[0],
                            h->iters, st));
     int cur = 0;
     int it = 0;
+    int nrho = pc ? nrz : nt;                    // entries of the current rho partials
+    const int nrho_next = pc ? nrz : nc;
     const int maxit = h->opt.cg_maxit;
     int chunk = pc ? 4 : 8;
     while (true) {
@@ -479,15 +556,15 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
         for (int c = 0; c < chunk && it < maxit; ++c, ++it) {
             const int nxt = cur ^ 1;
             if (h->prof_on) CHK(prof_record(h));
-            HIPCHK(launch_cg_apply(g, &h->seqs, ps.d, S, h->p, h->q, h->ppq, h->act[cur], st));
+            HIPCHK(launch_cg_apply(g, &h->seqs, tv, ps.d, S, h->p, h->q, h->ppq, h->act[cur], st));
             if (h->prof_on) CHK(prof_record(h));
-            HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, prho[cur], h->ppq, h->prr[nxt],
+            HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, prho[cur], nrho, h->ppq, nt, h->prr[nxt],
                                     h->act[cur], st));
-            if (pc)
-                HIPCHK(launch_fd_apply(g, &h->fd, ps.d, S, h->r, h->z, h->t1, h->t2, h->prz[nxt], h->act[cur], st));
-            HIPCHK(launch_cg_direction(g, S, zws, h->p, prho[cur], prho[nxt], h->prr[nxt], h->bb, rtol2, maxit,
-                                       h->act[cur], h->act[nxt], h->iters, st));
+            if (pc) HIPCHK(precondition(h->prz[nxt], h->act[cur]));
+            HIPCHK(launch_cg_direction(g, S, zws, h->p, prho[cur], nrho, prho[nxt], nrho_next, h->prr[nxt], h->bb,
+                                       rtol2, maxit, h->act[cur], h->act[nxt], h->iters, st));
             cur = nxt;
+            nrho = nrho_next;
         }
         chunk = std::min(chunk * 2, 32);
     }
@@ -548,11 +625,12 @@ int residual(mgrit_handle* h, int l, double* norm2) {
     HIPCHK(launch_axpy_slices(g, L.subtract.S, L.subtract.yi, C.G, L.subtract.xi, B.U, -1.0,
                               norm2 ? h->pnorm : nullptr, (void*)h->stream));
     if (norm2) {
-        const size_t n = (size_t)L.subtract.S * g->ntiles;
+        const size_t n = (size_t)L.subtract.S * g->pmax;
         HIPCHK(hipMemcpyAsync(h->h_norm, h->pnorm, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
         double acc = 0.0;
-        for (size_t i = 0; i < n; ++i) acc += h->h_norm[i];
+        for (int s = 0; s < L.subtract.S; ++s)
+            for (int c = 0; c < g->nchunk; ++c) acc += h->h_norm[(size_t)s * g->pmax + c];
         *norm2 = acc;
     }
     return 0;
@@ -664,6 +742,7 @@ int begin_solve(mgrit_handle* h, Staging& sg, const double* F, const double* psi
     HIPCHK(hipMemcpyAsync(*dU, dpsi, st * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     h->U0 = *dU;
     h->F0 = dF;
+    h->cur_rtol = 0.0;
     h->phi_count = 0;
     h->cg_count = 0;
     return 0;
@@ -697,6 +776,7 @@ void mgrit_default_options(mgrit_options* o) {
     o->cg_rtol = 1e-9;
     o->cg_maxit = 10000;
     o->precond = MGRIT_PRECOND_NONE;
+    o->cg_rtol_adapt = 0.0;
     o->divergence_factor = 0.0;
 }
 
@@ -724,9 +804,10 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
     if (o.coarse == MGRIT_COARSE_OPT && (o.m % 2))
         return fail(MGRIT_EINVAL, "the OPT coarse propagator needs an even coarsening factor");
     if (o.precision != MGRIT_PREC_FP64) return fail(MGRIT_EINVAL, "unknown precision");
-    if (o.precond != MGRIT_PRECOND_NONE && o.precond != MGRIT_PRECOND_FD)
+    if (o.precond < MGRIT_PRECOND_NONE || o.precond > MGRIT_PRECOND_FD_BF16)
         return fail(MGRIT_EINVAL, "unknown preconditioner");
-    if (o.max_iter < 1 || o.cg_maxit < 1 || !(o.cg_rtol > 0.0) || !(o.tol_abs >= 0.0) || !(o.tol_rel >= 0.0))
+    if (o.max_iter < 1 || o.cg_maxit < 1 || !(o.cg_rtol > 0.0) || !(o.tol_abs >= 0.0) || !(o.tol_rel >= 0.0) ||
+        !(o.cg_rtol_adapt >= 0.0))
         return fail(MGRIT_EINVAL, "bad iteration limits or tolerances");
     const long long nx = p.Mx - 1, ny = p.My - 1;
     if (nx * ny > (1LL << 30)) return fail(MGRIT_EINVAL, "grid too large");
@@ -738,18 +819,25 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
     h->t.assign(p.t, p.t + p.Nt + 1);
     h->prob.t = h->t.data();
     h->stream = (hipStream_t)stream;
+    if (const char* e = std::getenv("MGRIT_FORCE_TILE")) h->force_tile = std::atoi(e) ? 1 : 0;
+    if (const char* e = std::getenv("MGRIT_TILE_THRESHOLD")) h->tile_threshold = std::atoll(e);
     Geom& g = h->geom;
     g.nx = (int)nx;
     g.ny = (int)ny;
-    g.tiles_x = (g.nx + MGRIT_TILE - 1) / MGRIT_TILE;
-    g.tiles_y = (g.ny + MGRIT_TILE - 1) / MGRIT_TILE;
-    g.ntiles = g.tiles_x * g.tiles_y;
+    for (int v = 0; v < 2; ++v) {
+        const int TT = v == 0 ? 64 : 32;
+        g.tiles_x[v] = (g.nx + TT - 1) / TT;
+        g.tiles_y[v] = (g.ny + TT - 1) / TT;
+        g.ntiles[v] = g.tiles_x[v] * g.tiles_y[v];
+    }
     g.stride = nx * ny;
-    g.seq_off_x = g.tiles_x * MGRIT_TILE + MGRIT_TILE + MGRIT_KC;
-    g.seq_off_y = g.tiles_y * MGRIT_TILE + MGRIT_TILE + MGRIT_KC;
+    g.nchunk = (int)((g.stride + MGRIT_CHUNK - 1) / MGRIT_CHUNK);
+    g.pmax = std::max(g.ntiles[1], g.nchunk);
+    g.seq_off_x = g.tiles_x[0] * 64 + 64 + MGRIT_KC;
+    g.seq_off_y = g.tiles_y[0] * 64 + 64 + MGRIT_KC;
     g.mass = ((p.b - p.a) / p.Mx) * ((p.d - p.c) / p.My) / 12.0;
     int rc = build_sequences(h);
-    if (!rc && o.precond == MGRIT_PRECOND_FD) rc = build_fd(h);
+    if (!rc && o.precond != MGRIT_PRECOND_NONE) rc = build_fd(h);
     if (!rc) rc = build_levels(h);
     if (!rc) rc = alloc_workspace(h, h->Smax);
     if (rc) {
@@ -782,6 +870,10 @@ int mgrit_solve(mgrit_handle* h, const double* F, const double* psi0, const doub
     std::vector<double> hist;
     int it = 0, conv = 0, diverged = 0;
     while (it < h->opt.max_iter) {
+        if (h->opt.cg_rtol_adapt > 0.0) {
+            const double rho = hist.empty() ? 1.0 : hist.back() / hist[0];
+            h->cur_rtol = std::min(1e-4, std::max(h->opt.cg_rtol, h->opt.cg_rtol_adapt * rho));
+        }
         CHK(relax(h, 0));
         double n2 = 0.0;
         CHK(residual(h, 0, &n2));
@@ -798,7 +890,11 @@ int mgrit_solve(mgrit_handle* h, const double* F, const double* psi0, const doub
         ++it;
         CHK(coarse_correct0(h));
     }
-    if (!conv) CHK(f_relax(h, 0));
+    if (!conv) {
+        h->cur_rtol = 0.0;
+        CHK(f_relax(h, 0));
+    }
+    h->cur_rtol = 0.0;
     CHK(end_solve(h, U, dU, mem));
     fill_stats(h, st, it, conv, hist);
     if (diverged) return fail(MGRIT_EDIVERGED, "residual norm grew beyond the divergence guard");
@@ -922,8 +1018,8 @@ int mgrit_apply(mgrit_handle* h, int nslices, const double* theta, double sign, 
     if (e != hipSuccess) return fail(MGRIT_ENOMEM, "descriptor allocation failed");
     sg.owned.push_back(dd);
     HIPCHK(hipMemcpyAsync(dd, hd.data(), nslices * sizeof(ApplyDesc), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(launch_apply(&h->geom, &h->seqs, (const ApplyDesc*)dd, nslices, dv, dout, da, sign, 0, nullptr, nullptr,
-                        (void*)h->stream));
+    HIPCHK(launch_apply(&h->geom, &h->seqs, tile_variant(h, nslices), (const ApplyDesc*)dd, nslices, dv, dout, da,
+                        sign, 0, nullptr, nullptr, (void*)h->stream));
     if (mem == MGRIT_MEM_HOST)
         HIPCHK(hipMemcpyAsync(out, dout, nslices * st * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));

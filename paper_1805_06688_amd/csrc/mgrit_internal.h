@@ -9,12 +9,15 @@
 extern "C" {
 #endif
 
-// Output tile of the operator kernel and of every per-slice vector kernel:
-// TILE x TILE grid points (x rows, y columns).  Per-slice partial sums are
-// stored per tile, so reductions have a fixed order.
+// Output tiles of the operator and preconditioner kernels are TT x TT grid
+// points (x rows, y columns) with TT = 64 (variant 0) or 32 (variant 1); the
+// vector kernels work on chunks of 4096 consecutive elements.  Per-slice
+// partial sums are stored per tile or chunk (at most pmax per slice) and are
+// summed in index order, so every reduction has a fixed order.
 #define MGRIT_TILE 64
 // k-chunk of the Toeplitz contractions staged through LDS.
 #define MGRIT_KC 32
+#define MGRIT_CHUNK 4096
 
 // One slice of a batched propagator call.  Indices refer to slices of the
 // base arrays passed beside the descriptor array (stride n_x * n_y doubles).
@@ -38,12 +41,14 @@ typedef struct {
 
 // Geometry shared by every kernel.
 typedef struct {
-    int nx, ny;             // interior nodes
-    int tiles_x, tiles_y;   // ceil(n / TILE)
-    int ntiles;             // tiles per slice
-    long long stride;       // doubles per slice = nx * ny
-    int seq_off_x, seq_off_y; // index of distance 0 in the padded sequence arrays
-    double mass;            // h_x h_y / 12
+    int nx, ny;                 // interior nodes
+    int tiles_x[2], tiles_y[2]; // ceil(n / TT) for TT = 64, 32
+    int ntiles[2];              // tiles per slice for TT = 64, 32
+    int nchunk;                 // vector-kernel chunks per slice
+    int pmax;                   // partial sums stored per slice
+    long long stride;           // doubles per slice = nx * ny
+    int seq_off_x, seq_off_y;   // index of distance 0 in the padded sequence arrays
+    double mass;                // h_x h_y / 12
 } Geom;
 
 // Padded generating sequences on the device, already multiplied by K c:
@@ -68,6 +73,19 @@ typedef struct {
     const double* ly;
 } FdMats;
 
+// BF16 copies for the reduced-precision preconditioner, zero-padded to
+// npx = 64 tiles_x[0], npy = 64 tiles_y[0]: VxT[i][k] = Vx[k][i] and Vx[i][k]
+// (ld npx) for the products over x; VyT[j][k] = Vy[k][j] and Vy[j][k] (ld npy)
+// for the products over y; lx, ly padded with zeros.
+typedef struct {
+    const unsigned short* VxT;   // BF16 bit patterns
+    const unsigned short* Vx;
+    const unsigned short* VyT;
+    const unsigned short* Vy;
+    const float* lx;
+    const float* ly;
+} FdMatsB;
+
 // Host set-up (toeplitz_setup.cpp).
 void mgrit_toeplitz_sequences(double rho, int n, double* t, double* u, double* w);
 double mgrit_stiffness_scale(double rho, double h_par, double h_perp);
@@ -75,39 +93,46 @@ double mgrit_stiffness_scale(double rho, double h_par, double h_perp);
 double mgrit_fd_stiffness_entry(double rho, double h, double K, int l);
 int mgrit_fd_eigen(double rho, int n, double h, double K, double* V, double* lambda);
 
-// Kernel launchers (kernels.hip).  All return a hipError_t as int.
-// dot_mode: 0 none, 1 partial[s*ntiles+tile] = sum v*out, 2 = sum out*out.
-int launch_apply(const Geom* g, const Seqs* sq, const ApplyDesc* desc, int S, const double* vbase,
+// Kernel launchers (kernels.hip).  All return a hipError_t as int.  `tv`
+// selects the operator/preconditioner tile edge (0: 64, 1: 32).  Partial-sum
+// arrays hold pmax entries per slice; the producers write ntiles[tv] (tiled
+// kernels) or nchunk (vector kernels) of them, and each consumer is told how
+// many to sum.
+// dot_mode: 0 none, 1 partial = sum v*out, 2 = sum out*out.
+int launch_apply(const Geom* g, const Seqs* sq, int tv, const ApplyDesc* desc, int S, const double* vbase,
                  double* outbase, const double* addbase, double sign, int dot_mode, double* partial,
                  const int* active, void* stream);
-// Right-hand side of a batched propagator: b[s] = M u + theta_rhs A u (+ F),
-// partial of ||b||^2.
-int launch_rhs(const Geom* g, const Seqs* sq, const PropDesc* desc, int S, const double* ubase,
+// Right-hand side of a batched propagator: b[s] = M u + theta_rhs A u (+ F), partial of ||b||^2.
+int launch_rhs(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc, int S, const double* ubase,
                const double* fbase, double* bws, double* partial_bb, void* stream);
-// r[s] = b[s] - (M u + theta_lhs A u), partial of ||r||^2 into partial_rr.
-int launch_init_residual(const Geom* g, const Seqs* sq, const PropDesc* desc, int S, const double* ubase,
+// r[s] = b[s] - (M u + theta_lhs A u), partial of ||r||^2.
+int launch_init_residual(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc, int S, const double* ubase,
                          const double* bws, double* rws, double* partial_rr, void* stream);
+// q = B p for active slices, partial p.q.
+int launch_cg_apply(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc, int S, const double* pws,
+                    double* qws, double* partial_pq, const int* active, void* stream);
 // x = u (or 0 when ||b|| = 0), p = z; active flags from ||r|| vs rtol ||b||.
 int launch_cg_start(const Geom* g, const PropDesc* desc, int S, const double* ubase, double* xbase,
-                    const double* zws, double* pws, const double* partial_bb, const double* partial_rr,
-                    double rtol2, double* bb, int* active, int* iters, void* stream);
-// q = B p for active slices, partial p.q.
-int launch_cg_apply(const Geom* g, const Seqs* sq, const PropDesc* desc, int S, const double* pws, double* qws,
-                    double* partial_pq, const int* active, void* stream);
-// alpha = rho / p.q; x += alpha p, r -= alpha q; partial r.r into partial_rr_new.
+                    const double* zws, double* pws, const double* partial_bb, int nbb, const double* partial_rr,
+                    int nrr, double rtol2, double* bb, int* active, int* iters, void* stream);
+// alpha = rho / p.q; x += alpha p, r -= alpha q; partial r.r (nchunk entries).
 int launch_cg_update(const Geom* g, const PropDesc* desc, int S, double* xbase, double* rws, const double* pws,
-                     const double* qws, const double* partial_rho, const double* partial_pq,
+                     const double* qws, const double* partial_rho, int nrho, const double* partial_pq, int npq,
                      double* partial_rr_new, const int* active, void* stream);
 // p = z + (rho_new / rho) p; next active flags (from ||r||^2) and iteration counts.
-int launch_cg_direction(const Geom* g, int S, const double* zws, double* pws, const double* partial_rho,
-                        const double* partial_rho_new, const double* partial_rr_new, const double* bb, double rtol2,
-                        int maxit, const int* active, int* active_next, int* iters, void* stream);
+int launch_cg_direction(const Geom* g, int S, const double* zws, double* pws, const double* partial_rho, int nrho,
+                        const double* partial_rho_new, int nrho_new, const double* partial_rr_new, const double* bb,
+                        double rtol2, int maxit, const int* active, int* active_next, int* iters, void* stream);
 // z = P^{-1} r (four batched dense products), partial r.z; active may be NULL.
-int launch_fd_apply(const Geom* g, const FdMats* fd, const PropDesc* desc, int S, const double* rws, double* zws,
-                    double* t1, double* t2, double* partial_rz, const int* active, void* stream);
+int launch_fd_apply(const Geom* g, const FdMats* fd, int tv, const PropDesc* desc, int S, const double* rws,
+                    double* zws, double* t1, double* t2, double* partial_rz, const int* active, void* stream);
+// Same with BF16 products and FP32 accumulation (64-tiles; t1, t2 hold S padded BF16 slices;
+// ntiles[0] partials of r.z).
+int launch_fdb_apply(const Geom* g, const FdMatsB* fd, const PropDesc* desc, int S, const double* rws, double* zws,
+                     void* t1, void* t2, double* partial_rz, const int* active, void* stream);
 // x[s] += G[s] for slices with g >= 0.
 int launch_add_g(const Geom* g, const PropDesc* desc, int S, double* xbase, const double* gbase, void* stream);
-// y[yi[s]] += a * x[xi[s]]; when partial != NULL, partial of ||y||^2 after the update.
+// y[yi[s]] += a * x[xi[s]]; when partial != NULL, partial of ||y||^2 after the update (nchunk entries).
 int launch_axpy_slices(const Geom* g, int S, const int* yi, double* ybase, const int* xi, const double* xbase,
                        double a, double* partial, void* stream);
 // Fill slices of an array with zero.

@@ -18,7 +18,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 RELAX = {"F": 0, "FCF": 1}
 COARSE = {"cn": 0, "be": 1, "cn2": 2, "opt": 3}
 PRECISION = {"fp64": 0}
-PRECOND = {"none": 0, "fd": 1}
+PRECOND = {"none": 0, "fd": 1, "fd-bf16": 2}
 
 
 class _Problem(ctypes.Structure):
@@ -32,7 +32,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("max_levels", ctypes.c_int), ("relax", ctypes.c_int),
                 ("coarse", ctypes.c_int), ("precision", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("tol_abs", ctypes.c_double), ("tol_rel", ctypes.c_double), ("cg_rtol", ctypes.c_double),
-                ("cg_maxit", ctypes.c_int), ("precond", ctypes.c_int),
+                ("cg_maxit", ctypes.c_int), ("precond", ctypes.c_int), ("cg_rtol_adapt", ctypes.c_double),
                 ("divergence_factor", ctypes.c_double)]
 
 
@@ -181,7 +181,7 @@ class Solver:
 
     def __init__(self, beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0), m=8, max_levels=30,
                  relax="FCF", coarse="cn", precision="fp64", max_iter=100, tol_abs=1e-9, tol_rel=0.0, cg_rtol=1e-9,
-                 cg_maxit=10000, precond="none", divergence_factor=0.0, stream=None):
+                 cg_maxit=10000, precond="none", cg_rtol_adapt=0.0, divergence_factor=0.0, stream=None):
         self._h = None
         self._t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
         p = _Problem(beta, gamma, Kx, Ky, domain[0], domain[1], domain[2], domain[3], int(Mx), int(My),
@@ -190,6 +190,7 @@ class Solver:
         o.m, o.max_levels, o.max_iter, o.cg_maxit = int(m), int(max_levels), int(max_iter), int(cg_maxit)
         o.relax, o.coarse, o.precision = RELAX[relax], COARSE[coarse], PRECISION[precision]
         o.precond = PRECOND[precond]
+        o.cg_rtol_adapt = float(cg_rtol_adapt)
         o.tol_abs, o.tol_rel = float(tol_abs), float(tol_rel)
         o.cg_rtol, o.divergence_factor = float(cg_rtol), float(divergence_factor)
         if stream is None:

@@ -242,9 +242,11 @@ def test_full_size_apply_and_step_sampled():
     assert rel(prop[0], ref) <= 1e-10
 
 
-@pytest.mark.parametrize("level,coarse", [(0, "cn"), (1, "opt"), (1, "be")])
-def test_preconditioned_propagate_matches_oracle(level, coarse):
-    """PCG with the fast-diagonalisation preconditioner converges to the same propagator as plain CG."""
+@pytest.mark.parametrize("level,coarse,pc", [(0, "cn", "fd"), (1, "opt", "fd"), (1, "be", "fd"), (0, "cn", "fd-bf16"),
+                                             (1, "opt", "fd-bf16")])
+def test_preconditioned_propagate_matches_oracle(level, coarse, pc):
+    """PCG with the fast-diagonalisation preconditioner (FP64 or BF16 products) converges to the same
+    propagator as plain CG."""
     mg = _mg()
     beta, gamma, Kx, Ky, Mx, My = 0.65, 0.9, 2.0, 0.5, 97, 70
     prob = fem.Problem(beta, gamma, Kx, Ky, Mx, My)
@@ -255,7 +257,7 @@ def test_preconditioned_propagate_matches_oracle(level, coarse):
     u = wl.random_slices(41, 3, prob.nx, prob.ny)
     g = wl.random_slices(42, 3, prob.nx, prob.ny)
     with mg.Solver(beta, gamma, Kx, Ky, Mx, My, t, m=4, max_levels=3, coarse=coarse, cg_rtol=1e-14,
-                   precond="fd") as s:
+                   precond=pc) as s:
         out = host(s.propagate(level, steps, dev(u), dev(g)))
     solver = propagator.CGSolver(op, 1e-14, 20000)
     for i, k in enumerate(steps):
@@ -266,8 +268,8 @@ def test_preconditioned_propagate_matches_oracle(level, coarse):
         assert rel(out[i], ref) <= 1e-10, (i, rel(out[i], ref))
 
 
-@pytest.mark.parametrize("iters", [1, 3])
-def test_preconditioned_mgrit_iterates_match_oracle(iters):
+@pytest.mark.parametrize("iters,pc", [(1, "fd"), (3, "fd"), (2, "fd-bf16")])
+def test_preconditioned_mgrit_iterates_match_oracle(iters, pc):
     mg = _mg()
     prob, t, F, psi0 = _random_problem(5, 40, beta=0.75, gamma=0.85, Mx=70, My=66, Kx=2.0, Ky=1.0)
     op = fem.Operator(prob)
@@ -275,8 +277,22 @@ def test_preconditioned_mgrit_iterates_match_oracle(iters):
     o = omgrit.MGRIT(op, t, 4, max_levels=3, coarse="opt", cg_rtol=1e-14)
     ref = o.iterate(F, psi0, iters, U0=U0)
     with mg.Solver(prob.beta, prob.gamma, 2.0, 1.0, prob.Mx, prob.My, t, m=4, max_levels=3, coarse="opt",
-                   cg_rtol=1e-14, precond="fd") as s:
+                   cg_rtol=1e-14, precond=pc) as s:
         U, st, _ = s.iterate(dev(F), dev(psi0), iters, U_init=dev(U0))
         U = host(U)
     assert rel(U, ref) <= 1e-10
     assert st.cg_iterations / st.phi_applications < 30
+
+
+def test_adaptive_cg_tolerance_reaches_sequential():
+    """Loose CG tolerances in early MGRIT iterations (tightening with the residual) keep the fixed point."""
+    mg = _mg()
+    prob, t, F, psi0 = _random_problem(6, 48, beta=0.75, gamma=0.85, Mx=66, My=70, Kx=2.0, Ky=1.0)
+    op = fem.Operator(prob)
+    ref = propagator.sequential(op, propagator.CGSolver(op, 1e-14), t, F, psi0)
+    with mg.Solver(prob.beta, prob.gamma, 2.0, 1.0, prob.Mx, prob.My, t, m=4, max_levels=3, coarse="opt",
+                   precond="fd", cg_rtol=1e-13, cg_rtol_adapt=1e-3, tol_abs=0.0, tol_rel=1e-12, max_iter=30) as s:
+        U, st, rc = s.solve(dev(F), dev(psi0))
+        U = host(U)
+    assert rc == 0
+    assert rel(U, ref) <= 1e-10
