@@ -1,7 +1,8 @@
 """Benchmark: FP64 multilevel MGRIT V-cycle on one MI355X.
 
 Workload: 255 x 255 interior nodes, beta = 0.75, gamma = 0.85, K_x = 2, K_y = 1,
-T = 1, 1024 uniform steps, coarsening m = 8 (levels 1024 -> 128 -> 16 -> 2),
+T = 1, 1024 uniform steps, coarsening m = 8 (levels 1024 -> 128 -> 16, the
+16-point level solved by sequential stepping),
 F ~ N(0,1) per node and step and psi_0 ~ U[0,1] from seed 2, all FP64 and
 resident on the GPU before timing.  One step = one full MGRIT solve to the
 stop test; the result is checked against FP64 sequential stepping on the GPU
@@ -60,6 +61,7 @@ def main():
     ap.add_argument("--tol-rel", type=float, default=1e-9)
     ap.add_argument("--cpu-steps", type=int, default=48)
     ap.add_argument("--precond", default="fd-bf16")
+    ap.add_argument("--max-levels", type=int, default=3)
     ap.add_argument("--cg-adapt", type=float, default=0.0,
                     help="CG rtol of MGRIT iteration k = clamp(cg_adapt x relative residual, cg_rtol, 1e-4)")
     ap.add_argument("--skip-reference", action="store_true",
@@ -98,7 +100,8 @@ def main():
         seq_err = float(torch.linalg.norm(Useq - Uref) / torch.linalg.norm(Uref))
         del Useq
 
-    s = mgrit.Solver(*common, m=W["m"], coarse=args.coarse, cg_rtol=args.cg_rtol, cg_maxit=100000,
+    s = mgrit.Solver(*common, m=W["m"], max_levels=args.max_levels, coarse=args.coarse, cg_rtol=args.cg_rtol,
+                     cg_maxit=100000,
                      tol_abs=0.0, tol_rel=args.tol_rel, max_iter=40, precond=args.precond,
                      cg_rtol_adapt=args.cg_adapt)
     U = torch.empty((Nt + 1) * nx * ny, dtype=torch.float64, device="cuda")

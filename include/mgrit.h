@@ -97,6 +97,9 @@ typedef struct {
     double cg_rtol_adapt;   /* > 0: inexact early iterations (mgrit_solve only): CG rtol  */
                             /* of iteration k = clamp(cg_rtol_adapt x ||r_k-1|| / ||r_0||, */
                             /* cg_rtol, 1e-4), ||r|| the level-0 residual norms; 0: off   */
+    int warm_start;         /* 1: a relaxation that recomputes a point whose current value  */
+                            /* is an iterate starts CG from that value; 0: always from the  */
+                            /* propagated state (the converged result is the same)          */
     double divergence_factor; /* EDIVERGED when a norm exceeds this x the first (0: off) */
 } mgrit_options;
 
@@ -113,7 +116,8 @@ typedef struct mgrit_handle mgrit_handle;
 
 /* Fill `opt` with defaults: m = 8, max_levels = 30, FCF, CN, FP64, max_iter = 100,
  * tol_abs = 1e-9, tol_rel = 0, cg_rtol = 1e-9 (the paper's tolerances, Section 3.2),
- * cg_maxit = 10000, precond = NONE, cg_rtol_adapt = 0, divergence_factor = 0. */
+ * cg_maxit = 10000, precond = NONE, cg_rtol_adapt = 0, warm_start = 1,
+ * divergence_factor = 0. */
 void mgrit_default_options(mgrit_options* opt);
 
 /* Validate the problem, evaluate the Toeplitz generating sequences of Section 2

@@ -265,7 +265,7 @@ __global__ __launch_bounds__(NT) void k_apply(Geom g, Seqs sq, const ApplyDesc* 
 }
 
 // mode 0: right-hand side b = M u + theta_rhs A u (+F), partial ||b||^2
-// mode 1: initial residual r = b - (M u + theta_lhs A u), partial ||r||^2
+// mode 1: initial residual r = b - (M x + theta_lhs A x), partial ||r||^2 (ubase = x base)
 // mode 2: q = M p + theta_lhs A p (active slices), partial p.q
 template <int TT, int MODE>
 __global__ __launch_bounds__(NT) void k_prop_apply(Geom g, Seqs sq, const PropDesc* __restrict__ desc, int S,
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(NT) void k_prop_apply(Geom g, Seqs sq, const PropDe
         const double* f = (fbase && d.f >= 0) ? fbase + d.f * g.stride : nullptr;
         apply_tile<TT>(g, sq, ubase + d.u * g.stride, wsout + so, f, d.theta_rhs, 1.0, 2, tile, lds, red, &dot);
     } else if (MODE == 1) {
-        apply_tile<TT>(g, sq, ubase + d.u * g.stride, wsout + so, wsin + so, d.theta_lhs, -1.0, 2, tile, lds, red,
+        apply_tile<TT>(g, sq, ubase + d.x * g.stride, wsout + so, wsin + so, d.theta_lhs, -1.0, 2, tile, lds, red,
                        &dot);
     } else {
         apply_tile<TT>(g, sq, wsin + so, wsout + so, nullptr, d.theta_lhs, 1.0, 1, tile, lds, red, &dot);
@@ -300,8 +300,23 @@ __device__ __forceinline__ void chunk_range(const Geom& g, int c, long long& lo,
     if (hi > g.stride) hi = g.stride;
 }
 
+__global__ __launch_bounds__(NT) void k_cg_init_x(Geom g, const PropDesc* __restrict__ desc, int S,
+                                                  const double* ubase, const double* x0base, int warm,
+                                                  double* xbase) {
+    int s, c;
+    decode_block(g.nchunk, S, s, c);
+    if (s < 0) return;
+    const PropDesc d = desc[s];
+    const double* src = (warm && d.x0 >= 0) ? x0base + d.x0 * g.stride : ubase + d.u * g.stride;
+    double* x = xbase + d.x * g.stride;
+    if (src == x) return;
+    long long lo, hi;
+    chunk_range(g, c, lo, hi);
+    for (long long e = lo + threadIdx.x; e < hi; e += NT) x[e] = src[e];
+}
+
 __global__ __launch_bounds__(NT) void k_cg_start(Geom g, const PropDesc* __restrict__ desc, int S,
-                                                 const double* ubase, double* xbase, const double* zws, double* pws,
+                                                 double* xbase, const double* zws, double* pws,
                                                  const double* partial_bb, int nbb, const double* partial_rr, int nrr,
                                                  double rtol2, double* bb, int* active, int* iters) {
     int s, c;
@@ -310,7 +325,6 @@ __global__ __launch_bounds__(NT) void k_cg_start(Geom g, const PropDesc* __restr
     const PropDesc d = desc[s];
     const double b2 = slice_sum(partial_bb, g.pmax, s, nbb);
     const double r2 = slice_sum(partial_rr, g.pmax, s, nrr);
-    const double* u = ubase + d.u * g.stride;
     double* x = xbase + d.x * g.stride;
     const double* z = zws + (long long)s * g.stride;
     double* p = pws + (long long)s * g.stride;
@@ -318,7 +332,7 @@ __global__ __launch_bounds__(NT) void k_cg_start(Geom g, const PropDesc* __restr
     chunk_range(g, c, lo, hi);
     const bool zero = !(b2 > 0.0);
     for (long long e = lo + threadIdx.x; e < hi; e += NT) {
-        x[e] = zero ? 0.0 : u[e];
+        if (zero) x[e] = 0.0;
         p[e] = z[e];
     }
     if (c == 0 && threadIdx.x == 0) {
@@ -728,10 +742,18 @@ int launch_rhs(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc, int 
     return (int)hipGetLastError();
 }
 
-int launch_init_residual(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc, int S, const double* ubase,
+int launch_cg_init_x(const Geom* g, const PropDesc* desc, int S, const double* ubase, const double* x0base,
+                     int warm, double* xbase, void* stream) {
+    if (S <= 0) return 0;
+    hipLaunchKernelGGL(k_cg_init_x, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, desc, S,
+                       ubase, x0base, warm, xbase);
+    return (int)hipGetLastError();
+}
+
+int launch_init_residual(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc, int S, const double* xbase,
                          const double* bws, double* rws, double* partial_rr, void* stream) {
     if (S <= 0) return 0;
-    prop_apply<1>(g, sq, tv, desc, S, ubase, nullptr, bws, rws, partial_rr, nullptr, (hipStream_t)stream);
+    prop_apply<1>(g, sq, tv, desc, S, xbase, nullptr, bws, rws, partial_rr, nullptr, (hipStream_t)stream);
     return (int)hipGetLastError();
 }
 
@@ -746,8 +768,9 @@ int launch_cg_start(const Geom* g, const PropDesc* desc, int S, const double* ub
                     const double* zws, double* pws, const double* partial_bb, int nbb, const double* partial_rr,
                     int nrr, double rtol2, double* bb, int* active, int* iters, void* stream) {
     if (S <= 0) return 0;
+    (void)ubase;
     hipLaunchKernelGGL(k_cg_start, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, desc, S,
-                       ubase, xbase, zws, pws, partial_bb, nbb, partial_rr, nrr, rtol2, bb, active, iters);
+                       xbase, zws, pws, partial_bb, nbb, partial_rr, nrr, rtol2, bb, active, iters);
     return (int)hipGetLastError();
 }
 

@@ -60,6 +60,7 @@ struct Pass {
     int S = 0;
     std::vector<PropDesc> h;
     PropDesc* d = nullptr;
+    mutable int last_iters = 0;   // CG iterations the slowest slice needed last time (launch schedule)
 };
 
 struct Batch {
@@ -167,14 +168,17 @@ int upload_pairs(mgrit_handle* h, IndexPair& ip, const std::vector<int>& y, cons
 }
 
 // Descriptor of one application of the level-l propagator from point k-1 to k,
-// reading slice `u`, writing slice `x`.  Returns one or two passes.
-void make_step(const mgrit_handle* h, int l, int k, int u, int x, int tmp_slot, Batch& b) {
+// reading slice `u`, writing slice `x`; x0 is the slice of the level's state
+// that holds the previous value of point k (-1: none).  One or two passes.
+void make_step(const mgrit_handle* h, int l, int k, int u, int x, int tmp_slot, Batch& b, int x0 = -1) {
     const double tau = h->lv[l].tau[k];
     PropDesc d;
     d.u = u;
     d.x = x;
     d.f = -1;
     d.g = -1;
+    d.x0 = x0;
+    d.pad_ = 0;
     if (l == 0) {
         d.f = k - 1;                   // load F_k
         d.theta_rhs = -0.5 * tau;
@@ -206,6 +210,7 @@ void make_step(const mgrit_handle* h, int l, int k, int u, int x, int tmp_slot, 
         PropDesc d1 = d, d2 = d;
         d1.x = tmp_slot;
         d1.g = -1;
+        d1.x0 = -1;
         d1.theta_rhs = -0.5 * s1;
         d1.theta_lhs = 0.5 * s1;
         d2.u = tmp_slot;
@@ -263,13 +268,13 @@ int build_levels(mgrit_handle* h) {
             for (int j = 1; j < m; ++j) {
                 Batch& b = L.frelax[j - 1];
                 int slot = 0;
-                for (int c = 0; c + j <= L.N; c += m) make_step(h, l, c + j, c + j - 1, c + j, slot++, b);
+                for (int c = 0; c + j <= L.N; c += m) make_step(h, l, c + j, c + j - 1, c + j, slot++, b, c + j);
                 smax = std::max(smax, (int)b.pass[0].h.size());
             }
             int slot = 0;
-            for (int k = 1; k <= Nc; ++k) make_step(h, l, k * m, k * m - 1, k * m, slot++, L.crelax);
+            for (int k = 1; k <= Nc; ++k) make_step(h, l, k * m, k * m - 1, k * m, slot++, L.crelax, k * m);
             slot = 0;
-            for (int k = 1; k <= Nc; ++k) make_step(h, l, k * m, k * m - 1, k, slot++, L.resid);
+            for (int k = 1; k <= Nc; ++k) make_step(h, l, k * m, k * m - 1, k, slot++, L.resid, k * m);
             smax = std::max(smax, Nc);
             std::vector<int> y, x;
             for (int k = 0; k <= Nc; ++k) {
@@ -515,7 +520,7 @@ int tile_variant(const mgrit_handle* h, int S) {
 
 // Batched CG solve of one pass (S <= Smax slices).
 int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase, const double* fbase,
-             const double* gbase) {
+             const double* gbase, const double* x0base = nullptr, int warm = 0) {
     const int S = ps.S;
     if (S == 0) return 0;
     if (S > h->Smax) return fail(MGRIT_EINVAL, "batch of %d slices exceeds workspace (%d)", S, h->Smax);
@@ -534,7 +539,8 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
         return launch_fdb_apply(g, &h->fdb, ps.d, S, h->r, h->z, h->tb1, h->tb2, prz_out, act, st);
     };
     HIPCHK(launch_rhs(g, &h->seqs, tv, ps.d, S, ubase, fbase, h->b, h->pbb, st));
-    HIPCHK(launch_init_residual(g, &h->seqs, tv, ps.d, S, ubase, h->b, h->r, h->prr[0], st));
+    HIPCHK(launch_cg_init_x(g, ps.d, S, ubase, x0base, (x0base && warm && h->opt.warm_start) ? 1 : 0, xbase, st));
+    HIPCHK(launch_init_residual(g, &h->seqs, tv, ps.d, S, xbase, h->b, h->r, h->prr[0], st));
     if (pc) HIPCHK(precondition(h->prz[0], nullptr));
     double* zws = pc ? h->z : h->r;
     double** prho = pc ? h->prz : h->prr;        // rho = r.z (r.r without preconditioner)
@@ -545,7 +551,10 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     int nrho = pc ? nrz : nt;                    // entries of the current rho partials
     const int nrho_next = pc ? nrz : nc;
     const int maxit = h->opt.cg_maxit;
-    int chunk = pc ? 4 : 8;
+    // Iterations are launched in chunks between host checks of the active
+    // flags: the first chunk covers what this pass needed last time, later
+    // chunks are short, so few launches find every slice converged.
+    int chunk = ps.last_iters > 0 ? std::max(1, ps.last_iters - 1) : (pc ? 8 : 16);
     while (true) {
         HIPCHK(hipMemcpyAsync(h->h_act, h->act[cur], S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
@@ -566,13 +575,18 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
             cur = nxt;
             nrho = nrho_next;
         }
-        chunk = std::min(chunk * 2, 32);
+        chunk = ps.last_iters > 0 ? 2 : std::min(chunk * 2, 32);
     }
     HIPCHK(launch_add_g(g, ps.d, S, xbase, gbase, st));
     HIPCHK(hipMemcpyAsync(h->h_iters, h->iters, S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     long long its = 0;
-    for (int s = 0; s < S; ++s) its += h->h_iters[s];
+    int most = 0;
+    for (int s = 0; s < S; ++s) {
+        its += h->h_iters[s];
+        most = std::max(most, h->h_iters[s]);
+    }
+    ps.last_iters = most;
     h->cg_count += its;
     if (h->prof_on) h->prof_slices += its;
     h->phi_count += S;
@@ -592,24 +606,27 @@ Bases bases(mgrit_handle* h, int l) {
 }
 
 // Run a batch on level l with output array `xout` (the level's U unless given).
-int run_batch(mgrit_handle* h, int l, const Batch& b, double* xout = nullptr) {
+// warm: the level's state holds meaningful previous values of the target
+// points, used as CG start vectors (descriptors with x0 >= 0).
+int run_batch(mgrit_handle* h, int l, const Batch& b, double* xout = nullptr, int warm = 0) {
     Bases B = bases(h, l);
     double* X = xout ? xout : B.U;
-    if (b.npass == 1) return run_pass(h, b.pass[0], B.U, X, B.F, B.G);
+    if (b.npass == 1) return run_pass(h, b.pass[0], B.U, X, B.F, B.G, B.U, warm);
     CHK(run_pass(h, b.pass[0], B.U, h->tmp, B.F, nullptr));
-    return run_pass(h, b.pass[1], h->tmp, X, B.F, B.G);
+    return run_pass(h, b.pass[1], h->tmp, X, B.F, B.G, B.U, warm);
 }
 
-int f_relax(mgrit_handle* h, int l) {
-    for (const Batch& b : h->lv[l].frelax) CHK(run_batch(h, l, b));
+int f_relax(mgrit_handle* h, int l, int warm) {
+    for (const Batch& b : h->lv[l].frelax) CHK(run_batch(h, l, b, nullptr, warm));
     return 0;
 }
 
-int relax(mgrit_handle* h, int l) {
-    CHK(f_relax(h, l));
+// warm: the level's state already holds an iterate (not the zero start).
+int relax(mgrit_handle* h, int l, int warm) {
+    CHK(f_relax(h, l, warm));
     if (h->opt.relax == MGRIT_RELAX_FCF) {
-        CHK(run_batch(h, l, h->lv[l].crelax));
-        CHK(f_relax(h, l));
+        CHK(run_batch(h, l, h->lv[l].crelax, nullptr, warm));
+        CHK(f_relax(h, l, 1));
     }
     return 0;
 }
@@ -618,7 +635,7 @@ int relax(mgrit_handle* h, int l) {
 int residual(mgrit_handle* h, int l, double* norm2) {
     Level& L = h->lv[l];
     Level& C = h->lv[l + 1];
-    CHK(run_batch(h, l, L.resid, C.G));
+    CHK(run_batch(h, l, L.resid, C.G, 1));
     const Geom* g = &h->geom;
     Bases B = bases(h, l);
     HIPCHK(launch_zero_slices(g, 1, C.all_idx, C.G, (void*)h->stream));       // G_0 = 0
@@ -646,14 +663,14 @@ int coarsest_solve(mgrit_handle* h, int l) {
 int cycle(mgrit_handle* h, int l) {
     Level& L = h->lv[l];
     if (l == (int)h->lv.size() - 1) return coarsest_solve(h, l);
-    CHK(relax(h, l));
+    CHK(relax(h, l, 0));
     CHK(residual(h, l, nullptr));
     Level& C = h->lv[l + 1];
     HIPCHK(launch_zero_slices(&h->geom, C.N + 1, C.all_idx, C.U, (void*)h->stream));
     CHK(cycle(h, l + 1));
     HIPCHK(launch_axpy_slices(&h->geom, L.correct.S, L.correct.yi, L.U, L.correct.xi, C.U, 1.0, nullptr,
                               (void*)h->stream));
-    return f_relax(h, l);
+    return f_relax(h, l, 1);
 }
 
 // One level-0 correction after the residual has been restricted.
@@ -777,6 +794,7 @@ void mgrit_default_options(mgrit_options* o) {
     o->cg_maxit = 10000;
     o->precond = MGRIT_PRECOND_NONE;
     o->cg_rtol_adapt = 0.0;
+    o->warm_start = 1;
     o->divergence_factor = 0.0;
 }
 
@@ -807,7 +825,7 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
     if (o.precond < MGRIT_PRECOND_NONE || o.precond > MGRIT_PRECOND_FD_BF16)
         return fail(MGRIT_EINVAL, "unknown preconditioner");
     if (o.max_iter < 1 || o.cg_maxit < 1 || !(o.cg_rtol > 0.0) || !(o.tol_abs >= 0.0) || !(o.tol_rel >= 0.0) ||
-        !(o.cg_rtol_adapt >= 0.0))
+        !(o.cg_rtol_adapt >= 0.0) || (o.warm_start != 0 && o.warm_start != 1))
         return fail(MGRIT_EINVAL, "bad iteration limits or tolerances");
     const long long nx = p.Mx - 1, ny = p.My - 1;
     if (nx * ny > (1LL << 30)) return fail(MGRIT_EINVAL, "grid too large");
@@ -874,7 +892,7 @@ int mgrit_solve(mgrit_handle* h, const double* F, const double* psi0, const doub
             const double rho = hist.empty() ? 1.0 : hist.back() / hist[0];
             h->cur_rtol = std::min(1e-4, std::max(h->opt.cg_rtol, h->opt.cg_rtol_adapt * rho));
         }
-        CHK(relax(h, 0));
+        CHK(relax(h, 0, it > 0 ? 1 : 0));
         double n2 = 0.0;
         CHK(residual(h, 0, &n2));
         const double norm = std::sqrt(hxy * n2);
@@ -892,7 +910,7 @@ int mgrit_solve(mgrit_handle* h, const double* F, const double* psi0, const doub
     }
     if (!conv) {
         h->cur_rtol = 0.0;
-        CHK(f_relax(h, 0));
+        CHK(f_relax(h, 0, 1));
     }
     h->cur_rtol = 0.0;
     CHK(end_solve(h, U, dU, mem));
@@ -911,11 +929,11 @@ int mgrit_iterate(mgrit_handle* h, const double* F, const double* psi0, const do
     CHK(begin_solve(h, sg, F, psi0, U_init, U, mem, &dU));
     std::vector<double> hist;
     for (int i = 0; i < iterations; ++i) {
-        CHK(relax(h, 0));
+        CHK(relax(h, 0, i > 0 ? 1 : 0));
         CHK(residual(h, 0, nullptr));
         CHK(coarse_correct0(h));
     }
-    CHK(f_relax(h, 0));
+    CHK(f_relax(h, 0, iterations > 0 ? 1 : 0));
     CHK(end_solve(h, U, dU, mem));
     fill_stats(h, st, iterations, 0, hist);
     return MGRIT_OK;

@@ -22,10 +22,13 @@ extern "C" {
 // One slice of a batched propagator call.  Indices refer to slices of the
 // base arrays passed beside the descriptor array (stride n_x * n_y doubles).
 typedef struct {
-    int u;            // input state slice (start vector of CG)
+    int u;            // input state slice
     int x;            // output slice (the CG iterate)
     int f;            // load slice added to the right-hand side, -1 = none
     int g;            // slice added after the solve, -1 = none
+    int x0;           // slice of the level's state holding the previous value of the
+                      // target point (CG start vector when warm starts are on), -1 = none
+    int pad_;
     double theta_rhs; // right-hand side M u + theta_rhs A u (+ F)
     double theta_lhs; // system matrix M + theta_lhs A
 } PropDesc;
@@ -105,13 +108,16 @@ int launch_apply(const Geom* g, const Seqs* sq, int tv, const ApplyDesc* desc, i
 // Right-hand side of a batched propagator: b[s] = M u + theta_rhs A u (+ F), partial of ||b||^2.
 int launch_rhs(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc, int S, const double* ubase,
                const double* fbase, double* bws, double* partial_bb, void* stream);
-// r[s] = b[s] - (M u + theta_lhs A u), partial of ||r||^2.
-int launch_init_residual(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc, int S, const double* ubase,
+// CG start vector: x = x0base[x0] when warm and x0 >= 0, else x = u.
+int launch_cg_init_x(const Geom* g, const PropDesc* desc, int S, const double* ubase, const double* x0base,
+                     int warm, double* xbase, void* stream);
+// r[s] = b[s] - (M x + theta_lhs A x), partial of ||r||^2.
+int launch_init_residual(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc, int S, const double* xbase,
                          const double* bws, double* rws, double* partial_rr, void* stream);
 // q = B p for active slices, partial p.q.
 int launch_cg_apply(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc, int S, const double* pws,
                     double* qws, double* partial_pq, const int* active, void* stream);
-// x = u (or 0 when ||b|| = 0), p = z; active flags from ||r|| vs rtol ||b||.
+// x = 0 when ||b|| = 0, p = z; active flags from ||r|| vs rtol ||b||.
 int launch_cg_start(const Geom* g, const PropDesc* desc, int S, const double* ubase, double* xbase,
                     const double* zws, double* pws, const double* partial_bb, int nbb, const double* partial_rr,
                     int nrr, double rtol2, double* bb, int* active, int* iters, void* stream);

@@ -33,6 +33,7 @@ class _Options(ctypes.Structure):
                 ("coarse", ctypes.c_int), ("precision", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("tol_abs", ctypes.c_double), ("tol_rel", ctypes.c_double), ("cg_rtol", ctypes.c_double),
                 ("cg_maxit", ctypes.c_int), ("precond", ctypes.c_int), ("cg_rtol_adapt", ctypes.c_double),
+                ("warm_start", ctypes.c_int),
                 ("divergence_factor", ctypes.c_double)]
 
 
@@ -181,7 +182,8 @@ class Solver:
 
     def __init__(self, beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0), m=8, max_levels=30,
                  relax="FCF", coarse="cn", precision="fp64", max_iter=100, tol_abs=1e-9, tol_rel=0.0, cg_rtol=1e-9,
-                 cg_maxit=10000, precond="none", cg_rtol_adapt=0.0, divergence_factor=0.0, stream=None):
+                 cg_maxit=10000, precond="none", cg_rtol_adapt=0.0, warm_start=True, divergence_factor=0.0,
+                 stream=None):
         self._h = None
         self._t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
         p = _Problem(beta, gamma, Kx, Ky, domain[0], domain[1], domain[2], domain[3], int(Mx), int(My),
@@ -191,6 +193,7 @@ class Solver:
         o.relax, o.coarse, o.precision = RELAX[relax], COARSE[coarse], PRECISION[precision]
         o.precond = PRECOND[precond]
         o.cg_rtol_adapt = float(cg_rtol_adapt)
+        o.warm_start = 1 if warm_start else 0
         o.tol_abs, o.tol_rel = float(tol_abs), float(tol_rel)
         o.cg_rtol, o.divergence_factor = float(cg_rtol), float(divergence_factor)
         if stream is None:
