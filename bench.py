@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "space-time DOF/s at 1e-8 rel. error vs FP64 sequential"
 FP64_PEAK_TFLOPS = 78.6          # MI355X dense FP64 (matrix and vector)
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_prop_apply2_fp64_vcycle_255_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_prop_apply64_fp64_vcycle_255_traffic.json")
 
 
 def cpu_baseline(W, t, F, psi0, steps, cg_rtol):
@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--max-levels", type=int, default=3)
     ap.add_argument("--cg-adapt", type=float, default=0.0,
                     help="CG rtol of MGRIT iteration k = clamp(cg_adapt x relative residual, cg_rtol, 1e-4)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 512 MiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--skip-reference", action="store_true",
                     help="time MGRIT only (no sequential reference, no accuracy check): for profiler runs")
     args = ap.parse_args()
@@ -73,6 +75,10 @@ def main():
 
     import numpy as np
     import torch
+    if args.calibrate_copy:
+        from paper_1805_06688_amd import profiling
+        profiling.copy(512)
+        return
     from paper_1805_06688_amd import mgrit, workloads as wl
 
     W = wl.FP64_VCYCLE_255
@@ -114,7 +120,7 @@ def main():
         _, st, rc = s.solve(Fd, pd, out=U)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    apply_ms, launches, slice_applies = s.profile_read()
+    prof = [s.profile_read(v) for v in (0, 1)]
     s.profile(False)
     levels = s.levels()
     err = None if Uref is None else float(torch.linalg.norm(U.view(Nt + 1, ny, nx) - Uref) / torch.linalg.norm(Uref))
@@ -123,17 +129,28 @@ def main():
     dof = nx * ny * Nt
     per_step = elapsed / args.steps
     flops_per_apply = 6.0 * nx * nx * ny + 6.0 * nx * ny * ny
-    achieved = flops_per_apply * slice_applies / (apply_ms * 1e-3) / 1e12 if apply_ms > 0 else None
+
+    def achieved(v):
+        ms, n, sl = prof[v]
+        return flops_per_apply * sl / (ms * 1e-3) / 1e12 if ms > 0 else None
+
+    from paper_1805_06688_amd import profiling
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
-            traffic = json.load(fh).get("bytes_per_launch")
-    roofline = {"bound": "mfma", "kernel": "k_prop_apply<2> (CG operator, FP64 MFMA)",
-                "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS if achieved else None, "traffic": traffic,
-                "avg_launch_ms": apply_ms / launches if launches else None,
-                "launches": launches, "slice_applies_per_launch": slice_applies / launches if launches else None,
-                "flops_per_slice_apply": flops_per_apply}
+            tr = json.load(fh)
+        if tr.get("source_hash") == profiling.source_hash():
+            traffic = tr.get("bytes_per_launch")
+    ms0, n0, sl0 = prof[0]
+    a0 = achieved(0)
+    roofline = {"bound": "mfma", "kernel": "k_prop_apply<64,2> (CG operator, FP64 MFMA, 64-point tiles)",
+                "achieved": a0, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": a0 / FP64_PEAK_TFLOPS if a0 else None, "traffic": traffic,
+                "avg_launch_ms": ms0 / n0 if n0 else None, "launches": n0,
+                "slice_applies_per_launch": sl0 / n0 if n0 else None, "flops_per_slice_apply": flops_per_apply,
+                "small_tile_kernel": {"kernel": "k_prop_apply<32,2>", "achieved_tflops": achieved(1),
+                                      "launches": prof[1][1],
+                                      "avg_launch_ms": prof[1][0] / prof[1][1] if prof[1][1] else None}}
     out = {"metric": METRIC, "value": dof / per_step, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": per_step * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",

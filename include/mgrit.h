@@ -204,11 +204,13 @@ int mgrit_fd_eigen(double rho, int n, double h, double K, double* V, double* lam
 
 /* Instrumentation.  While enabled, a pair of HIP events on the handle's stream
  * brackets every launch of the CG operator kernel (q = (M_h + theta A_h) p, the
- * dominant kernel); enabling resets the counters.  mgrit_profile_read returns
- * the summed kernel time in ms, the number of launches and the number of
- * slice applications they performed (the sum of CG iterations over slices). */
+ * dominant kernel); enabling resets the counters.  mgrit_profile_read returns,
+ * for the 64-point (variant 0) or 32-point (variant 1) tile version of that
+ * kernel, the summed kernel time in ms, the number of launches and the number
+ * of slice applications they performed (the sum of CG iterations over slices). */
 int mgrit_profile_enable(mgrit_handle* h, int on);
-int mgrit_profile_read(const mgrit_handle* h, double* apply_ms, long long* launches, long long* slice_applies);
+int mgrit_profile_read(const mgrit_handle* h, int variant, double* apply_ms, long long* launches,
+                       long long* slice_applies);
 
 /* Number of time points per level; writes up to `cap` values, returns the level count. */
 int mgrit_levels(const mgrit_handle* h, int* n_per_level, int cap);

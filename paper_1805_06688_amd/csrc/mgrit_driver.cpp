@@ -126,9 +126,10 @@ struct mgrit_handle {
     // instrumentation of the CG operator kernel
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;
+    std::vector<int> prof_tv;                 // tile variant of each recorded event pair
     size_t prof_used = 0;
-    double prof_ms = 0.0;
-    long long prof_launches = 0, prof_slices = 0;
+    double prof_ms[2] = {0.0, 0.0};
+    long long prof_launches[2] = {0, 0}, prof_slices[2] = {0, 0};
     // caller arrays of the current solve (level 0)
     double* U0 = nullptr;
     const double* F0 = nullptr;
@@ -489,12 +490,14 @@ int alloc_workspace(mgrit_handle* h, int S) {
     return 0;
 }
 
-int prof_record(mgrit_handle* h) {
+int prof_record(mgrit_handle* h, int tv) {
     if (h->prof_used == h->prof_ev.size()) {
         hipEvent_t e;
         HIPCHK(hipEventCreate(&e));
         h->prof_ev.push_back(e);
+        h->prof_tv.push_back(0);
     }
+    h->prof_tv[h->prof_used] = tv;
     HIPCHK(hipEventRecord(h->prof_ev[h->prof_used++], h->stream));
     return 0;
 }
@@ -504,8 +507,8 @@ int prof_drain(mgrit_handle* h) {
     for (size_t i = 0; i + 1 < h->prof_used; i += 2) {
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, h->prof_ev[i], h->prof_ev[i + 1]));
-        h->prof_ms += ms;
-        h->prof_launches += 1;
+        h->prof_ms[h->prof_tv[i]] += ms;
+        h->prof_launches[h->prof_tv[i]] += 1;
     }
     h->prof_used = 0;
     return 0;
@@ -564,9 +567,9 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
         if (!any || it >= maxit) break;
         for (int c = 0; c < chunk && it < maxit; ++c, ++it) {
             const int nxt = cur ^ 1;
-            if (h->prof_on) CHK(prof_record(h));
+            if (h->prof_on) CHK(prof_record(h, tv));
             HIPCHK(launch_cg_apply(g, &h->seqs, tv, ps.d, S, h->p, h->q, h->ppq, h->act[cur], st));
-            if (h->prof_on) CHK(prof_record(h));
+            if (h->prof_on) CHK(prof_record(h, tv));
             HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, prho[cur], nrho, h->ppq, nt, h->prr[nxt],
                                     h->act[cur], st));
             if (pc) HIPCHK(precondition(h->prz[nxt], h->act[cur]));
@@ -588,7 +591,7 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     }
     ps.last_iters = most;
     h->cg_count += its;
-    if (h->prof_on) h->prof_slices += its;
+    if (h->prof_on) h->prof_slices[tv] += its;
     h->phi_count += S;
     return 0;
 }
@@ -1058,17 +1061,21 @@ int mgrit_profile_enable(mgrit_handle* h, int on) {
     HIPCHK(hipStreamSynchronize(h->stream));
     h->prof_on = on != 0;
     h->prof_used = 0;
-    h->prof_ms = 0.0;
-    h->prof_launches = 0;
-    h->prof_slices = 0;
+    for (int v = 0; v < 2; ++v) {
+        h->prof_ms[v] = 0.0;
+        h->prof_launches[v] = 0;
+        h->prof_slices[v] = 0;
+    }
     return MGRIT_OK;
 }
 
-int mgrit_profile_read(const mgrit_handle* h, double* apply_ms, long long* launches, long long* slice_applies) {
+int mgrit_profile_read(const mgrit_handle* h, int variant, double* apply_ms, long long* launches,
+                       long long* slice_applies) {
     if (!h) return fail(MGRIT_EINVAL, "NULL handle");
-    if (apply_ms) *apply_ms = h->prof_ms;
-    if (launches) *launches = h->prof_launches;
-    if (slice_applies) *slice_applies = h->prof_slices;
+    if (variant < 0 || variant > 1) return fail(MGRIT_EINVAL, "variant must be 0 or 1");
+    if (apply_ms) *apply_ms = h->prof_ms[variant];
+    if (launches) *launches = h->prof_launches[variant];
+    if (slice_applies) *slice_applies = h->prof_slices[variant];
     return MGRIT_OK;
 }
 

@@ -86,7 +86,7 @@ def load_library(path=_LIB_PATH):
     lib.mgrit_stiffness_scale.restype = c_dbl
     lib.mgrit_profile_enable.argtypes = [P, c_int]
     lib.mgrit_profile_enable.restype = c_int
-    lib.mgrit_profile_read.argtypes = [P, ctypes.POINTER(c_dbl), ctypes.POINTER(ctypes.c_longlong),
+    lib.mgrit_profile_read.argtypes = [P, c_int, ctypes.POINTER(c_dbl), ctypes.POINTER(ctypes.c_longlong),
                                        ctypes.POINTER(ctypes.c_longlong)]
     lib.mgrit_profile_read.restype = c_int
     lib.mgrit_fd_stiffness_entry.argtypes = [c_dbl, c_dbl, c_dbl, c_int]
@@ -298,9 +298,10 @@ class Solver:
     def profile(self, on=True):
         _check(_lib.mgrit_profile_enable(self._h, 1 if on else 0))
 
-    def profile_read(self):
+    def profile_read(self, variant=0):
+        """(kernel ms, launches, slice applications) of the 64-tile (0) or 32-tile (1) operator kernel."""
         ms, n, sl = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_longlong()
-        _check(_lib.mgrit_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(sl)))
+        _check(_lib.mgrit_profile_read(self._h, int(variant), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(sl)))
         return ms.value, n.value, sl.value
 
     def levels(self):

@@ -1,0 +1,86 @@
+"""Helpers for profiling the solver with rocprofv3.
+
+    python -m paper_1805_06688_amd.profiling copy [MiB]
+        a plain device-to-device copy of a known size (HBM-counter calibration)
+    python -m paper_1805_06688_amd.profiling stats KERNEL_STATS_CSV
+        markdown table of a rocprofv3 --stats kernel summary
+    python -m paper_1805_06688_amd.profiling counters COUNTER_CSV REGEX
+        mean value per dispatch of every counter for kernels matching REGEX
+    python -m paper_1805_06688_amd.profiling source-hash
+        hash of the HIP kernel sources (counters are tied to one version)
+"""
+import csv
+import hashlib
+import os
+import re
+import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(CSRC, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def copy(mib=512, reps=8):
+    import torch
+    n = mib * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copied {mib} MiB x {reps}: {mib * 1024} KiB read and {mib * 1024} KiB written per dispatch")
+
+
+def short_name(name):
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return name.split("(")[0]
+
+
+def stats(path):
+    rows = list(csv.DictReader(open(path)))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    print("| kernel | calls | total ms | avg us | % |")
+    print("|---|---:|---:|---:|---:|")
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        t = float(r["TotalDurationNs"])
+        if t < 1e-3 * total:
+            continue
+        print(f"| `{short_name(r['Name'])}` | {r['Calls']} | {t / 1e6:.1f} | {float(r['AverageNs']) / 1e3:.1f} "
+              f"| {100 * t / total:.1f} |")
+
+
+def counters(path, regex):
+    pat = re.compile(regex)
+    acc = {}
+    for r in csv.DictReader(open(path)):
+        if not pat.search(r.get("Kernel_Name", "")):
+            continue
+        key = (short_name(r["Kernel_Name"]), r.get("Grid_Size", "?"), r["Counter_Name"])
+        v = acc.setdefault(key, [0, 0.0])
+        v[0] += 1
+        v[1] += float(r["Counter_Value"])
+    for (k, g, c), (n, tot) in sorted(acc.items()):
+        print(f"{k} grid={g} {c}: dispatches={n} mean={tot / n:.1f}")
+
+
+if __name__ == "__main__":
+    cmd = sys.argv[1] if len(sys.argv) > 1 else ""
+    if cmd == "copy":
+        copy(int(sys.argv[2]) if len(sys.argv) > 2 else 512)
+    elif cmd == "stats":
+        stats(sys.argv[2])
+    elif cmd == "counters":
+        counters(sys.argv[2], sys.argv[3])
+    elif cmd == "source-hash":
+        print(source_hash())
+    else:
+        print(__doc__)
+        sys.exit(2)
