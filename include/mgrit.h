@@ -212,11 +212,54 @@ int mgrit_profile_enable(mgrit_handle* h, int on);
 int mgrit_profile_read(const mgrit_handle* h, int variant, double* apply_ms, long long* launches,
                        long long* slice_applies);
 
+/* Device memory a handle for (prob, opt) allocates, plus staging of the
+ * caller's arrays when mem = MGRIT_MEM_HOST (an upper estimate).  Only
+ * the sizes of prob and opt are read. */
+int mgrit_footprint(const mgrit_problem* prob, const mgrit_options* opt, int mem, size_t* bytes);
+/* Device memory the handle owns now. */
+int mgrit_device_bytes(const mgrit_handle* h, size_t* bytes);
+
 /* Number of time points per level; writes up to `cap` values, returns the level count. */
 int mgrit_levels(const mgrit_handle* h, int* n_per_level, int cap);
 
 void mgrit_destroy(mgrit_handle* h);
 const char* mgrit_last_error(void);
+
+/* ---- Serving: many solves in flight on one GPU ----
+ * A server admits submitted solves in arrival order while their footprint
+ * (mgrit_footprint) fits the device budget and fewer than max_concurrent
+ * run; each admitted solve gets its own handle and HIP stream (default
+ * priority) on a worker thread, so the kernels of different solves overlap
+ * on the device; memory is released as each solve finishes and the next
+ * queued solves are admitted.  Every solve is computed exactly as alone
+ * (all reductions are per slice in a fixed order), so its result does not
+ * depend on the mix.  Inputs and U must stay valid until the solve is done;
+ * with MGRIT_MEM_DEVICE they stay on the device throughout. */
+typedef struct mgrit_server mgrit_server;
+
+typedef struct {
+    int rc;               /* return code of mgrit_solve (or of its setup)            */
+    mgrit_stats stats;
+    double submit_s;      /* seconds since server creation                           */
+    double start_s;       /* admitted                                                */
+    double finish_s;      /* result written                                          */
+    size_t bytes;         /* footprint charged against the budget                    */
+} mgrit_request_info;
+
+/* device_budget_bytes: memory the server may commit to solves at once;
+ * max_concurrent >= 1.  Errors: EINVAL. */
+int mgrit_server_create(size_t device_budget_bytes, int max_concurrent, mgrit_server** out);
+/* Queue one solve (arguments as in mgrit_setup and mgrit_solve; the problem's
+ * time grid is copied).  Returns EINVAL at once for invalid arguments or a
+ * footprint above the whole budget.  *id identifies the request. */
+int mgrit_server_submit(mgrit_server* s, const mgrit_problem* prob, const mgrit_options* opt, const double* F,
+                        const double* psi0, double* U, int mem, long long* id);
+/* Block until request `id` has finished; fill *info (may be NULL). */
+int mgrit_server_wait(mgrit_server* s, long long id, mgrit_request_info* info);
+/* *done = 1 when request `id` has finished. */
+int mgrit_server_poll(mgrit_server* s, long long id, int* done);
+/* Wait for every request, stop the workers, free everything. */
+void mgrit_server_destroy(mgrit_server* s);
 
 #ifdef __cplusplus
 }

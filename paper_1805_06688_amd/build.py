@@ -38,11 +38,12 @@ def build(verbose=True):
     o = os.path.join(OUT_DIR, "kernels.o")
     _run([HIPCC] + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "kernels.hip"), "-o", o])
     objs.append(o)
-    o = os.path.join(OUT_DIR, "mgrit_driver.o")
-    _run([HIPCC] + DEVICE_FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, "mgrit_driver.cpp"), "-o", o])
-    objs.append(o)
+    for src in ("mgrit_driver.cpp", "server.cpp"):
+        o = os.path.join(OUT_DIR, src.replace(".cpp", ".o"))
+        _run([HIPCC] + DEVICE_FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", o])
+        objs.append(o)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lquadmath"])
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lquadmath", "-lpthread"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -120,6 +120,7 @@ struct mgrit_handle {
     double* h_norm = nullptr;                // pinned
     long long phi_count = 0, cg_count = 0;
     std::vector<void*> allocations;
+    size_t dev_bytes = 0;           // device memory owned by the handle
     double cur_rtol = 0.0;          // CG tolerance of the current MGRIT iteration
     int force_tile = -1;            // tuning override (MGRIT_FORCE_TILE=0|1)
     long long tile_threshold = 512; // 64-tiles when S * tiles64 >= this (MGRIT_TILE_THRESHOLD)
@@ -142,6 +143,7 @@ int dmalloc(mgrit_handle* h, void** p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) return fail(MGRIT_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     h->allocations.push_back(*p);
+    h->dev_bytes += bytes;
     return 0;
 }
 
@@ -1076,6 +1078,44 @@ int mgrit_profile_read(const mgrit_handle* h, int variant, double* apply_ms, lon
     if (apply_ms) *apply_ms = h->prof_ms[variant];
     if (launches) *launches = h->prof_launches[variant];
     if (slice_applies) *slice_applies = h->prof_slices[variant];
+    return MGRIT_OK;
+}
+
+int mgrit_device_bytes(const mgrit_handle* h, size_t* bytes) {
+    if (!h || !bytes) return fail(MGRIT_EINVAL, "NULL argument");
+    *bytes = h->dev_bytes;
+    return MGRIT_OK;
+}
+
+int mgrit_footprint(const mgrit_problem* p, const mgrit_options* o, int mem, size_t* bytes) {
+    if (!p || !o || !bytes) return fail(MGRIT_EINVAL, "NULL argument");
+    if (p->Mx < 2 || p->My < 2 || p->Nt < 1 || o->m < 2 || o->max_levels < 2)
+        return fail(MGRIT_EINVAL, "bad sizes");
+    const double nx = p->Mx - 1, ny = p->My - 1, st = nx * ny;
+    const double tx0 = std::ceil(nx / 64), ty0 = std::ceil(ny / 64);
+    const double npx = tx0 * 64, npy = ty0 * 64;
+    const double nt1 = std::ceil(nx / 32) * std::ceil(ny / 32), nch = std::ceil(st / MGRIT_CHUNK);
+    const double pmax = std::max(nt1, nch);
+    std::vector<int> N(1, p->Nt);
+    while ((int)N.size() < o->max_levels && N.back() / o->m >= 2) N.push_back(N.back() / o->m);
+    double smax = 1, d = 0;                                  // d: doubles
+    double desc = 0;                                         // descriptor and index bytes
+    const bool two = o->coarse == MGRIT_COARSE_CN2 || o->coarse == MGRIT_COARSE_OPT;
+    for (size_t l = 0; l < N.size(); ++l) {
+        if (l > 0) d += 2.0 * (N[l] + 1) * st;
+        desc += 4.0 * (N[l] + 1) + 48.0 * (two ? 2 : 1) * (3.0 * N[l] + 4);
+        if (l + 1 < N.size()) smax = std::max(smax, std::max((double)((N[l] - 1) / o->m + 1), (double)N[l + 1]));
+    }
+    const bool pc = o->precond != MGRIT_PRECOND_NONE;
+    d += 2 * (2 * (npx + 96) + 1) + 2 * (2 * (npy + 96) + 1);                       // sequences
+    d += smax * st * (4 + (two ? 1 : 0) + (pc ? 1 : 0) + (o->precond == MGRIT_PRECOND_FD ? 2 : 0));
+    d += smax * pmax * (5 + (pc ? 2 : 0)) + smax * 3;
+    double b = 0;
+    if (pc) d += 2 * nx * nx + 2 * ny * ny + nx + ny;
+    if (o->precond == MGRIT_PRECOND_FD_BF16) b += 4 * npx * npx + 4 * npy * npy + 4 * (npx + npy) + 4 * smax * npx * npy;
+    if (mem == MGRIT_MEM_HOST) d += (2.0 * p->Nt + 2) * st;
+    const double total = 8 * d + b + desc + smax * 12;
+    *bytes = (size_t)(total * 1.02) + (size_t)64 * 4096;
     return MGRIT_OK;
 }
 

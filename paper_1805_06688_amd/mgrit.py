@@ -47,10 +47,17 @@ class Stats(ctypes.Structure):
         return [self.residual_history[i] for i in range(n)]
 
 
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("rc", ctypes.c_int), ("stats", Stats), ("submit_s", ctypes.c_double),
+                ("start_s", ctypes.c_double), ("finish_s", ctypes.c_double), ("bytes", ctypes.c_size_t)]
+
+
 SYMBOLS = ("mgrit_default_options", "mgrit_setup", "mgrit_solve", "mgrit_iterate", "mgrit_sequential",
            "mgrit_propagate", "mgrit_apply", "mgrit_sequences", "mgrit_levels", "mgrit_destroy",
            "mgrit_last_error", "mgrit_toeplitz_sequences", "mgrit_stiffness_scale", "mgrit_profile_enable",
-           "mgrit_profile_read", "mgrit_fd_stiffness_entry", "mgrit_fd_eigen")
+           "mgrit_profile_read", "mgrit_fd_stiffness_entry", "mgrit_fd_eigen", "mgrit_footprint",
+           "mgrit_device_bytes", "mgrit_server_create", "mgrit_server_submit", "mgrit_server_wait",
+           "mgrit_server_poll", "mgrit_server_destroy")
 
 
 def load_library(path=_LIB_PATH):
@@ -93,6 +100,22 @@ def load_library(path=_LIB_PATH):
     lib.mgrit_fd_stiffness_entry.restype = c_dbl
     lib.mgrit_fd_eigen.argtypes = [c_dbl, c_int, c_dbl, c_dbl, ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl)]
     lib.mgrit_fd_eigen.restype = c_int
+    lib.mgrit_footprint.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Options), c_int,
+                                    ctypes.POINTER(ctypes.c_size_t)]
+    lib.mgrit_footprint.restype = c_int
+    lib.mgrit_device_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.mgrit_device_bytes.restype = c_int
+    lib.mgrit_server_create.argtypes = [ctypes.c_size_t, c_int, ctypes.POINTER(P)]
+    lib.mgrit_server_create.restype = c_int
+    lib.mgrit_server_submit.argtypes = [P, ctypes.POINTER(_Problem), ctypes.POINTER(_Options), P, P, P, c_int,
+                                        ctypes.POINTER(ctypes.c_longlong)]
+    lib.mgrit_server_submit.restype = c_int
+    lib.mgrit_server_wait.argtypes = [P, ctypes.c_longlong, ctypes.POINTER(RequestInfo)]
+    lib.mgrit_server_wait.restype = c_int
+    lib.mgrit_server_poll.argtypes = [P, ctypes.c_longlong, ctypes.POINTER(c_int)]
+    lib.mgrit_server_poll.restype = c_int
+    lib.mgrit_server_destroy.argtypes = [P]
+    lib.mgrit_server_destroy.restype = None
     lib.mgrit_last_error.argtypes = []
     lib.mgrit_last_error.restype = ctypes.c_char_p
     return lib
@@ -177,25 +200,43 @@ def default_options():
     return o
 
 
+def make_problem(beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0)):
+    """(ctypes problem struct, the time grid array it points to)."""
+    t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
+    p = _Problem(beta, gamma, Kx, Ky, domain[0], domain[1], domain[2], domain[3], int(Mx), int(My), len(t) - 1,
+                 t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return p, t
+
+
+def make_options(m=8, max_levels=30, relax="FCF", coarse="cn", precision="fp64", max_iter=100, tol_abs=1e-9,
+                 tol_rel=0.0, cg_rtol=1e-9, cg_maxit=10000, precond="none", cg_rtol_adapt=0.0, warm_start=True,
+                 divergence_factor=0.0):
+    o = default_options()
+    o.m, o.max_levels, o.max_iter, o.cg_maxit = int(m), int(max_levels), int(max_iter), int(cg_maxit)
+    o.relax, o.coarse, o.precision = RELAX[relax], COARSE[coarse], PRECISION[precision]
+    o.precond = PRECOND[precond]
+    o.cg_rtol_adapt = float(cg_rtol_adapt)
+    o.warm_start = 1 if warm_start else 0
+    o.tol_abs, o.tol_rel = float(tol_abs), float(tol_rel)
+    o.cg_rtol, o.divergence_factor = float(cg_rtol), float(divergence_factor)
+    return o
+
+
+def footprint(beta, gamma, Kx, Ky, Mx, My, t, mem=MEM_DEVICE, **opts):
+    p, _t = make_problem(beta, gamma, Kx, Ky, Mx, My, t)
+    o = make_options(**opts)
+    b = ctypes.c_size_t()
+    _check(_lib.mgrit_footprint(ctypes.byref(p), ctypes.byref(o), int(mem), ctypes.byref(b)))
+    return b.value
+
+
 class Solver:
     """One problem (eqs. 1.1-1.3 on a time grid) set up on the GPU."""
 
-    def __init__(self, beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0), m=8, max_levels=30,
-                 relax="FCF", coarse="cn", precision="fp64", max_iter=100, tol_abs=1e-9, tol_rel=0.0, cg_rtol=1e-9,
-                 cg_maxit=10000, precond="none", cg_rtol_adapt=0.0, warm_start=True, divergence_factor=0.0,
-                 stream=None):
+    def __init__(self, beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0), stream=None, **opts):
         self._h = None
-        self._t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
-        p = _Problem(beta, gamma, Kx, Ky, domain[0], domain[1], domain[2], domain[3], int(Mx), int(My),
-                     len(self._t) - 1, self._t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
-        o = default_options()
-        o.m, o.max_levels, o.max_iter, o.cg_maxit = int(m), int(max_levels), int(max_iter), int(cg_maxit)
-        o.relax, o.coarse, o.precision = RELAX[relax], COARSE[coarse], PRECISION[precision]
-        o.precond = PRECOND[precond]
-        o.cg_rtol_adapt = float(cg_rtol_adapt)
-        o.warm_start = 1 if warm_start else 0
-        o.tol_abs, o.tol_rel = float(tol_abs), float(tol_rel)
-        o.cg_rtol, o.divergence_factor = float(cg_rtol), float(divergence_factor)
+        p, self._t = make_problem(beta, gamma, Kx, Ky, Mx, My, t, domain)
+        o = make_options(**opts)
         if stream is None:
             stream = self._torch_stream()
         h = ctypes.c_void_p()
@@ -304,7 +345,72 @@ class Solver:
         _check(_lib.mgrit_profile_read(self._h, int(variant), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(sl)))
         return ms.value, n.value, sl.value
 
+    def device_bytes(self):
+        b = ctypes.c_size_t()
+        _check(_lib.mgrit_device_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
     def levels(self):
         buf = (ctypes.c_int * 64)()
         L = _lib.mgrit_levels(self._h, buf, 64)
         return [buf[i] - 1 for i in range(L)]
+
+
+class Request:
+    """A submitted solve; keeps its arrays alive until it has finished."""
+
+    def __init__(self, server, rid, arrays, U, shape):
+        self._server, self.id, self._arrays, self.U, self._shape = server, rid, arrays, U, shape
+
+    def done(self):
+        d = ctypes.c_int()
+        _check(_lib.mgrit_server_poll(self._server._s, self.id, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self):
+        info = RequestInfo()
+        _check(_lib.mgrit_server_wait(self._server._s, self.id, ctypes.byref(info)))
+        self._arrays = None
+        return self.U.reshape(self._shape), info
+
+
+class Server:
+    """Admission by device-memory footprint, concurrent solves on separate streams (C ABI mgrit_server_*)."""
+
+    def __init__(self, device_budget_bytes, max_concurrent=4):
+        self._s = None
+        s = ctypes.c_void_p()
+        _check(_lib.mgrit_server_create(ctypes.c_size_t(int(device_budget_bytes)), int(max_concurrent),
+                                        ctypes.byref(s)))
+        self._s = s
+
+    def submit(self, F, psi0, beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0), out=None, **opts):
+        p, tt = make_problem(beta, gamma, Kx, Ky, Mx, My, t, domain)
+        o = make_options(**opts)
+        mem = _mem_of(psi0)
+        n = (int(Mx) - 1) * (int(My) - 1)
+        Nt = len(tt) - 1
+        if out is None:
+            if _is_torch(psi0):
+                import torch
+                out = torch.empty((Nt + 1) * n, dtype=torch.float64, device=psi0.device)
+            else:
+                out = np.empty((Nt + 1) * n)
+        rid = ctypes.c_longlong()
+        _check(_lib.mgrit_server_submit(self._s, ctypes.byref(p), ctypes.byref(o), _ptr(F, mem, Nt * n),
+                                        _ptr(psi0, mem, n), _ptr(out, mem, (Nt + 1) * n), mem, ctypes.byref(rid)))
+        return Request(self, rid.value, (F, psi0, tt), out, (Nt + 1, int(My) - 1, int(Mx) - 1))
+
+    def close(self):
+        if self._s is not None:
+            _lib.mgrit_server_destroy(self._s)
+            self._s = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        self.close()

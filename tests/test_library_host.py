@@ -89,3 +89,22 @@ def test_fd_eigen_matches_scipy(rho, n, h, K):
     assert np.abs(V.T @ Kd @ V - np.diag(lam)).max() < 1e-11 * np.abs(lam).max()
     for l in range(min(n, 5)):
         assert mg.fd_stiffness_entry(rho, h, K, l) == pytest.approx(Kd[0, l], rel=1e-12)
+
+
+def test_footprint_grows_with_the_problem():
+    mg = _lib()
+    t1 = np.linspace(0, 1, 65)
+    t2 = np.linspace(0, 1, 257)
+    a = mg.footprint(0.7, 0.8, 1, 1, 64, 64, t1, m=4, precond="fd-bf16", coarse="opt")
+    b = mg.footprint(0.7, 0.8, 1, 1, 128, 128, t1, m=4, precond="fd-bf16", coarse="opt")
+    c = mg.footprint(0.7, 0.8, 1, 1, 64, 64, t2, m=4, precond="fd-bf16", coarse="opt")
+    d = mg.footprint(0.7, 0.8, 1, 1, 64, 64, t1, mem=mg.MEM_HOST, m=4, precond="fd-bf16", coarse="opt")
+    assert a < b and a < c and a < d
+
+
+def test_server_rejects_bad_arguments_without_gpu_work():
+    mg = _lib()
+    with pytest.raises(mg.MgritError):
+        mg.Server(0, 1)
+    with pytest.raises(mg.MgritError):
+        mg.Server(1 << 20, 0)
