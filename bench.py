@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -50,6 +52,54 @@ def cpu_baseline(W, t, F, psi0, steps, cg_rtol):
                       f"{len(t) - 1} steps, CG rtol {cg_rtol:g}, numpy FP64 on the host; {dt:.1f} s"}
 
 
+SOLVE_OPTS = dict(coarse="opt", precond="fd-bf16", cg_rtol=1e-10, cg_maxit=100000, tol_abs=0.0, tol_rel=1e-9,
+                  max_iter=40, max_levels=3)
+
+
+def serving(mgrit, wl, torch, n_requests, rate, max_concurrent, budget_gb):
+    """Replay a seeded Poisson trace through the server; latency = finish - arrival."""
+    trace = wl.serving_trace(5, n_requests, rate)
+    dev = [(torch.from_numpy(r["F"]).cuda(), torch.from_numpy(r["psi0"]).cuda()) for r in trace]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    handles = []
+    with mgrit.Server(int(budget_gb * (1 << 30)), max_concurrent=max_concurrent) as srv:
+        for r, (F, p) in zip(trace, dev):
+            delay = r["arrival"] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            handles.append((srv.submit(F, p, r["beta"], r["gamma"], r["Kx"], r["Ky"], r["nx"] + 1, r["ny"] + 1,
+                                       r["t"], m=8, **SOLVE_OPTS), time.perf_counter() - t0))
+        done = [(h.wait()[1], sub) for h, sub in handles]
+    span = max(i.finish_s for i, _ in done) - min(i.submit_s for i, _ in done)
+    lat = np.array([i.finish_s - i.submit_s for i, _ in done])
+    dof = sum(r["nx"] * r["ny"] * r["Nt"] for r in trace)
+    ok = all(i.rc == 0 for i, _ in done)
+    return {"requests": n_requests, "arrival_rate_per_s": rate, "max_concurrent": max_concurrent,
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "mean_queue_s": float(np.mean([i.start_s - i.submit_s for i, _ in done])),
+            "throughput_dof_per_s": dof / span, "all_converged": ok,
+            "trace": "seed 5: Poisson arrivals; n_x, n_y ~ U{63..255}, N_t ~ U{64..512} (multiple of 8), "
+                     "beta, gamma ~ U(0.55, 0.95), K = 1, m = 8, FP64 accuracy (CG 1e-10, stop 1e-9 rel.)"}
+
+
+def many_instance(mgrit, wl, torch, n_problems, max_concurrent):
+    """Independent problems of uneven sizes submitted at once; aggregate DOF/s."""
+    probs = wl.many_problems(4, n_problems)
+    dev = [(torch.from_numpy(r["F"]).cuda(), torch.from_numpy(r["psi0"]).cuda()) for r in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with mgrit.Server(200 << 30, max_concurrent=max_concurrent) as srv:
+        hs = [srv.submit(F, p, r["beta"], r["gamma"], r["Kx"], r["Ky"], r["nx"] + 1, r["ny"] + 1, r["t"], m=r["m"],
+                         **SOLVE_OPTS) for r, (F, p) in zip(probs, dev)]
+        infos = [h.wait()[1] for h in hs]
+    dt = time.perf_counter() - t0
+    dof = sum(r["nx"] * r["ny"] * r["Nt"] for r in probs)
+    return {"problems": n_problems, "max_concurrent": max_concurrent, "dof_per_s": dof / dt, "seconds": dt,
+            "all_converged": all(i.rc == 0 for i in infos),
+            "set": "seed 4: n ~ U{127..255} square, N_t ~ U{64..256}, m in {4, 8, 16}, beta, gamma ~ U(0.55, 0.95)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +114,7 @@ def main():
     ap.add_argument("--max-levels", type=int, default=3)
     ap.add_argument("--cg-adapt", type=float, default=0.0,
                     help="CG rtol of MGRIT iteration k = clamp(cg_adapt x relative residual, cg_rtol, 1e-4)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving trace and the many-instance batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 512 MiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--skip-reference", action="store_true",
@@ -163,6 +214,9 @@ def main():
                       "sequential_dof_per_s": dof / seq_s if seq_s else None, "sequential_rel_l2_err": seq_err,
                       "parallelism": "time (MGRIT), one GPU"},
            "roofline": roofline}
+    if not args.no_serving and not args.skip_reference:
+        out["serving"] = serving(mgrit, wl, torch, 32, 4.0, 4, 64)
+        out["many_instance"] = many_instance(mgrit, wl, torch, 16, 4)
     if not args.no_cpu and not args.skip_reference:
         out["cpu_baseline"] = cpu_baseline(W, t, F, psi0, args.cpu_steps, args.cg_rtol)
     print(json.dumps(out), flush=True)

@@ -63,3 +63,37 @@ FP64_VCYCLE_255 = dict(name="fp64-vcycle-255x255x1024", beta=0.75, gamma=0.85, K
 # u = x^2 (1-x)^2 y^2 (1-y)^2 e^{-t}.
 FP64_TWOLEVEL_31 = dict(name="fp64-twolevel-31x31x64", beta=0.7, gamma=0.8, Kx=1.0, Ky=1.0, Mx=32, My=32, Nt=64,
                         T=1.0, m=4, levels=2, amp=1.0)
+
+
+def serving_trace(seed, n_requests, rate, n_range=(63, 255), nt_range=(64, 512), m=8):
+    """Poisson arrivals (rate per second) of solves with n_x, n_y ~ U{n_range}, N_t ~ U{nt_range}
+    (a multiple of m), beta, gamma ~ U(0.55, 0.95), K = 1, T = 1, uniform grid; F ~ N(0,1), psi_0 ~ U[0,1].
+    Returns a list of dicts with the arrival time and every input (host arrays)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        nx, ny = (int(v) for v in rng.integers(n_range[0], n_range[1] + 1, 2))
+        Nt = int(rng.integers(nt_range[0], nt_range[1] + 1)) // m * m
+        beta, gamma = (float(v) for v in rng.uniform(0.55, 0.95, 2))
+        F, psi0 = random_inputs(seed * 1000 + k, Nt, nx, ny)
+        out.append(dict(arrival=t, nx=nx, ny=ny, Nt=Nt, beta=beta, gamma=gamma, Kx=1.0, Ky=1.0, F=F, psi0=psi0,
+                        t=uniform_grid(Nt)))
+    return out
+
+
+def many_problems(seed, n_problems, n_range=(127, 255), nt_range=(64, 256), ms=(4, 8, 16)):
+    """Independent problems of uneven sizes (seeded): n ~ U{n_range} square, N_t ~ U{nt_range} (a multiple
+    of the drawn m), m from ms, beta, gamma ~ U(0.55, 0.95), K = 1; F ~ N(0,1), psi_0 ~ U[0,1]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_problems):
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        m = int(rng.choice(ms))
+        Nt = max(2 * m, int(rng.integers(nt_range[0], nt_range[1] + 1)) // m * m)
+        beta, gamma = (float(v) for v in rng.uniform(0.55, 0.95, 2))
+        F, psi0 = random_inputs(seed * 1000 + k, Nt, n, n)
+        out.append(dict(nx=n, ny=n, Nt=Nt, m=m, beta=beta, gamma=gamma, Kx=1.0, Ky=1.0, F=F, psi0=psi0,
+                        t=uniform_grid(Nt)))
+    return out
