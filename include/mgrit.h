@@ -73,6 +73,15 @@ extern "C" {
  * FP64, so the solution is the FP64 one. */
 #define MGRIT_PRECOND_FD_BF16 2
 
+/* Tile edge of the operator kernels (64 or 32 nodes).  AUTO times both on the
+ * first batch of each width and keeps the faster; RULE takes 64 when the batch
+ * holds at least 512 such tiles.  The choice changes speed only: results are
+ * bitwise the same (dot products are summed per 32 x 32 block in a fixed order). */
+#define MGRIT_TILE_AUTO  0
+#define MGRIT_TILE_RULE  1
+#define MGRIT_TILE_64    2
+#define MGRIT_TILE_32    3
+
 typedef struct {
     double beta, gamma;     /* fractional orders, 1/2 < beta, gamma < 1 (eq. 1.1)        */
     double Kx, Ky;          /* diffusion coefficients, > 0                               */
@@ -101,6 +110,7 @@ typedef struct {
                             /* is an iterate starts CG from that value; 0: always from the  */
                             /* propagated state (the converged result is the same)          */
     double divergence_factor; /* EDIVERGED when a norm exceeds this x the first (0: off) */
+    int tile_policy;        /* MGRIT_TILE_*                                              */
 } mgrit_options;
 
 typedef struct {
@@ -117,7 +127,7 @@ typedef struct mgrit_handle mgrit_handle;
 /* Fill `opt` with defaults: m = 8, max_levels = 30, FCF, CN, FP64, max_iter = 100,
  * tol_abs = 1e-9, tol_rel = 0, cg_rtol = 1e-9 (the paper's tolerances, Section 3.2),
  * cg_maxit = 10000, precond = NONE, cg_rtol_adapt = 0, warm_start = 1,
- * divergence_factor = 0. */
+ * divergence_factor = 0, tile_policy = AUTO. */
 void mgrit_default_options(mgrit_options* opt);
 
 /* Validate the problem, evaluate the Toeplitz generating sequences of Section 2

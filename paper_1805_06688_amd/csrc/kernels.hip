@@ -91,8 +91,8 @@ __device__ __forceinline__ double slice_sum(const double* partial, int pmax, int
     return acc;
 }
 
-// out = add + sign (M v + theta A v) on one TT x TT tile; returns the
-// block-reduced dot product selected by dot_mode (valid in every thread).
+// out = add + sign (M v + theta A v) on one TT x TT tile; with dot_mode the
+// dot products of its 32 x 32 quadrants go to dot_out[32-tile index].
 template <int TT>
 __device__ void apply_tile(const Geom& g, const Seqs& sq, const double* __restrict__ v, double* __restrict__ out,
                            const double* __restrict__ add, double theta, double sign, int dot_mode, int tile,
@@ -219,29 +219,42 @@ __device__ void apply_tile(const Geom& g, const Seqs& sq, const double* __restri
             }
     __syncthreads();
 
-    double dot = 0.0;
+    // Per 32 x 32 quadrant (the partial-sum unit of both tile sizes, with the
+    // same thread -> element order), so the sums do not depend on TT.
     const double mass = g.mass;
-    for (int idx = tid; idx < TT * TT; idx += NT) {
-        const int jl = idx / TT, il = idx - jl * TT;
-        const int i = i0 + il, j = j0 + jl;
-        if (i >= nx || j >= ny) continue;
-        const long long o = (long long)j * nx + i;
-        const double c = v[o];
-        const bool hl = i > 0, hr = i + 1 < nx, hd = j > 0, hu = j + 1 < ny;
-        double m7 = 6.0 * c;
-        m7 += hl ? v[o - 1] : 0.0;
-        m7 += hr ? v[o + 1] : 0.0;
-        m7 += hd ? v[o - nx] : 0.0;
-        m7 += hu ? v[o + nx] : 0.0;
-        m7 += (hr && hu) ? v[o + nx + 1] : 0.0;
-        m7 += (hl && hd) ? v[o - nx - 1] : 0.0;
-        double val = sign * (mass * m7 + theta * epi[jl * (TT + 1) + il]);
-        if (add) val += add[o];
-        out[o] = val;
-        if (dot_mode == 1) dot += c * val;
-        else if (dot_mode == 2) dot += val * val;
+#pragma unroll
+    for (int qd = 0; qd < (TT / 32) * (TT / 32); ++qd) {
+        const int qx = qd % (TT / 32), qy = qd / (TT / 32);
+        double dot = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int idx = tid + NT * k;
+            const int jl = qy * 32 + idx / 32, il = qx * 32 + (idx & 31);
+            const int i = i0 + il, j = j0 + jl;
+            if (i >= nx || j >= ny) continue;
+            const long long o = (long long)j * nx + i;
+            const double c = v[o];
+            const bool hl = i > 0, hr = i + 1 < nx, hd = j > 0, hu = j + 1 < ny;
+            double m7 = 6.0 * c;
+            m7 += hl ? v[o - 1] : 0.0;
+            m7 += hr ? v[o + 1] : 0.0;
+            m7 += hd ? v[o - nx] : 0.0;
+            m7 += hu ? v[o + nx] : 0.0;
+            m7 += (hr && hu) ? v[o + nx + 1] : 0.0;
+            m7 += (hl && hd) ? v[o - nx - 1] : 0.0;
+            double val = sign * (mass * m7 + theta * epi[jl * (TT + 1) + il]);
+            if (add) val += add[o];
+            out[o] = val;
+            if (dot_mode == 1) dot += c * val;
+            else if (dot_mode == 2) dot += val * val;
+        }
+        if (dot_mode) {
+            dot = block_sum(dot, red);
+            const int gx = i0 / 32 + qx, gy = j0 / 32 + qy;
+            if (threadIdx.x == 0 && gx < g.tiles_x[1] && gy < g.tiles_y[1])
+                dot_out[gx + g.tiles_x[1] * gy] = dot;
+        }
     }
-    if (dot_mode) *dot_out = block_sum(dot, red);
 }
 
 // ---- operator application over slices given by ApplyDesc ----
@@ -258,10 +271,8 @@ __global__ __launch_bounds__(NT) void k_apply(Geom g, Seqs sq, const ApplyDesc* 
     __shared__ double red[4];
     const ApplyDesc d = desc[s];
     const double* addp = (addbase && d.add >= 0) ? addbase + d.add * g.stride : nullptr;
-    double dot = 0.0;
     apply_tile<TT>(g, sq, vbase + d.v * g.stride, outbase + d.out * g.stride, addp, d.theta, sign, dot_mode, tile,
-                   lds, red, &dot);
-    if (dot_mode && threadIdx.x == 0) partial[(long long)s * g.pmax + tile] = dot;
+                   lds, red, dot_mode ? partial + (long long)s * g.pmax : nullptr);
 }
 
 // mode 0: right-hand side b = M u + theta_rhs A u (+F), partial ||b||^2
@@ -275,22 +286,21 @@ __global__ __launch_bounds__(NT) void k_prop_apply(Geom g, Seqs sq, const PropDe
     int s, tile;
     decode_block(g.ntiles[tv], S, s, tile);
     if (s < 0) return;
-    if (MODE == 2 && !active[s]) return;
+    if (MODE == 2 && active && !active[s]) return;
     __shared__ double lds[TC<TT>::LDS];
     __shared__ double red[4];
     const PropDesc d = desc[s];
     const long long so = (long long)s * g.stride;
-    double dot = 0.0;
+    double* part = partial + (long long)s * g.pmax;
     if (MODE == 0) {
         const double* f = (fbase && d.f >= 0) ? fbase + d.f * g.stride : nullptr;
-        apply_tile<TT>(g, sq, ubase + d.u * g.stride, wsout + so, f, d.theta_rhs, 1.0, 2, tile, lds, red, &dot);
+        apply_tile<TT>(g, sq, ubase + d.u * g.stride, wsout + so, f, d.theta_rhs, 1.0, 2, tile, lds, red, part);
     } else if (MODE == 1) {
         apply_tile<TT>(g, sq, ubase + d.x * g.stride, wsout + so, wsin + so, d.theta_lhs, -1.0, 2, tile, lds, red,
-                       &dot);
+                       part);
     } else {
-        apply_tile<TT>(g, sq, wsin + so, wsout + so, nullptr, d.theta_lhs, 1.0, 1, tile, lds, red, &dot);
+        apply_tile<TT>(g, sq, wsin + so, wsout + so, nullptr, d.theta_lhs, 1.0, 1, tile, lds, red, part);
     }
-    if (threadIdx.x == 0) partial[(long long)s * g.pmax + tile] = dot;
 }
 
 // Element range of chunk c of a flattened slice.
@@ -491,23 +501,30 @@ __global__ __launch_bounds__(NT) void k_fd_gemm(Geom g, int S, const double* __r
     __syncthreads();
     double* Y = yout + so;
     const double theta = EPI == 1 ? desc[s].theta_lhs : 0.0;
-    double dot = 0.0;
-    for (int idx = tid; idx < TT * TT; idx += NT) {
-        const int jl = idx / TT, il = idx - jl * TT;
-        const int i = i0 + il, j = j0 + jl;
-        if (i >= nx || j >= ny) continue;
-        const long long o = (long long)j * nx + i;
-        double v = epi[jl * (TT + 1) + il];
-        if (EPI == 1) v /= 1.0 + theta * (lx[i] + ly[j]);
-        Y[o] = v;
-        if (EPI == 2) dot += v * rws[so + o];
-    }
-    if (EPI == 2) {
-        dot = block_sum(dot, red);
-        if (threadIdx.x == 0) partial[(long long)s * g.pmax + tile] = dot;
+#pragma unroll
+    for (int qd = 0; qd < (TT / 32) * (TT / 32); ++qd) {     // per 32 x 32 quadrant, as in apply_tile
+        const int qx = qd % (TT / 32), qy = qd / (TT / 32);
+        double dot = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int idx = tid + NT * k;
+            const int jl = qy * 32 + idx / 32, il = qx * 32 + (idx & 31);
+            const int i = i0 + il, j = j0 + jl;
+            if (i >= nx || j >= ny) continue;
+            const long long o = (long long)j * nx + i;
+            double v = epi[jl * (TT + 1) + il];
+            if (EPI == 1) v /= 1.0 + theta * (lx[i] + ly[j]);
+            Y[o] = v;
+            if (EPI == 2) dot += v * rws[so + o];
+        }
+        if (EPI == 2) {
+            dot = block_sum(dot, red);
+            const int gx = i0 / 32 + qx, gy = j0 / 32 + qy;
+            if (threadIdx.x == 0 && gx < g.tiles_x[1] && gy < g.tiles_y[1])
+                partial[(long long)s * g.pmax + gx + g.tiles_x[1] * gy] = dot;
+        }
     }
 }
-
 
 // ---- fast-diagonalisation preconditioner in BF16 (FP32 accumulation) ----
 // v_mfma_f32_16x16x32_bf16 lane layout (gfx950): A[i][k] and B^T[j][k] hold 8
@@ -623,25 +640,33 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __
             }
     __syncthreads();
     const double theta = EPI == 1 ? desc[s].theta_lhs : 0.0;
-    double dot = 0.0;
-    for (int idx = tid; idx < 64 * 64; idx += NT) {
-        const int jl = idx >> 6, il = idx & 63;
-        const int i = i0 + il, j = j0 + jl;
-        float v = epi[jl * 65 + il];
-        if (EPI == 1) v = (float)((double)v / (1.0 + theta * ((double)lx[i] + (double)ly[j])));
-        if (EPI == 2) {
-            if (i < nx && j < ny) {
-                const long long o = (long long)j * nx + i;
-                ((double*)yout)[so + o] = (double)v;
-                dot += (double)v * rws[so + o];
+#pragma unroll
+    for (int qd = 0; qd < 4; ++qd) {                          // per 32 x 32 quadrant, as in apply_tile
+        const int qx = qd & 1, qy = qd >> 1;
+        double dot = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int idx = tid + NT * k;
+            const int jl = qy * 32 + idx / 32, il = qx * 32 + (idx & 31);
+            const int i = i0 + il, j = j0 + jl;
+            float v = epi[jl * 65 + il];
+            if (EPI == 1) v = (float)((double)v / (1.0 + theta * ((double)lx[i] + (double)ly[j])));
+            if (EPI == 2) {
+                if (i < nx && j < ny) {
+                    const long long o = (long long)j * nx + i;
+                    ((double*)yout)[so + o] = (double)v;
+                    dot += (double)v * rws[so + o];
+                }
+            } else {
+                ((__bf16*)yout)[sob + (long long)j * npx + i] = (__bf16)v;
             }
-        } else {
-            ((__bf16*)yout)[sob + (long long)j * npx + i] = (__bf16)v;
         }
-    }
-    if (EPI == 2) {
-        dot = block_sum(dot, red);
-        if (threadIdx.x == 0) partial[(long long)s * g.pmax + tile] = dot;
+        if (EPI == 2) {
+            dot = block_sum(dot, red);
+            const int gx = i0 / 32 + qx, gy = j0 / 32 + qy;
+            if (threadIdx.x == 0 && gx < g.tiles_x[1] && gy < g.tiles_y[1])
+                partial[(long long)s * g.pmax + gx + g.tiles_x[1] * gy] = dot;
+        }
     }
 }
 

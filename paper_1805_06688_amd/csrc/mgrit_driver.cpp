@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -122,8 +123,8 @@ struct mgrit_handle {
     std::vector<void*> allocations;
     size_t dev_bytes = 0;           // device memory owned by the handle
     double cur_rtol = 0.0;          // CG tolerance of the current MGRIT iteration
-    int force_tile = -1;            // tuning override (MGRIT_FORCE_TILE=0|1)
-    long long tile_threshold = 512; // 64-tiles when S * tiles64 >= this (MGRIT_TILE_THRESHOLD)
+    std::map<int, int> tile_of;     // tile variant chosen per batch width (autotuned)
+    hipEvent_t tune_ev[5] = {};
     // instrumentation of the CG operator kernel
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;
@@ -516,11 +517,48 @@ int prof_drain(mgrit_handle* h) {
     return 0;
 }
 
-// Operator tile edge for a batch of S slices: 64 when the batch fills the
-// chip with such tiles, else 32.
-int tile_variant(const mgrit_handle* h, int S) {
-    if (h->force_tile >= 0) return h->force_tile;
-    return (long long)S * h->geom.ntiles[0] >= h->tile_threshold ? 0 : 1;
+// Operator tile edge for a batch of S slices (0: 64, 1: 32).  RULE: 64 when
+// the batch fills the chip with such tiles.  AUTO: the first pass of each
+// batch width times the CG operator kernel in both variants on the pass's
+// right-hand sides (it writes q and its partials, recomputed before use) and
+// keeps the faster; without a pass to time on, the rule.  The iterates do not depend on the choice: every tiled
+// kernel sums its dot products per 32 x 32 block in one fixed order.
+int tile_variant(mgrit_handle* h, const Pass* ps, int S, int* tv) {
+    const int rule = (long long)S * h->geom.ntiles[0] >= 512 ? 0 : 1;
+    switch (h->opt.tile_policy) {
+        case MGRIT_TILE_64: *tv = 0; return 0;
+        case MGRIT_TILE_32: *tv = 1; return 0;
+        case MGRIT_TILE_RULE: *tv = rule; return 0;
+        default: break;
+    }
+    auto it = h->tile_of.find(S);
+    if (it != h->tile_of.end()) {
+        *tv = it->second;
+        return 0;
+    }
+    if (!ps) {                                          // nothing to time on: the rule
+        *tv = rule;
+        return 0;
+    }
+    if (!h->tune_ev[0])
+        for (hipEvent_t& e : h->tune_ev) HIPCHK(hipEventCreate(&e));
+    const Geom* g = &h->geom;
+    const int order[4] = {0, 1, 0, 1};                  // alternate to average out clocks
+    HIPCHK(hipEventRecord(h->tune_ev[0], h->stream));
+    for (int k = 0; k < 4; ++k) {
+        HIPCHK(launch_cg_apply(g, &h->seqs, order[k], ps->d, S, h->b, h->q, h->ppq, nullptr, (void*)h->stream));
+        HIPCHK(hipEventRecord(h->tune_ev[k + 1], h->stream));
+    }
+    HIPCHK(hipEventSynchronize(h->tune_ev[4]));
+    float ms[2] = {0.f, 0.f};
+    for (int k = 0; k < 4; ++k) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, h->tune_ev[k], h->tune_ev[k + 1]));
+        ms[order[k]] += t;
+    }
+    *tv = ms[0] <= ms[1] ? 0 : 1;
+    h->tile_of[S] = *tv;
+    return 0;
 }
 
 // Batched CG solve of one pass (S <= Smax slices).
@@ -535,15 +573,18 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     const double rtol2 = rtol * rtol;
     const int pk = h->opt.precond;
     const bool pc = pk != MGRIT_PRECOND_NONE;
-    const int tv = tile_variant(h, S);
-    const int nt = g->ntiles[tv], nc = g->nchunk;
-    const int nrz = pk == MGRIT_PRECOND_FD_BF16 ? g->ntiles[0] : nt;   // r.z partials per slice
+    int tv = 0;
+    CHK(tile_variant(h, nullptr, S, &tv));
+    // Tiled kernels leave one partial sum per 32 x 32 block whatever their tile
+    // size, so the reductions (and the iterates) do not depend on tv.
+    const int nt = g->ntiles[1], nc = g->nchunk;
     auto precondition = [&](double* prz_out, const int* act) -> int {
         if (pk == MGRIT_PRECOND_FD)
             return launch_fd_apply(g, &h->fd, tv, ps.d, S, h->r, h->z, h->t1, h->t2, prz_out, act, st);
         return launch_fdb_apply(g, &h->fdb, ps.d, S, h->r, h->z, h->tb1, h->tb2, prz_out, act, st);
     };
     HIPCHK(launch_rhs(g, &h->seqs, tv, ps.d, S, ubase, fbase, h->b, h->pbb, st));
+    CHK(tile_variant(h, &ps, S, &tv));
     HIPCHK(launch_cg_init_x(g, ps.d, S, ubase, x0base, (x0base && warm && h->opt.warm_start) ? 1 : 0, xbase, st));
     HIPCHK(launch_init_residual(g, &h->seqs, tv, ps.d, S, xbase, h->b, h->r, h->prr[0], st));
     if (pc) HIPCHK(precondition(h->prz[0], nullptr));
@@ -553,8 +594,8 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
                            h->iters, st));
     int cur = 0;
     int it = 0;
-    int nrho = pc ? nrz : nt;                    // entries of the current rho partials
-    const int nrho_next = pc ? nrz : nc;
+    int nrho = nt;                               // entries of the current rho partials
+    const int nrho_next = pc ? nt : nc;
     const int maxit = h->opt.cg_maxit;
     // Iterations are launched in chunks between host checks of the active
     // flags: the first chunk covers what this pass needed last time, later
@@ -801,6 +842,7 @@ void mgrit_default_options(mgrit_options* o) {
     o->cg_rtol_adapt = 0.0;
     o->warm_start = 1;
     o->divergence_factor = 0.0;
+    o->tile_policy = MGRIT_TILE_AUTO;
 }
 
 const char* mgrit_last_error(void) { return g_err; }
@@ -829,6 +871,8 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
     if (o.precision != MGRIT_PREC_FP64) return fail(MGRIT_EINVAL, "unknown precision");
     if (o.precond < MGRIT_PRECOND_NONE || o.precond > MGRIT_PRECOND_FD_BF16)
         return fail(MGRIT_EINVAL, "unknown preconditioner");
+    if (o.tile_policy < MGRIT_TILE_AUTO || o.tile_policy > MGRIT_TILE_32)
+        return fail(MGRIT_EINVAL, "unknown tile policy");
     if (o.max_iter < 1 || o.cg_maxit < 1 || !(o.cg_rtol > 0.0) || !(o.tol_abs >= 0.0) || !(o.tol_rel >= 0.0) ||
         !(o.cg_rtol_adapt >= 0.0) || (o.warm_start != 0 && o.warm_start != 1))
         return fail(MGRIT_EINVAL, "bad iteration limits or tolerances");
@@ -842,8 +886,6 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
     h->t.assign(p.t, p.t + p.Nt + 1);
     h->prob.t = h->t.data();
     h->stream = (hipStream_t)stream;
-    if (const char* e = std::getenv("MGRIT_FORCE_TILE")) h->force_tile = std::atoi(e) ? 1 : 0;
-    if (const char* e = std::getenv("MGRIT_TILE_THRESHOLD")) h->tile_threshold = std::atoll(e);
     Geom& g = h->geom;
     g.nx = (int)nx;
     g.ny = (int)ny;
@@ -877,6 +919,8 @@ void mgrit_destroy(mgrit_handle* h) {
     else (void)hipDeviceSynchronize();
     for (void* p : h->allocations) (void)hipFree(p);
     for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->tune_ev)
+        if (e) (void)hipEventDestroy(e);
     if (h->h_act) (void)hipHostFree(h->h_act);
     if (h->h_iters) (void)hipHostFree(h->h_iters);
     if (h->h_norm) (void)hipHostFree(h->h_norm);
@@ -1041,7 +1085,9 @@ int mgrit_apply(mgrit_handle* h, int nslices, const double* theta, double sign, 
     if (e != hipSuccess) return fail(MGRIT_ENOMEM, "descriptor allocation failed");
     sg.owned.push_back(dd);
     HIPCHK(hipMemcpyAsync(dd, hd.data(), nslices * sizeof(ApplyDesc), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(launch_apply(&h->geom, &h->seqs, tile_variant(h, nslices), (const ApplyDesc*)dd, nslices, dv, dout, da,
+    int tv = 0;
+    CHK(tile_variant(h, nullptr, nslices, &tv));
+    HIPCHK(launch_apply(&h->geom, &h->seqs, tv, (const ApplyDesc*)dd, nslices, dv, dout, da,
                         sign, 0, nullptr, nullptr, (void*)h->stream));
     if (mem == MGRIT_MEM_HOST)
         HIPCHK(hipMemcpyAsync(out, dout, nslices * st * sizeof(double), hipMemcpyDeviceToHost, h->stream));

@@ -19,6 +19,7 @@ RELAX = {"F": 0, "FCF": 1}
 COARSE = {"cn": 0, "be": 1, "cn2": 2, "opt": 3}
 PRECISION = {"fp64": 0}
 PRECOND = {"none": 0, "fd": 1, "fd-bf16": 2}
+TILE = {"auto": 0, "rule": 1, "64": 2, "32": 3}
 
 
 class _Problem(ctypes.Structure):
@@ -34,7 +35,7 @@ class _Options(ctypes.Structure):
                 ("tol_abs", ctypes.c_double), ("tol_rel", ctypes.c_double), ("cg_rtol", ctypes.c_double),
                 ("cg_maxit", ctypes.c_int), ("precond", ctypes.c_int), ("cg_rtol_adapt", ctypes.c_double),
                 ("warm_start", ctypes.c_int),
-                ("divergence_factor", ctypes.c_double)]
+                ("divergence_factor", ctypes.c_double), ("tile_policy", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -210,8 +211,9 @@ def make_problem(beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0)):
 
 def make_options(m=8, max_levels=30, relax="FCF", coarse="cn", precision="fp64", max_iter=100, tol_abs=1e-9,
                  tol_rel=0.0, cg_rtol=1e-9, cg_maxit=10000, precond="none", cg_rtol_adapt=0.0, warm_start=True,
-                 divergence_factor=0.0):
+                 divergence_factor=0.0, tile="auto"):
     o = default_options()
+    o.tile_policy = TILE[str(tile)]
     o.m, o.max_levels, o.max_iter, o.cg_maxit = int(m), int(max_levels), int(max_iter), int(cg_maxit)
     o.relax, o.coarse, o.precision = RELAX[relax], COARSE[coarse], PRECISION[precision]
     o.precond = PRECOND[precond]

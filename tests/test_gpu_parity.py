@@ -314,3 +314,24 @@ def test_warm_start_keeps_fixed_point_and_saves_iterations():
     assert rel(out[True][0], ref) <= 1e-10 and rel(out[False][0], ref) <= 1e-10
     assert out[True][2] == out[False][2]
     assert out[True][1] < 0.8 * out[False][1]
+
+
+@pytest.mark.parametrize("pc", ["none", "fd", "fd-bf16"])
+def test_tile_policy_changes_speed_only(pc):
+    """64- and 32-node operator tiles (forced, by rule or autotuned) give bitwise the same solve."""
+    mg = _mg()
+    prob, t, F, psi0 = _random_problem(9, 32, beta=0.7, gamma=0.9, Mx=97, My=70, Kx=1.5, Ky=1.0)
+    out = {}
+    for tile in ("64", "32", "rule", "auto"):
+        with mg.Solver(prob.beta, prob.gamma, 1.5, 1.0, prob.Mx, prob.My, t, m=4, max_levels=3, coarse="opt",
+                       precond=pc, cg_rtol=1e-12, tol_abs=0.0, tol_rel=1e-10, max_iter=30, tile=tile) as s:
+            U, st, rc = s.solve(dev(F), dev(psi0))
+            assert rc == 0
+            out[tile] = (U.clone(), st.cg_iterations, st.iterations, st.history())
+    base = out["64"]
+    for tile, (U, cg, its, hist) in out.items():
+        assert torch.equal(U, base[0]), tile
+        assert (cg, its, hist) == base[1:], tile
+    op = fem.Operator(prob)
+    ref = propagator.sequential(op, propagator.CGSolver(op, 1e-14), t, F, psi0)
+    assert rel(host(base[0]), ref) <= 1e-9
