@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--precond", default="fd-bf16")
     ap.add_argument("--max-levels", type=int, default=3)
     ap.add_argument("--tile", default="auto", help="operator tile policy: auto | rule | 64 | 32")
+    ap.add_argument("--cg-rtol-coarse", type=float, default=0.0,
+                    help="CG tolerance on the coarse levels (0: --cg-rtol)")
     ap.add_argument("--cg-adapt", type=float, default=0.0,
                     help="CG rtol of MGRIT iteration k = clamp(cg_adapt x relative residual, cg_rtol, 1e-4)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving trace and the many-instance batch")
@@ -161,7 +163,7 @@ def main():
     s = mgrit.Solver(*common, m=W["m"], max_levels=args.max_levels, coarse=args.coarse, cg_rtol=args.cg_rtol,
                      cg_maxit=100000,
                      tol_abs=0.0, tol_rel=args.tol_rel, max_iter=40, precond=args.precond,
-                     cg_rtol_adapt=args.cg_adapt, tile=args.tile)
+                     cg_rtol_adapt=args.cg_adapt, tile=args.tile, cg_rtol_coarse=args.cg_rtol_coarse)
     U = torch.empty((Nt + 1) * nx * ny, dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
         s.solve(Fd, pd, out=U)
@@ -210,6 +212,7 @@ def main():
                       "Kx": W["Kx"], "Ky": W["Ky"], "m": W["m"], "levels": levels, "relax": "FCF",
                       "coarse": args.coarse, "precond": args.precond, "cg_rtol": args.cg_rtol,
                       "tol_rel": args.tol_rel, "cg_rtol_adapt": args.cg_adapt, "tile": args.tile,
+                      "cg_rtol_coarse": args.cg_rtol_coarse,
                       "mgrit_iterations": st.iterations, "phi_per_solve": st.phi_applications,
                       "cg_iterations_per_solve": st.cg_iterations, "rel_l2_err_vs_fp64_sequential": err,
                       "sequential_dof_per_s": dof / seq_s if seq_s else None, "sequential_rel_l2_err": seq_err,

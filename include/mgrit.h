@@ -111,6 +111,10 @@ typedef struct {
                             /* propagated state (the converged result is the same)          */
     double divergence_factor; /* EDIVERGED when a norm exceeds this x the first (0: off) */
     int tile_policy;        /* MGRIT_TILE_*                                              */
+    double cg_rtol_coarse;  /* > 0: CG rtol of the propagators on levels >= 1 (coarse     */
+                            /* corrections only; the fixed point is set by level 0, so    */
+                            /* this changes the MGRIT iteration count, not the solution); */
+                            /* 0: cg_rtol                                                  */
 } mgrit_options;
 
 typedef struct {
@@ -127,7 +131,7 @@ typedef struct mgrit_handle mgrit_handle;
 /* Fill `opt` with defaults: m = 8, max_levels = 30, FCF, CN, FP64, max_iter = 100,
  * tol_abs = 1e-9, tol_rel = 0, cg_rtol = 1e-9 (the paper's tolerances, Section 3.2),
  * cg_maxit = 10000, precond = NONE, cg_rtol_adapt = 0, warm_start = 1,
- * divergence_factor = 0, tile_policy = AUTO. */
+ * divergence_factor = 0, tile_policy = AUTO, cg_rtol_coarse = 0. */
 void mgrit_default_options(mgrit_options* opt);
 
 /* Validate the problem, evaluate the Toeplitz generating sequences of Section 2

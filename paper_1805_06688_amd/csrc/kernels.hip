@@ -57,8 +57,17 @@ struct TC {
     static constexpr int FD_LDS = (2 * KC * GAS > EPI) ? 2 * KC * GAS : EPI;
 };
 
+// Block -> (slice, tile).  Workgroups are dealt to the 8 XCDs round-robin;
+// with 8 or more slices every tile of a slice goes to one XCD (its L2 holds
+// the slice and the halos its tiles share), the grid padded to a multiple of
+// 8 slices.  Fewer than 8 slices are spread over all XCDs instead.
 __device__ __forceinline__ void decode_block(int ntiles, int S, int& s, int& tile) {
     const int bid = blockIdx.x;
+    if (S < 8) {
+        s = bid / ntiles;
+        tile = bid - s * ntiles;
+        return;
+    }
     const int xcd = bid & 7;
     const int local = bid >> 3;
     s = (local / ntiles) * 8 + xcd;
@@ -66,7 +75,7 @@ __device__ __forceinline__ void decode_block(int ntiles, int S, int& s, int& til
     if (s >= S) s = -1;
 }
 
-inline int grid_blocks(int ntiles, int S) { return ntiles * ((S + 7) / 8) * 8; }
+inline int grid_blocks(int ntiles, int S) { return S < 8 ? ntiles * S : ntiles * ((S + 7) / 8) * 8; }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -123,6 +123,7 @@ struct mgrit_handle {
     std::vector<void*> allocations;
     size_t dev_bytes = 0;           // device memory owned by the handle
     double cur_rtol = 0.0;          // CG tolerance of the current MGRIT iteration
+    int cur_level = 0;              // level of the passes being run
     std::map<int, int> tile_of;     // tile variant chosen per batch width (autotuned)
     hipEvent_t tune_ev[5] = {};
     // instrumentation of the CG operator kernel
@@ -569,7 +570,8 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     if (S > h->Smax) return fail(MGRIT_EINVAL, "batch of %d slices exceeds workspace (%d)", S, h->Smax);
     const Geom* g = &h->geom;
     void* st = (void*)h->stream;
-    const double rtol = h->cur_rtol > 0.0 ? h->cur_rtol : h->opt.cg_rtol;
+    double rtol = h->cur_rtol > 0.0 ? h->cur_rtol : h->opt.cg_rtol;
+    if (h->cur_level > 0 && h->opt.cg_rtol_coarse > 0.0) rtol = h->opt.cg_rtol_coarse;
     const double rtol2 = rtol * rtol;
     const int pk = h->opt.precond;
     const bool pc = pk != MGRIT_PRECOND_NONE;
@@ -655,6 +657,7 @@ Bases bases(mgrit_handle* h, int l) {
 // warm: the level's state holds meaningful previous values of the target
 // points, used as CG start vectors (descriptors with x0 >= 0).
 int run_batch(mgrit_handle* h, int l, const Batch& b, double* xout = nullptr, int warm = 0) {
+    h->cur_level = l;
     Bases B = bases(h, l);
     double* X = xout ? xout : B.U;
     if (b.npass == 1) return run_pass(h, b.pass[0], B.U, X, B.F, B.G, B.U, warm);
@@ -843,6 +846,7 @@ void mgrit_default_options(mgrit_options* o) {
     o->warm_start = 1;
     o->divergence_factor = 0.0;
     o->tile_policy = MGRIT_TILE_AUTO;
+    o->cg_rtol_coarse = 0.0;
 }
 
 const char* mgrit_last_error(void) { return g_err; }
@@ -871,6 +875,7 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
     if (o.precision != MGRIT_PREC_FP64) return fail(MGRIT_EINVAL, "unknown precision");
     if (o.precond < MGRIT_PRECOND_NONE || o.precond > MGRIT_PRECOND_FD_BF16)
         return fail(MGRIT_EINVAL, "unknown preconditioner");
+    if (!(o.cg_rtol_coarse >= 0.0 && o.cg_rtol_coarse < 1.0)) return fail(MGRIT_EINVAL, "bad cg_rtol_coarse");
     if (o.tile_policy < MGRIT_TILE_AUTO || o.tile_policy > MGRIT_TILE_32)
         return fail(MGRIT_EINVAL, "unknown tile policy");
     if (o.max_iter < 1 || o.cg_maxit < 1 || !(o.cg_rtol > 0.0) || !(o.tol_abs >= 0.0) || !(o.tol_rel >= 0.0) ||
@@ -1016,6 +1021,7 @@ int mgrit_propagate(mgrit_handle* h, int level, const int* step, int nslices, co
     CHK(sg.in(u_in, nslices * st, mem, &du));
     CHK(sg.in(g, nslices * st, mem, &dg));
     CHK(sg.outbuf(u_out, nslices * st, mem, &dout));
+    h->cur_level = level;
     for (int s0 = 0; s0 < nslices; s0 += h->Smax) {
         const int S = std::min(h->Smax, nslices - s0);
         Batch b;

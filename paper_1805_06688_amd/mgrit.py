@@ -35,7 +35,8 @@ class _Options(ctypes.Structure):
                 ("tol_abs", ctypes.c_double), ("tol_rel", ctypes.c_double), ("cg_rtol", ctypes.c_double),
                 ("cg_maxit", ctypes.c_int), ("precond", ctypes.c_int), ("cg_rtol_adapt", ctypes.c_double),
                 ("warm_start", ctypes.c_int),
-                ("divergence_factor", ctypes.c_double), ("tile_policy", ctypes.c_int)]
+                ("divergence_factor", ctypes.c_double), ("tile_policy", ctypes.c_int),
+                ("cg_rtol_coarse", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -211,9 +212,10 @@ def make_problem(beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0)):
 
 def make_options(m=8, max_levels=30, relax="FCF", coarse="cn", precision="fp64", max_iter=100, tol_abs=1e-9,
                  tol_rel=0.0, cg_rtol=1e-9, cg_maxit=10000, precond="none", cg_rtol_adapt=0.0, warm_start=True,
-                 divergence_factor=0.0, tile="auto"):
+                 divergence_factor=0.0, tile="auto", cg_rtol_coarse=0.0):
     o = default_options()
     o.tile_policy = TILE[str(tile)]
+    o.cg_rtol_coarse = float(cg_rtol_coarse)
     o.m, o.max_levels, o.max_iter, o.cg_maxit = int(m), int(max_levels), int(max_iter), int(cg_maxit)
     o.relax, o.coarse, o.precision = RELAX[relax], COARSE[coarse], PRECISION[precision]
     o.precond = PRECOND[precond]

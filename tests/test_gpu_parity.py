@@ -335,3 +335,21 @@ def test_tile_policy_changes_speed_only(pc):
     op = fem.Operator(prob)
     ref = propagator.sequential(op, propagator.CGSolver(op, 1e-14), t, F, psi0)
     assert rel(host(base[0]), ref) <= 1e-9
+
+
+def test_loose_coarse_cg_keeps_fixed_point():
+    """Coarse-level propagators solved to a loose CG tolerance change the corrections, not the fixed point."""
+    mg = _mg()
+    prob, t, F, psi0 = _random_problem(10, 64, beta=0.8, gamma=0.7, Mx=70, My=58, Kx=1.0, Ky=2.0)
+    op = fem.Operator(prob)
+    ref = propagator.sequential(op, propagator.CGSolver(op, 1e-14), t, F, psi0)
+    its = {}
+    for rc_coarse in (0.0, 1e-3):
+        with mg.Solver(prob.beta, prob.gamma, 1.0, 2.0, prob.Mx, prob.My, t, m=4, max_levels=3, coarse="opt",
+                       precond="fd-bf16", cg_rtol=1e-13, cg_rtol_coarse=rc_coarse, tol_abs=0.0, tol_rel=1e-12,
+                       max_iter=40) as s:
+            U, st, rc = s.solve(dev(F), dev(psi0))
+            assert rc == 0
+            assert rel(host(U), ref) <= 1e-10, rc_coarse
+            its[rc_coarse] = (st.iterations, st.cg_iterations)
+    assert its[1e-3][1] < its[0.0][1]
