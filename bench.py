@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "space-time DOF/s at 1e-8 rel. error vs FP64 sequential"
 FP64_PEAK_TFLOPS = 78.6          # MI355X dense FP64 (matrix and vector)
+FP32_PEAK_TFLOPS = 157.3         # MI355X dense FP32 (matrix)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_prop_apply64_fp64_vcycle_255_traffic.json")
 
@@ -113,7 +114,9 @@ def main():
     ap.add_argument("--precond", default="fd-bf16")
     ap.add_argument("--max-levels", type=int, default=3)
     ap.add_argument("--tile", default="auto", help="operator tile policy: auto | rule | 64 | 32")
-    ap.add_argument("--cg-rtol-coarse", type=float, default=0.0,
+    ap.add_argument("--precision", default="fp64", help="fp64 | mixed | mixed-coarse")
+    ap.add_argument("--inner-rtol", type=float, default=0.0, help="mixed precision: inner FP32 tolerance floor")
+    ap.add_argument("--cg-rtol-coarse", type=float, default=1e-3,
                     help="CG tolerance on the coarse levels (0: --cg-rtol)")
     ap.add_argument("--cg-adapt", type=float, default=0.0,
                     help="CG rtol of MGRIT iteration k = clamp(cg_adapt x relative residual, cg_rtol, 1e-4)")
@@ -163,7 +166,8 @@ def main():
     s = mgrit.Solver(*common, m=W["m"], max_levels=args.max_levels, coarse=args.coarse, cg_rtol=args.cg_rtol,
                      cg_maxit=100000,
                      tol_abs=0.0, tol_rel=args.tol_rel, max_iter=40, precond=args.precond,
-                     cg_rtol_adapt=args.cg_adapt, tile=args.tile, cg_rtol_coarse=args.cg_rtol_coarse)
+                     cg_rtol_adapt=args.cg_adapt, tile=args.tile, cg_rtol_coarse=args.cg_rtol_coarse,
+                     precision=args.precision, inner_rtol=args.inner_rtol)
     U = torch.empty((Nt + 1) * nx * ny, dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
         s.solve(Fd, pd, out=U)
@@ -174,7 +178,7 @@ def main():
         _, st, rc = s.solve(Fd, pd, out=U)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    prof = [s.profile_read(v) for v in (0, 1)]
+    prof = [s.profile_read(v) for v in (0, 1, 2, 3)]
     s.profile(False)
     levels = s.levels()
     err = None if Uref is None else float(torch.linalg.norm(U.view(Nt + 1, ny, nx) - Uref) / torch.linalg.norm(Uref))
@@ -195,24 +199,32 @@ def main():
             tr = json.load(fh)
         if tr.get("source_hash") == profiling.source_hash():
             traffic = tr.get("bytes_per_launch")
-    ms0, n0, sl0 = prof[0]
-    a0 = achieved(0)
-    roofline = {"bound": "mfma", "kernel": "k_prop_apply<64,2> (CG operator, FP64 MFMA, 64-point tiles)",
-                "achieved": a0, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": a0 / FP64_PEAK_TFLOPS if a0 else None, "traffic": traffic,
+    # dominant kernel: the operator variant with the most kernel time
+    names = ["k_prop_apply<64,2> (CG operator, FP64 MFMA, 64-point tiles)",
+             "k_prop_apply<32,2> (CG operator, FP64 MFMA, 32-point tiles)",
+             "k_apply32<64> (inner CG operator of mixed precision, FP32 MFMA, 64-point tiles)",
+             "k_apply32<32> (inner CG operator of mixed precision, FP32 MFMA, 32-point tiles)"]
+    peaks = [FP64_PEAK_TFLOPS, FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS, FP32_PEAK_TFLOPS]
+    v0 = max(range(4), key=lambda v: prof[v][0])
+    ms0, n0, sl0 = prof[v0]
+    a0 = achieved(v0)
+    roofline = {"bound": "mfma", "kernel": names[v0], "achieved": a0, "peak": peaks[v0], "unit": "TFLOP/s",
+                "frac": a0 / peaks[v0] if a0 else None, "traffic": traffic if v0 == 0 else None,
                 "avg_launch_ms": ms0 / n0 if n0 else None, "launches": n0,
                 "slice_applies_per_launch": sl0 / n0 if n0 else None, "flops_per_slice_apply": flops_per_apply,
-                "small_tile_kernel": {"kernel": "k_prop_apply<32,2>", "achieved_tflops": achieved(1),
-                                      "launches": prof[1][1],
-                                      "avg_launch_ms": prof[1][0] / prof[1][1] if prof[1][1] else None}}
+                "other_variants": [{"kernel": names[v].split(" (")[0], "achieved_tflops": achieved(v),
+                                    "launches": prof[v][1], "total_ms": prof[v][0],
+                                    "avg_launch_ms": prof[v][0] / prof[v][1] if prof[v][1] else None}
+                                   for v in range(4) if v != v0 and prof[v][1]]}
     out = {"metric": METRIC, "value": dof / per_step, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": per_step * 1e3, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f64+f32", "data": "synthetic",
            "config": {"workload": W["name"], "nx": nx, "ny": ny, "Nt": Nt, "beta": W["beta"], "gamma": W["gamma"],
                       "Kx": W["Kx"], "Ky": W["Ky"], "m": W["m"], "levels": levels, "relax": "FCF",
                       "coarse": args.coarse, "precond": args.precond, "cg_rtol": args.cg_rtol,
                       "tol_rel": args.tol_rel, "cg_rtol_adapt": args.cg_adapt, "tile": args.tile,
-                      "cg_rtol_coarse": args.cg_rtol_coarse,
+                      "cg_rtol_coarse": args.cg_rtol_coarse, "precision": args.precision,
+                      "inner_rtol": args.inner_rtol, "refinements_per_solve": st.refinements,
                       "mgrit_iterations": st.iterations, "phi_per_solve": st.phi_applications,
                       "cg_iterations_per_solve": st.cg_iterations, "rel_l2_err_vs_fp64_sequential": err,
                       "sequential_dof_per_s": dof / seq_s if seq_s else None, "sequential_rel_l2_err": seq_err,

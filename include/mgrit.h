@@ -61,6 +61,16 @@ extern "C" {
 #define MGRIT_COARSE_OPT  3
 
 #define MGRIT_PREC_FP64   0   /* every operator application in FP64 (FP64 MFMA)        */
+/* MIXED: each propagator solve by iterative refinement.  The right-hand side,
+ * the iterate and its residual r = b - B x stay FP64 and the stop test is the
+ * FP64 one (||r|| <= rtol ||b||); each refinement step solves B d = r / ||r||
+ * by PCG in FP32 (operator on the FP32 matrix cores, FP32 vectors, FP64
+ * reductions) to the relative tolerance max(rtol ||b|| / ||r||, inner_rtol).
+ * The solution is the FP64 one to the CG tolerance.  MIXED_COARSE: FP64 on
+ * level 0 (and in sequential stepping), MIXED on the coarse levels.  Both take
+ * precond NONE or FD_BF16. */
+#define MGRIT_PREC_MIXED        1
+#define MGRIT_PREC_MIXED_COARSE 2
 
 /* Preconditioner of the spatial CG solves (Section 3.2 uses none).  FD: exact
  * inverse of the tensor-product (bilinear-element) discretisation of the same
@@ -115,6 +125,7 @@ typedef struct {
                             /* corrections only; the fixed point is set by level 0, so    */
                             /* this changes the MGRIT iteration count, not the solution); */
                             /* 0: cg_rtol                                                  */
+    double inner_rtol;      /* mixed precision: floor of the inner FP32 tolerance (0: 1e-5) */
 } mgrit_options;
 
 typedef struct {
@@ -124,6 +135,7 @@ typedef struct {
     long long phi_applications; /* propagator applications (one per slice)              */
     long long cg_iterations;    /* CG iterations summed over all slices                 */
     double residual_history[64];/* level-0 residual norm per iteration (first 64)       */
+    long long refinements;      /* mixed precision: refinement steps summed over slices */
 } mgrit_stats;
 
 typedef struct mgrit_handle mgrit_handle;
@@ -131,7 +143,7 @@ typedef struct mgrit_handle mgrit_handle;
 /* Fill `opt` with defaults: m = 8, max_levels = 30, FCF, CN, FP64, max_iter = 100,
  * tol_abs = 1e-9, tol_rel = 0, cg_rtol = 1e-9 (the paper's tolerances, Section 3.2),
  * cg_maxit = 10000, precond = NONE, cg_rtol_adapt = 0, warm_start = 1,
- * divergence_factor = 0, tile_policy = AUTO, cg_rtol_coarse = 0. */
+ * divergence_factor = 0, tile_policy = AUTO, cg_rtol_coarse = 0, inner_rtol = 0. */
 void mgrit_default_options(mgrit_options* opt);
 
 /* Validate the problem, evaluate the Toeplitz generating sequences of Section 2
@@ -220,8 +232,9 @@ int mgrit_fd_eigen(double rho, int n, double h, double K, double* V, double* lam
  * brackets every launch of the CG operator kernel (q = (M_h + theta A_h) p, the
  * dominant kernel); enabling resets the counters.  mgrit_profile_read returns,
  * for the 64-point (variant 0) or 32-point (variant 1) tile version of that
- * kernel, the summed kernel time in ms, the number of launches and the number
- * of slice applications they performed (the sum of CG iterations over slices). */
+ * kernel, or of its FP32 version in mixed precision (variants 2 and 3), the
+ * summed kernel time in ms, the number of launches and the number of slice
+ * applications they performed (the sum of CG iterations over slices). */
 int mgrit_profile_enable(mgrit_handle* h, int on);
 int mgrit_profile_read(const mgrit_handle* h, int variant, double* apply_ms, long long* launches,
                        long long* slice_applies);

@@ -32,6 +32,33 @@
 namespace {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// Matrix-core step of the operator tiles per element type: FP64
+// v_mfma_f64_16x16x4f64, or FP32 v_mfma_f32_16x16x4f32 for the inner solves
+// of mixed precision.  Both take A[i][k] in lane i + 16 k and B[k][j] in lane
+// j + 16 k; accumulator element r of lane l holds D[row(l/16, r)][l % 16] with
+// row = l/16 + 4 r (FP64) or 4 (l/16) + r (FP32).
+template <typename T>
+struct MF;
+template <>
+struct MF<double> {
+    typedef dbl4 V;
+    typedef Seqs S;
+    static __device__ __forceinline__ V mma(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+};
+template <>
+struct MF<float> {
+    typedef flt4 V;
+    typedef Seqs32 S;
+    static __device__ __forceinline__ V mma(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
 
 constexpr int KC = MGRIT_KC;         // contraction chunk
 constexpr int NT = 256;              // threads per workgroup
@@ -102,10 +129,12 @@ __device__ __forceinline__ double slice_sum(const double* partial, int pmax, int
 
 // out = add + sign (M v + theta A v) on one TT x TT tile; with dot_mode the
 // dot products of its 32 x 32 quadrants go to dot_out[32-tile index].
-template <int TT>
-__device__ void apply_tile(const Geom& g, const Seqs& sq, const double* __restrict__ v, double* __restrict__ out,
-                           const double* __restrict__ add, double theta, double sign, int dot_mode, int tile,
-                           double* lds, double* red, double* dot_out) {
+template <int TT, typename T>
+__device__ void apply_tile(const Geom& g, const typename MF<T>::S& sq, const T* __restrict__ v, T* __restrict__ out,
+                           const T* __restrict__ add, double theta_d, double sign_d, int dot_mode, int tile, T* lds,
+                           double* red, double* dot_out) {
+    typedef typename MF<T>::V V;
+    const T theta = (T)theta_d, sign = (T)sign_d;
     typedef TC<TT> C;
     constexpr int FR = C::FR;
     const int nx = g.nx, ny = g.ny;
@@ -117,23 +146,23 @@ __device__ void apply_tile(const Geom& g, const Seqs& sq, const double* __restri
     const int lr = lane & 15, lk = lane >> 4;
     const int wi = wave & 1, wj = wave >> 1;
 
-    dbl4 acc[FR][FR];
+    V acc[FR][FR];
 #pragma unroll
     for (int a = 0; a < FR; ++a)
 #pragma unroll
-        for (int b = 0; b < FR; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < FR; ++b) acc[a][b] = V{0, 0, 0, 0};
 
-    double* strip = lds;
-    double* w0 = lds + C::STRIP;
-    double* w1 = w0 + C::WIN;
-    double* w2 = w1 + C::WIN;
+    T* strip = lds;
+    T* w0 = lds + C::STRIP;
+    T* w1 = w0 + C::WIN;
+    T* w2 = w1 + C::WIN;
 
     // ---- x-direction: contraction over x with the A_x factors ----
     for (int k0 = 0; k0 < nx; k0 += KC) {
         for (int idx = tid; idx < C::HALO * KC; idx += NT) {
             const int jj = idx / KC, kk = idx - jj * KC;
             const int k = k0 + kk, j = j0 - 1 + jj;
-            strip[jj * C::SXS + kk] = (k < nx && j >= 0 && j < ny) ? v[(long long)j * nx + k] : 0.0;
+            strip[jj * C::SXS + kk] = (k < nx && j >= 0 && j < ny) ? v[(long long)j * nx + k] : T(0);
         }
         const int dbase = k0 - i0 - (TT - 1);
         for (int q = tid; q < C::WIN; q += NT) {
@@ -146,7 +175,7 @@ __device__ void apply_tile(const Geom& g, const Seqs& sq, const double* __restri
 #pragma unroll
         for (int ks = 0; ks < KC; ks += 4) {
             const int kk = ks + lk;
-            double a0[FR], a1[FR], a2[FR], b0[FR], b1[FR], b2[FR];
+            T a0[FR], a1[FR], a2[FR], b0[FR], b1[FR], b2[FR];
 #pragma unroll
             for (int f = 0; f < FR; ++f) {
                 const int il = wi * C::WR + f * 16 + lr;
@@ -163,9 +192,9 @@ __device__ void apply_tile(const Geom& g, const Seqs& sq, const double* __restri
             for (int fi = 0; fi < FR; ++fi)
 #pragma unroll
                 for (int fj = 0; fj < FR; ++fj) {
-                    acc[fi][fj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[fi], b0[fj], acc[fi][fj], 0, 0, 0);
-                    acc[fi][fj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[fi], b1[fj], acc[fi][fj], 0, 0, 0);
-                    acc[fi][fj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[fi], b2[fj], acc[fi][fj], 0, 0, 0);
+                    acc[fi][fj] = MF<T>::mma(a0[fi], b0[fj], acc[fi][fj]);
+                    acc[fi][fj] = MF<T>::mma(a1[fi], b1[fj], acc[fi][fj]);
+                    acc[fi][fj] = MF<T>::mma(a2[fi], b2[fj], acc[fi][fj]);
                 }
         }
         __syncthreads();
@@ -176,7 +205,7 @@ __device__ void apply_tile(const Geom& g, const Seqs& sq, const double* __restri
         for (int idx = tid; idx < KC * C::HALO; idx += NT) {
             const int kk = idx / C::HALO, ii = idx - kk * C::HALO;
             const int k = k0 + kk, i = i0 - 1 + ii;
-            strip[kk * C::SYS + ii] = (k < ny && i >= 0 && i < nx) ? v[(long long)k * nx + i] : 0.0;
+            strip[kk * C::SYS + ii] = (k < ny && i >= 0 && i < nx) ? v[(long long)k * nx + i] : T(0);
         }
         const int ebase = j0 - k0 - (KC - 1);
         for (int q = tid; q < C::WIN; q += NT) {
@@ -189,7 +218,7 @@ __device__ void apply_tile(const Geom& g, const Seqs& sq, const double* __restri
 #pragma unroll
         for (int ks = 0; ks < KC; ks += 4) {
             const int kk = ks + lk;
-            double a0[FR], a1[FR], a2[FR], b0[FR], b1[FR], b2[FR];
+            T a0[FR], a1[FR], a2[FR], b0[FR], b1[FR], b2[FR];
 #pragma unroll
             for (int f = 0; f < FR; ++f) {
                 const int il = wi * C::WR + f * 16 + lr;
@@ -206,23 +235,23 @@ __device__ void apply_tile(const Geom& g, const Seqs& sq, const double* __restri
             for (int fi = 0; fi < FR; ++fi)
 #pragma unroll
                 for (int fj = 0; fj < FR; ++fj) {
-                    acc[fi][fj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[fi], b0[fj], acc[fi][fj], 0, 0, 0);
-                    acc[fi][fj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[fi], b1[fj], acc[fi][fj], 0, 0, 0);
-                    acc[fi][fj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[fi], b2[fj], acc[fi][fj], 0, 0, 0);
+                    acc[fi][fj] = MF<T>::mma(a0[fi], b0[fj], acc[fi][fj]);
+                    acc[fi][fj] = MF<T>::mma(a1[fi], b1[fj], acc[fi][fj]);
+                    acc[fi][fj] = MF<T>::mma(a2[fi], b2[fj], acc[fi][fj]);
                 }
         }
         __syncthreads();
     }
 
     // ---- epilogue: stage A v through LDS, add the mass stencil ----
-    double* epi = lds;
+    T* epi = lds;
 #pragma unroll
     for (int fi = 0; fi < FR; ++fi)
 #pragma unroll
         for (int fj = 0; fj < FR; ++fj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int il = wi * C::WR + fi * 16 + lk + 4 * r;
+                const int il = wi * C::WR + fi * 16 + MF<T>::row(lk, r);
                 const int jl = wj * C::WR + fj * 16 + lr;
                 epi[jl * (TT + 1) + il] = acc[fi][fj][r];
             }
@@ -230,7 +259,7 @@ __device__ void apply_tile(const Geom& g, const Seqs& sq, const double* __restri
 
     // Per 32 x 32 quadrant (the partial-sum unit of both tile sizes, with the
     // same thread -> element order), so the sums do not depend on TT.
-    const double mass = g.mass;
+    const T mass = (T)g.mass;
 #pragma unroll
     for (int qd = 0; qd < (TT / 32) * (TT / 32); ++qd) {
         const int qx = qd % (TT / 32), qy = qd / (TT / 32);
@@ -242,20 +271,20 @@ __device__ void apply_tile(const Geom& g, const Seqs& sq, const double* __restri
             const int i = i0 + il, j = j0 + jl;
             if (i >= nx || j >= ny) continue;
             const long long o = (long long)j * nx + i;
-            const double c = v[o];
+            const T c = v[o];
             const bool hl = i > 0, hr = i + 1 < nx, hd = j > 0, hu = j + 1 < ny;
-            double m7 = 6.0 * c;
-            m7 += hl ? v[o - 1] : 0.0;
-            m7 += hr ? v[o + 1] : 0.0;
-            m7 += hd ? v[o - nx] : 0.0;
-            m7 += hu ? v[o + nx] : 0.0;
-            m7 += (hr && hu) ? v[o + nx + 1] : 0.0;
-            m7 += (hl && hd) ? v[o - nx - 1] : 0.0;
-            double val = sign * (mass * m7 + theta * epi[jl * (TT + 1) + il]);
+            T m7 = T(6) * c;
+            m7 += hl ? v[o - 1] : T(0);
+            m7 += hr ? v[o + 1] : T(0);
+            m7 += hd ? v[o - nx] : T(0);
+            m7 += hu ? v[o + nx] : T(0);
+            m7 += (hr && hu) ? v[o + nx + 1] : T(0);
+            m7 += (hl && hd) ? v[o - nx - 1] : T(0);
+            T val = sign * (mass * m7 + theta * epi[jl * (TT + 1) + il]);
             if (add) val += add[o];
             out[o] = val;
-            if (dot_mode == 1) dot += c * val;
-            else if (dot_mode == 2) dot += val * val;
+            if (dot_mode == 1) dot += (double)c * (double)val;
+            else if (dot_mode == 2) dot += (double)val * (double)val;
         }
         if (dot_mode) {
             dot = block_sum(dot, red);
@@ -280,7 +309,7 @@ __global__ __launch_bounds__(NT) void k_apply(Geom g, Seqs sq, const ApplyDesc* 
     __shared__ double red[4];
     const ApplyDesc d = desc[s];
     const double* addp = (addbase && d.add >= 0) ? addbase + d.add * g.stride : nullptr;
-    apply_tile<TT>(g, sq, vbase + d.v * g.stride, outbase + d.out * g.stride, addp, d.theta, sign, dot_mode, tile,
+    apply_tile<TT, double>(g, sq, vbase + d.v * g.stride, outbase + d.out * g.stride, addp, d.theta, sign, dot_mode, tile,
                    lds, red, dot_mode ? partial + (long long)s * g.pmax : nullptr);
 }
 
@@ -303,12 +332,12 @@ __global__ __launch_bounds__(NT) void k_prop_apply(Geom g, Seqs sq, const PropDe
     double* part = partial + (long long)s * g.pmax;
     if (MODE == 0) {
         const double* f = (fbase && d.f >= 0) ? fbase + d.f * g.stride : nullptr;
-        apply_tile<TT>(g, sq, ubase + d.u * g.stride, wsout + so, f, d.theta_rhs, 1.0, 2, tile, lds, red, part);
+        apply_tile<TT, double>(g, sq, ubase + d.u * g.stride, wsout + so, f, d.theta_rhs, 1.0, 2, tile, lds, red, part);
     } else if (MODE == 1) {
-        apply_tile<TT>(g, sq, ubase + d.x * g.stride, wsout + so, wsin + so, d.theta_lhs, -1.0, 2, tile, lds, red,
+        apply_tile<TT, double>(g, sq, ubase + d.x * g.stride, wsout + so, wsin + so, d.theta_lhs, -1.0, 2, tile, lds, red,
                        part);
     } else {
-        apply_tile<TT>(g, sq, wsin + so, wsout + so, nullptr, d.theta_lhs, 1.0, 1, tile, lds, red, part);
+        apply_tile<TT, double>(g, sq, wsin + so, wsout + so, nullptr, d.theta_lhs, 1.0, 1, tile, lds, red, part);
     }
 }
 
@@ -317,6 +346,145 @@ __device__ __forceinline__ void chunk_range(const Geom& g, int c, long long& lo,
     lo = (long long)c * CH;
     hi = lo + CH;
     if (hi > g.stride) hi = g.stride;
+}
+
+// ---- mixed precision: FP32 inner solves of an iterative refinement ----
+// The outer loop keeps b, x and r = b - B x in FP64; each step solves
+// B d = r / ||r|| by PCG in FP32 (operator on the FP32 matrix cores, vectors
+// in FP32, every reduction accumulated in FP64) and sets x += ||r|| d.
+
+// q32 = M p32 + theta_lhs A p32 on active slices, partial p.q.
+template <int TT>
+__global__ __launch_bounds__(NT) void k_apply32(Geom g, Seqs32 sq, const PropDesc* __restrict__ desc, int S,
+                                                const float* pws, float* qws, double* partial, const int* active) {
+    const int tv = TT == 64 ? 0 : 1;
+    int s, tile;
+    decode_block(g.ntiles[tv], S, s, tile);
+    if (s < 0) return;
+    if (active && !active[s]) return;
+    __shared__ float lds[TC<TT>::LDS];
+    __shared__ double red[4];
+    const long long so = (long long)s * g.stride;
+    apply_tile<TT, float>(g, sq, pws + so, qws + so, nullptr, desc[s].theta_lhs, 1.0, 1, tile, lds, red,
+                          partial + (long long)s * g.pmax);
+}
+
+// Start of a refinement step from the FP64 residual (np partials of ||b||^2
+// and ||r||^2 per slice): outer flag ||r|| > rtol ||b||, scale ||r||, inner
+// tolerance eta^2 = max(rtol^2 ||b||^2 / ||r||^2, eta_min^2), r32 = r / ||r||,
+// d32 = 0 and, when p32 is given (no preconditioner), p32 = r32 with partial
+// r32.r32.  On the first step x = 0 where b = 0 and the counts restart.
+__global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restrict__ desc, int S, double* xbase,
+                                                 const double* rws, const double* partial_bb,
+                                                 const double* partial_rr, int np, double rtol2, double eta_min2,
+                                                 int first, double* bb, double* scale, double* eta2, int* oact,
+                                                 int* iact, int* iters, float* r32, float* d32, float* p32,
+                                                 double* partial_rr32) {
+    int s, c;
+    decode_block(g.nchunk, S, s, c);
+    if (s < 0) return;
+    __shared__ double red[4];
+    const double b2 = slice_sum(partial_bb, g.pmax, s, np);
+    const double r2 = slice_sum(partial_rr, g.pmax, s, np);
+    const bool zero = !(b2 > 0.0);
+    const bool active = !zero && r2 > rtol2 * b2;
+    const long long so = (long long)s * g.stride;
+    long long lo, hi;
+    chunk_range(g, c, lo, hi);
+    if (first && zero) {
+        double* x = xbase + desc[s].x * g.stride;
+        for (long long e = lo + threadIdx.x; e < hi; e += NT) x[e] = 0.0;
+    }
+    if (active) {
+        const double inv = 1.0 / sqrt(r2);
+        const double* r = rws + so;
+        double acc = 0.0;
+        for (long long e = lo + threadIdx.x; e < hi; e += NT) {
+            const float rv = (float)(r[e] * inv);
+            r32[so + e] = rv;
+            d32[so + e] = 0.0f;
+            if (p32) p32[so + e] = rv;
+            acc += (double)rv * (double)rv;
+        }
+        if (p32) {
+            acc = block_sum(acc, red);
+            if (threadIdx.x == 0) partial_rr32[(long long)s * g.pmax + c] = acc;
+        }
+    }
+    if (c == 0 && threadIdx.x == 0) {
+        bb[s] = b2;
+        oact[s] = active ? 1 : 0;
+        iact[s] = active ? 1 : 0;
+        scale[s] = active ? sqrt(r2) : 0.0;
+        eta2[s] = active ? fmax(rtol2 * b2 / r2, eta_min2) : 0.0;
+        if (first) iters[s] = 0;
+    }
+}
+
+// alpha = rho / p.q; d32 += alpha p32, r32 -= alpha q32; partial r32.r32.
+__global__ __launch_bounds__(NT) void k_mx_update(Geom g, int S, float* d32, float* r32, const float* p32,
+                                                  const float* q32, const double* partial_rho, int nrho,
+                                                  const double* partial_pq, int npq, double* partial_rr_new,
+                                                  const int* active) {
+    int s, c;
+    decode_block(g.nchunk, S, s, c);
+    if (s < 0 || !active[s]) return;
+    __shared__ double red[4];
+    const float alpha = (float)(slice_sum(partial_rho, g.pmax, s, nrho) / slice_sum(partial_pq, g.pmax, s, npq));
+    const long long so = (long long)s * g.stride;
+    long long lo, hi;
+    chunk_range(g, c, lo, hi);
+    double acc = 0.0;
+    for (long long e = so + lo + threadIdx.x; e < so + hi; e += NT) {
+        d32[e] += alpha * p32[e];
+        const float rn = r32[e] - alpha * q32[e];
+        r32[e] = rn;
+        acc += (double)rn * (double)rn;
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partial_rr_new[(long long)s * g.pmax + c] = acc;
+}
+
+// p32 = z32 + (rho_new / rho) p32; the inner solve of slice s stops when
+// ||r32||^2 <= eta2[s] (its right-hand side has unit norm) or at maxit
+// iterations in all (counted over the refinement steps).
+__global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float* z32, float* p32,
+                                                     const double* partial_rho, int nrho,
+                                                     const double* partial_rho_new, int nrho_new,
+                                                     const double* partial_rr_new, const double* eta2, int maxit,
+                                                     const int* active, int* active_next, int* iters) {
+    int s, c;
+    decode_block(g.nchunk, S, s, c);
+    if (s < 0) return;
+    if (!active[s]) {
+        if (c == 0 && threadIdx.x == 0) active_next[s] = 0;
+        return;
+    }
+    const float beta = (float)(slice_sum(partial_rho_new, g.pmax, s, nrho_new) / slice_sum(partial_rho, g.pmax, s, nrho));
+    const long long so = (long long)s * g.stride;
+    long long lo, hi;
+    chunk_range(g, c, lo, hi);
+    for (long long e = so + lo + threadIdx.x; e < so + hi; e += NT) p32[e] = z32[e] + beta * p32[e];
+    if (c == 0 && threadIdx.x == 0) {
+        const double rrn = slice_sum(partial_rr_new, g.pmax, s, g.nchunk);
+        const int it = iters[s] + 1;
+        iters[s] = it;
+        active_next[s] = (rrn > eta2[s] && it < maxit) ? 1 : 0;
+    }
+}
+
+// x += ||r|| d32 on slices whose refinement step ran.
+__global__ __launch_bounds__(NT) void k_mx_refine(Geom g, const PropDesc* __restrict__ desc, int S, double* xbase,
+                                                  const float* d32, const double* scale, const int* oact) {
+    int s, c;
+    decode_block(g.nchunk, S, s, c);
+    if (s < 0 || !oact[s]) return;
+    double* x = xbase + desc[s].x * g.stride;
+    const float* d = d32 + (long long)s * g.stride;
+    const double a = scale[s];
+    long long lo, hi;
+    chunk_range(g, c, lo, hi);
+    for (long long e = lo + threadIdx.x; e < hi; e += NT) x[e] += a * (double)d[e];
 }
 
 __global__ __launch_bounds__(NT) void k_cg_init_x(Geom g, const PropDesc* __restrict__ desc, int S,
@@ -542,8 +710,9 @@ __global__ __launch_bounds__(NT) void k_fd_gemm(Geom g, int S, const double* __r
 // Operands are zero-padded to npx x npy (multiples of 64) so the products need
 // no bounds checks except on the FP64 input r and the FP64 output z.
 // LEFT:  Y[s] = A X[s], A[i][k] row-major (ld npx)        RIGHT: Y[s] = X[s] B, B^T[j][k] row-major (ld npy)
-// IN 0: X = FP64 r [ny][nx];  IN 1: X = BF16 padded [npy][npx]
-// EPI 0: Y BF16 padded; 1: scaled by 1 / (1 + theta (lx + ly)), BF16 padded; 2: Y = FP64 z [ny][nx] + r.z
+// IN 0: X = r [ny][nx] (RT = FP64, or FP32 in the inner solves of mixed precision);  IN 1: X = BF16 padded
+// EPI 0: Y BF16 padded; 1: scaled by 1 / (1 + theta (lx + ly)), BF16 padded; 2: Y = z [ny][nx] (RT) + r.z,
+//        also copied to ycopy when given
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 constexpr int BK = 64;            // k-chunk of the BF16 products
@@ -554,12 +723,12 @@ union Pack8 {
     __bf16 h[8];
 };
 
-template <bool LEFT, int IN, int EPI>
+template <bool LEFT, int IN, int EPI, typename RT>
 __global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __restrict__ mat,
                                                  const void* __restrict__ xin, void* __restrict__ yout,
                                                  const PropDesc* __restrict__ desc, const float* __restrict__ lx,
-                                                 const float* __restrict__ ly, const double* __restrict__ rws,
-                                                 double* partial, const int* active) {
+                                                 const float* __restrict__ ly, const RT* __restrict__ rws,
+                                                 RT* __restrict__ ycopy, double* partial, const int* active) {
     int s, tile;
     decode_block(g.ntiles[0], S, s, tile);
     if (s < 0) return;
@@ -578,7 +747,7 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __
     const int lr = lane & 15, lg = lane >> 4;
     const int wi = wave & 1, wj = wave >> 1;
     const long long sob = (long long)s * npx * npy;          // BF16 padded slice offset
-    const long long so = (long long)s * g.stride;            // FP64 slice offset
+    const long long so = (long long)s * g.stride;            // slice offset of r and z
     const int K = LEFT ? npx : npy;
 
     flt4 acc[2][2];
@@ -604,12 +773,12 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __
         }
         // B tile ([j][k])
         if (LEFT && IN == 0) {
-            const double* X = rws + so;
+            const RT* X = rws + so;
             for (int idx = tid; idx < 64 * 64; idx += NT) {
                 const int jj = idx >> 6, kk = idx & 63;
                 const int k = k0 + kk, j = j0 + jj;
-                const double v = (k < nx && j < ny) ? X[(long long)j * nx + k] : 0.0;
-                Bs[jj * BLD + kk] = (__bf16)(float)v;
+                const float v = (k < nx && j < ny) ? (float)X[(long long)j * nx + k] : 0.0f;
+                Bs[jj * BLD + kk] = (__bf16)v;
             }
         } else {
             for (int idx = tid; idx < 64 * 8; idx += NT) {
@@ -663,8 +832,9 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __
             if (EPI == 2) {
                 if (i < nx && j < ny) {
                     const long long o = (long long)j * nx + i;
-                    ((double*)yout)[so + o] = (double)v;
-                    dot += (double)v * rws[so + o];
+                    ((RT*)yout)[so + o] = (RT)v;
+                    if (ycopy) ycopy[so + o] = (RT)v;
+                    dot += (double)v * (double)rws[so + o];
                 }
             } else {
                 ((__bf16*)yout)[sob + (long long)j * npx + i] = (__bf16)v;
@@ -836,24 +1006,95 @@ int launch_fd_apply(const Geom* g, const FdMats* fd, int tv, const PropDesc* des
 }
 
 
-int launch_fdb_apply(const Geom* g, const FdMatsB* fd, const PropDesc* desc, int S, const double* rws, double* zws,
-                     void* t1, void* t2, double* partial_rz, const int* active, void* stream) {
-    if (S <= 0) return 0;
+}  // extern "C"
+
+namespace {
+
+// t1 = Vx^T r ; t2 = (t1 Vy) / (1 + theta (lx + ly)) ; t1 = Vx t2 ; z = t1 Vy^T (+ r.z)
+template <typename RT>
+void fdb_chain(const Geom* g, const FdMatsB* fd, const PropDesc* desc, int S, const RT* rws, RT* zws, RT* zcopy,
+               void* t1, void* t2, double* partial_rz, const int* active, hipStream_t st) {
     const dim3 grid(grid_blocks(g->ntiles[0], S)), blk(NT);
-    hipStream_t st = (hipStream_t)stream;
-    // t1 = Vx^T r ; t2 = (t1 Vy) / (1 + theta (lx + ly)) ; t1 = Vx t2 ; z = t1 Vy^T (+ r.z)
     const __bf16* VxT = (const __bf16*)fd->VxT;
     const __bf16* Vx = (const __bf16*)fd->Vx;
     const __bf16* VyT = (const __bf16*)fd->VyT;
     const __bf16* Vy = (const __bf16*)fd->Vy;
-    hipLaunchKernelGGL((k_fdb_gemm<true, 0, 0>), grid, blk, 0, st, *g, S, VxT, (const void*)nullptr, t1, desc, fd->lx,
-                       fd->ly, rws, (double*)nullptr, active);
-    hipLaunchKernelGGL((k_fdb_gemm<false, 1, 1>), grid, blk, 0, st, *g, S, VyT, (const void*)t1, t2, desc, fd->lx,
-                       fd->ly, rws, (double*)nullptr, active);
-    hipLaunchKernelGGL((k_fdb_gemm<true, 1, 0>), grid, blk, 0, st, *g, S, Vx, (const void*)t2, t1, desc, fd->lx,
-                       fd->ly, rws, (double*)nullptr, active);
-    hipLaunchKernelGGL((k_fdb_gemm<false, 1, 2>), grid, blk, 0, st, *g, S, Vy, (const void*)t1, (void*)zws, desc,
-                       fd->lx, fd->ly, rws, partial_rz, active);
+    hipLaunchKernelGGL((k_fdb_gemm<true, 0, 0, RT>), grid, blk, 0, st, *g, S, VxT, (const void*)nullptr, t1, desc,
+                       fd->lx, fd->ly, rws, (RT*)nullptr, (double*)nullptr, active);
+    hipLaunchKernelGGL((k_fdb_gemm<false, 1, 1, RT>), grid, blk, 0, st, *g, S, VyT, (const void*)t1, t2, desc,
+                       fd->lx, fd->ly, rws, (RT*)nullptr, (double*)nullptr, active);
+    hipLaunchKernelGGL((k_fdb_gemm<true, 1, 0, RT>), grid, blk, 0, st, *g, S, Vx, (const void*)t2, t1, desc,
+                       fd->lx, fd->ly, rws, (RT*)nullptr, (double*)nullptr, active);
+    hipLaunchKernelGGL((k_fdb_gemm<false, 1, 2, RT>), grid, blk, 0, st, *g, S, Vy, (const void*)t1, (void*)zws,
+                       desc, fd->lx, fd->ly, rws, zcopy, partial_rz, active);
+}
+
+}  // namespace
+
+extern "C" {
+
+int launch_fdb_apply(const Geom* g, const FdMatsB* fd, const PropDesc* desc, int S, const double* rws, double* zws,
+                     void* t1, void* t2, double* partial_rz, const int* active, void* stream) {
+    if (S <= 0) return 0;
+    fdb_chain<double>(g, fd, desc, S, rws, zws, nullptr, t1, t2, partial_rz, active, (hipStream_t)stream);
+    return (int)hipGetLastError();
+}
+
+int launch_fdb_apply32(const Geom* g, const FdMatsB* fd, const PropDesc* desc, int S, const float* r32, float* z32,
+                       float* zcopy, void* t1, void* t2, double* partial_rz, const int* active, void* stream) {
+    if (S <= 0) return 0;
+    fdb_chain<float>(g, fd, desc, S, r32, z32, zcopy, t1, t2, partial_rz, active, (hipStream_t)stream);
+    return (int)hipGetLastError();
+}
+
+int launch_apply32(const Geom* g, const Seqs32* sq, int tv, const PropDesc* desc, int S, const float* p32,
+                   float* q32, double* partial_pq, const int* active, void* stream) {
+    if (S <= 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    if (tv == 0)
+        hipLaunchKernelGGL(k_apply32<64>, dim3(grid_blocks(g->ntiles[0], S)), dim3(NT), 0, st, *g, *sq, desc, S, p32,
+                           q32, partial_pq, active);
+    else
+        hipLaunchKernelGGL(k_apply32<32>, dim3(grid_blocks(g->ntiles[1], S)), dim3(NT), 0, st, *g, *sq, desc, S, p32,
+                           q32, partial_pq, active);
+    return (int)hipGetLastError();
+}
+
+int launch_mx_begin(const Geom* g, const PropDesc* desc, int S, double* xbase, const double* rws,
+                    const double* partial_bb, const double* partial_rr, int np, double rtol2, double eta_min2,
+                    int first, double* bb, double* scale, double* eta2, int* oact, int* iact, int* iters, float* r32,
+                    float* d32, float* p32, double* partial_rr32, void* stream) {
+    if (S <= 0) return 0;
+    hipLaunchKernelGGL(k_mx_begin, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, desc, S,
+                       xbase, rws, partial_bb, partial_rr, np, rtol2, eta_min2, first, bb, scale, eta2, oact, iact,
+                       iters, r32, d32, p32, partial_rr32);
+    return (int)hipGetLastError();
+}
+
+int launch_mx_update(const Geom* g, int S, float* d32, float* r32, const float* p32, const float* q32,
+                     const double* partial_rho, int nrho, const double* partial_pq, int npq, double* partial_rr_new,
+                     const int* active, void* stream) {
+    if (S <= 0) return 0;
+    hipLaunchKernelGGL(k_mx_update, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, S, d32,
+                       r32, p32, q32, partial_rho, nrho, partial_pq, npq, partial_rr_new, active);
+    return (int)hipGetLastError();
+}
+
+int launch_mx_direction(const Geom* g, int S, const float* z32, float* p32, const double* partial_rho, int nrho,
+                        const double* partial_rho_new, int nrho_new, const double* partial_rr_new, const double* eta2,
+                        int maxit, const int* active, int* active_next, int* iters, void* stream) {
+    if (S <= 0) return 0;
+    hipLaunchKernelGGL(k_mx_direction, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, S,
+                       z32, p32, partial_rho, nrho, partial_rho_new, nrho_new, partial_rr_new, eta2, maxit, active,
+                       active_next, iters);
+    return (int)hipGetLastError();
+}
+
+int launch_mx_refine(const Geom* g, const PropDesc* desc, int S, double* xbase, const float* d32,
+                     const double* scale, const int* oact, void* stream) {
+    if (S <= 0) return 0;
+    hipLaunchKernelGGL(k_mx_refine, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, desc, S,
+                       xbase, d32, scale, oact);
     return (int)hipGetLastError();
 }
 

@@ -62,6 +62,7 @@ struct Pass {
     std::vector<PropDesc> h;
     PropDesc* d = nullptr;
     mutable int last_iters = 0;   // CG iterations the slowest slice needed last time (launch schedule)
+    mutable int last_inner = 0;   // the same for the first inner solve of mixed precision
 };
 
 struct Batch {
@@ -101,6 +102,8 @@ struct mgrit_handle {
     Geom geom;
     Seqs seqs;
     double* d_seq = nullptr;                 // T1x | A2x | T1y | A2y
+    float* d_seq32 = nullptr;                // FP32 copy (mixed precision)
+    Seqs32 seqs32{};
     std::vector<double> host_seq_x, host_seq_y;
     double cx = 0, cy = 0;
     std::vector<Level> lv;
@@ -114,6 +117,12 @@ struct mgrit_handle {
     double *pbb = nullptr, *prr[2] = {nullptr, nullptr}, *ppq = nullptr, *pnorm = nullptr;
     double* prz[2] = {nullptr, nullptr};
     double* bb = nullptr;
+    // mixed precision: FP32 inner workspace, per-slice scale, inner tolerance
+    // and outer flags, partials of the FP64 outer residual
+    float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
+    double *mx_scale = nullptr, *mx_eta2 = nullptr, *pout = nullptr;
+    int* mx_oact = nullptr;
+    long long refine_count = 0;             // refinement steps summed over slices
     int* act[2] = {nullptr, nullptr};
     int* iters = nullptr;
     int* h_act = nullptr;                    // pinned
@@ -125,14 +134,15 @@ struct mgrit_handle {
     double cur_rtol = 0.0;          // CG tolerance of the current MGRIT iteration
     int cur_level = 0;              // level of the passes being run
     std::map<int, int> tile_of;     // tile variant chosen per batch width (autotuned)
+    std::map<int, int> tile_of32;   // the same for the FP32 inner operator
     hipEvent_t tune_ev[5] = {};
     // instrumentation of the CG operator kernel
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;
     std::vector<int> prof_tv;                 // tile variant of each recorded event pair
     size_t prof_used = 0;
-    double prof_ms[2] = {0.0, 0.0};
-    long long prof_launches[2] = {0, 0}, prof_slices[2] = {0, 0};
+    double prof_ms[4] = {0.0, 0.0, 0.0, 0.0};                 // variants: FP64 64, 32; FP32 64, 32
+    long long prof_launches[4] = {0, 0, 0, 0}, prof_slices[4] = {0, 0, 0, 0};
     // caller arrays of the current solve (level 0)
     double* U0 = nullptr;
     const double* F0 = nullptr;
@@ -376,6 +386,15 @@ int build_sequences(mgrit_handle* h) {
     h->seqs.A2x = h->d_seq + lx;
     h->seqs.T1y = h->d_seq + 2 * lx;
     h->seqs.A2y = h->d_seq + 2 * lx + ly;
+    if (h->opt.precision != MGRIT_PREC_FP64) {
+        std::vector<float> b32(buf.begin(), buf.end());
+        CHK(dalloc(h, &h->d_seq32, b32.size()));
+        HIPCHK(hipMemcpy(h->d_seq32, b32.data(), b32.size() * sizeof(float), hipMemcpyHostToDevice));
+        h->seqs32.T1x = h->d_seq32;
+        h->seqs32.A2x = h->d_seq32 + lx;
+        h->seqs32.T1y = h->d_seq32 + 2 * lx;
+        h->seqs32.A2y = h->d_seq32 + 2 * lx + ly;
+    }
     return 0;
 }
 
@@ -488,6 +507,21 @@ int alloc_workspace(mgrit_handle* h, int S) {
     CHK(dalloc(h, &h->act[0], S));
     CHK(dalloc(h, &h->act[1], S));
     CHK(dalloc(h, &h->iters, S));
+    if (h->opt.precision != MGRIT_PREC_FP64) {
+        CHK(dalloc(h, &h->r32, S * st));
+        CHK(dalloc(h, &h->z32, S * st));
+        CHK(dalloc(h, &h->p32, S * st));
+        CHK(dalloc(h, &h->q32, S * st));
+        CHK(dalloc(h, &h->d32, S * st));
+        CHK(dalloc(h, &h->mx_scale, S));
+        CHK(dalloc(h, &h->mx_eta2, S));
+        CHK(dalloc(h, &h->mx_oact, S));
+        CHK(dalloc(h, &h->pout, S * nt));
+        if (!h->prz[0]) {
+            CHK(dalloc(h, &h->prz[0], S * nt));
+            CHK(dalloc(h, &h->prz[1], S * nt));
+        }
+    }
     HIPCHK(hipHostMalloc((void**)&h->h_act, S * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&h->h_iters, S * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&h->h_norm, S * nt * sizeof(double), hipHostMallocDefault));
@@ -522,9 +556,10 @@ int prof_drain(mgrit_handle* h) {
 // the batch fills the chip with such tiles.  AUTO: the first pass of each
 // batch width times the CG operator kernel in both variants on the pass's
 // right-hand sides (it writes q and its partials, recomputed before use) and
-// keeps the faster; without a pass to time on, the rule.  The iterates do not depend on the choice: every tiled
+// keeps the faster; without a pass to time on, the rule.  The FP32 operator
+// of mixed precision is timed on its own, on the scaled residuals.  The iterates do not depend on the choice: every tiled
 // kernel sums its dot products per 32 x 32 block in one fixed order.
-int tile_variant(mgrit_handle* h, const Pass* ps, int S, int* tv) {
+int tile_variant(mgrit_handle* h, const Pass* ps, int S, int* tv, bool fp32 = false) {
     const int rule = (long long)S * h->geom.ntiles[0] >= 512 ? 0 : 1;
     switch (h->opt.tile_policy) {
         case MGRIT_TILE_64: *tv = 0; return 0;
@@ -532,8 +567,9 @@ int tile_variant(mgrit_handle* h, const Pass* ps, int S, int* tv) {
         case MGRIT_TILE_RULE: *tv = rule; return 0;
         default: break;
     }
-    auto it = h->tile_of.find(S);
-    if (it != h->tile_of.end()) {
+    std::map<int, int>& cache = fp32 ? h->tile_of32 : h->tile_of;
+    auto it = cache.find(S);
+    if (it != cache.end()) {
         *tv = it->second;
         return 0;
     }
@@ -547,7 +583,11 @@ int tile_variant(mgrit_handle* h, const Pass* ps, int S, int* tv) {
     const int order[4] = {0, 1, 0, 1};                  // alternate to average out clocks
     HIPCHK(hipEventRecord(h->tune_ev[0], h->stream));
     for (int k = 0; k < 4; ++k) {
-        HIPCHK(launch_cg_apply(g, &h->seqs, order[k], ps->d, S, h->b, h->q, h->ppq, nullptr, (void*)h->stream));
+        if (fp32)
+            HIPCHK(launch_apply32(g, &h->seqs32, order[k], ps->d, S, h->r32, h->q32, h->ppq, nullptr,
+                                  (void*)h->stream));
+        else
+            HIPCHK(launch_cg_apply(g, &h->seqs, order[k], ps->d, S, h->b, h->q, h->ppq, nullptr, (void*)h->stream));
         HIPCHK(hipEventRecord(h->tune_ev[k + 1], h->stream));
     }
     HIPCHK(hipEventSynchronize(h->tune_ev[4]));
@@ -558,9 +598,12 @@ int tile_variant(mgrit_handle* h, const Pass* ps, int S, int* tv) {
         ms[order[k]] += t;
     }
     *tv = ms[0] <= ms[1] ? 0 : 1;
-    h->tile_of[S] = *tv;
+    cache[S] = *tv;
     return 0;
 }
+
+int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase, const double* fbase,
+                   const double* gbase, const double* x0base, int warm);
 
 // Batched CG solve of one pass (S <= Smax slices).
 int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase, const double* fbase,
@@ -568,6 +611,8 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     const int S = ps.S;
     if (S == 0) return 0;
     if (S > h->Smax) return fail(MGRIT_EINVAL, "batch of %d slices exceeds workspace (%d)", S, h->Smax);
+    if (h->opt.precision == MGRIT_PREC_MIXED || (h->opt.precision == MGRIT_PREC_MIXED_COARSE && h->cur_level > 0))
+        return run_pass_mixed(h, ps, ubase, xbase, fbase, gbase, x0base, warm);
     const Geom* g = &h->geom;
     void* st = (void*)h->stream;
     double rtol = h->cur_rtol > 0.0 ? h->cur_rtol : h->opt.cg_rtol;
@@ -637,6 +682,90 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     ps.last_iters = most;
     h->cg_count += its;
     if (h->prof_on) h->prof_slices[tv] += its;
+    h->phi_count += S;
+    return 0;
+}
+
+// The same solve by iterative refinement: b, x and the residual r = b - B x
+// in FP64; each step solves B d = r / ||r|| by PCG in FP32 (FP32 matrix-core
+// operator, BF16 preconditioner products, FP64 reductions) to the relative
+// tolerance max(rtol ||b|| / ||r||, inner_rtol) and sets x += ||r|| d, until
+// the FP64 residual meets ||r|| <= rtol ||b|| (the test of the FP64 solve).
+int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase, const double* fbase,
+                   const double* gbase, const double* x0base, int warm) {
+    const int S = ps.S;
+    const Geom* g = &h->geom;
+    void* st = (void*)h->stream;
+    double rtol = h->cur_rtol > 0.0 ? h->cur_rtol : h->opt.cg_rtol;
+    if (h->cur_level > 0 && h->opt.cg_rtol_coarse > 0.0) rtol = h->opt.cg_rtol_coarse;
+    const double rtol2 = rtol * rtol;
+    const double eta = h->opt.inner_rtol > 0.0 ? h->opt.inner_rtol : 1e-5;
+    const bool pc = h->opt.precond == MGRIT_PRECOND_FD_BF16;
+    const int nt = g->ntiles[1], nc = g->nchunk;
+    const int maxit = h->opt.cg_maxit;
+    int tv = 0, tv32 = -1;
+    CHK(tile_variant(h, nullptr, S, &tv));
+    HIPCHK(launch_rhs(g, &h->seqs, tv, ps.d, S, ubase, fbase, h->b, h->pbb, st));
+    CHK(tile_variant(h, &ps, S, &tv));
+    HIPCHK(launch_cg_init_x(g, ps.d, S, ubase, x0base, (x0base && warm && h->opt.warm_start) ? 1 : 0, xbase, st));
+    HIPCHK(launch_init_residual(g, &h->seqs, tv, ps.d, S, xbase, h->b, h->r, h->pout, st));
+    float* zws = pc ? h->z32 : h->r32;
+    double** prho = pc ? h->prz : h->prr;        // rho = r.z (r.r without preconditioner)
+    int steps = 0;
+    for (int outer = 0; outer < 32; ++outer) {
+        HIPCHK(launch_mx_begin(g, ps.d, S, xbase, h->r, h->pbb, h->pout, nt, rtol2, eta * eta, outer == 0 ? 1 : 0,
+                               h->bb, h->mx_scale, h->mx_eta2, h->mx_oact, h->act[0], h->iters, h->r32, h->d32,
+                               pc ? nullptr : h->p32, h->prr[0], st));
+        HIPCHK(hipMemcpyAsync(h->h_act, h->mx_oact, S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        int nact = 0;
+        for (int s = 0; s < S; ++s) nact += h->h_act[s] != 0;
+        if (nact == 0) break;
+        steps += nact;
+        if (tv32 < 0) CHK(tile_variant(h, &ps, S, &tv32, true));
+        if (pc)
+            HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, h->p32, h->tb1, h->tb2, h->prz[0],
+                                      h->act[0], st));
+        int cur = 0, it = 0;
+        int nrho = pc ? nt : nc;
+        const int nrho_next = pc ? nt : nc;
+        int chunk = (outer == 0 && ps.last_inner > 0) ? std::max(1, ps.last_inner - 1) : 6;
+        while (true) {
+            HIPCHK(hipMemcpyAsync(h->h_act, h->act[cur], S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+            if (h->prof_on) CHK(prof_drain(h));
+            bool any = false;
+            for (int s = 0; s < S; ++s) any |= h->h_act[s] != 0;
+            if (!any || it >= maxit) break;
+            for (int c = 0; c < chunk && it < maxit; ++c, ++it) {
+                const int nxt = cur ^ 1;
+                if (h->prof_on) CHK(prof_record(h, 2 + tv32));
+                HIPCHK(launch_apply32(g, &h->seqs32, tv32, ps.d, S, h->p32, h->q32, h->ppq, h->act[cur], st));
+                if (h->prof_on) CHK(prof_record(h, 2 + tv32));
+                HIPCHK(launch_mx_update(g, S, h->d32, h->r32, h->p32, h->q32, prho[cur], nrho, h->ppq, nt,
+                                        h->prr[nxt], h->act[cur], st));
+                if (pc)
+                    HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, nullptr, h->tb1, h->tb2,
+                                              h->prz[nxt], h->act[cur], st));
+                HIPCHK(launch_mx_direction(g, S, zws, h->p32, prho[cur], nrho, prho[nxt], nrho_next, h->prr[nxt],
+                                           h->mx_eta2, maxit, h->act[cur], h->act[nxt], h->iters, st));
+                cur = nxt;
+                nrho = nrho_next;
+            }
+            chunk = 2;
+        }
+        if (outer == 0) ps.last_inner = it;
+        HIPCHK(launch_mx_refine(g, ps.d, S, xbase, h->d32, h->mx_scale, h->mx_oact, st));
+        HIPCHK(launch_init_residual(g, &h->seqs, tv, ps.d, S, xbase, h->b, h->r, h->pout, st));
+    }
+    HIPCHK(launch_add_g(g, ps.d, S, xbase, gbase, st));
+    HIPCHK(hipMemcpyAsync(h->h_iters, h->iters, S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    long long its = 0;
+    for (int s = 0; s < S; ++s) its += h->h_iters[s];
+    h->cg_count += its;
+    h->refine_count += steps;
+    if (h->prof_on && tv32 >= 0) h->prof_slices[2 + tv32] += its;
     h->phi_count += S;
     return 0;
 }
@@ -783,6 +912,7 @@ void fill_stats(mgrit_handle* h, mgrit_stats* st, int iters, int conv, const std
     st->levels = (int)h->lv.size();
     st->phi_applications = h->phi_count;
     st->cg_iterations = h->cg_count;
+    st->refinements = h->refine_count;
     for (int i = 0; i < 64; ++i) st->residual_history[i] = i < (int)hist.size() ? hist[i] : 0.0;
 }
 
@@ -810,6 +940,7 @@ int begin_solve(mgrit_handle* h, Staging& sg, const double* F, const double* psi
     h->F0 = dF;
     h->cur_rtol = 0.0;
     h->phi_count = 0;
+    h->refine_count = 0;
     h->cg_count = 0;
     return 0;
 }
@@ -847,6 +978,7 @@ void mgrit_default_options(mgrit_options* o) {
     o->divergence_factor = 0.0;
     o->tile_policy = MGRIT_TILE_AUTO;
     o->cg_rtol_coarse = 0.0;
+    o->inner_rtol = 0.0;
 }
 
 const char* mgrit_last_error(void) { return g_err; }
@@ -872,7 +1004,11 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
         return fail(MGRIT_EINVAL, "unknown coarse propagator");
     if (o.coarse == MGRIT_COARSE_OPT && (o.m % 2))
         return fail(MGRIT_EINVAL, "the OPT coarse propagator needs an even coarsening factor");
-    if (o.precision != MGRIT_PREC_FP64) return fail(MGRIT_EINVAL, "unknown precision");
+    if (o.precision < MGRIT_PREC_FP64 || o.precision > MGRIT_PREC_MIXED_COARSE)
+        return fail(MGRIT_EINVAL, "unknown precision");
+    if (o.precision != MGRIT_PREC_FP64 && o.precond == MGRIT_PRECOND_FD)
+        return fail(MGRIT_EINVAL, "mixed precision takes precond NONE or FD_BF16");
+    if (!(o.inner_rtol >= 0.0 && o.inner_rtol < 1.0)) return fail(MGRIT_EINVAL, "bad inner_rtol");
     if (o.precond < MGRIT_PRECOND_NONE || o.precond > MGRIT_PRECOND_FD_BF16)
         return fail(MGRIT_EINVAL, "unknown preconditioner");
     if (!(o.cg_rtol_coarse >= 0.0 && o.cg_rtol_coarse < 1.0)) return fail(MGRIT_EINVAL, "bad cg_rtol_coarse");
@@ -1115,7 +1251,7 @@ int mgrit_profile_enable(mgrit_handle* h, int on) {
     HIPCHK(hipStreamSynchronize(h->stream));
     h->prof_on = on != 0;
     h->prof_used = 0;
-    for (int v = 0; v < 2; ++v) {
+    for (int v = 0; v < 4; ++v) {
         h->prof_ms[v] = 0.0;
         h->prof_launches[v] = 0;
         h->prof_slices[v] = 0;
@@ -1126,7 +1262,7 @@ int mgrit_profile_enable(mgrit_handle* h, int on) {
 int mgrit_profile_read(const mgrit_handle* h, int variant, double* apply_ms, long long* launches,
                        long long* slice_applies) {
     if (!h) return fail(MGRIT_EINVAL, "NULL handle");
-    if (variant < 0 || variant > 1) return fail(MGRIT_EINVAL, "variant must be 0 or 1");
+    if (variant < 0 || variant > 3) return fail(MGRIT_EINVAL, "variant must be 0..3");
     if (apply_ms) *apply_ms = h->prof_ms[variant];
     if (launches) *launches = h->prof_launches[variant];
     if (slice_applies) *slice_applies = h->prof_slices[variant];
@@ -1166,6 +1302,11 @@ int mgrit_footprint(const mgrit_problem* p, const mgrit_options* o, int mem, siz
     if (pc) d += 2 * nx * nx + 2 * ny * ny + nx + ny;
     if (o->precond == MGRIT_PRECOND_FD_BF16) b += 4 * npx * npx + 4 * npy * npy + 4 * (npx + npy) + 4 * smax * npx * npy;
     if (mem == MGRIT_MEM_HOST) d += (2.0 * p->Nt + 2) * st;
+    if (o->precision != MGRIT_PREC_FP64) {
+        b += 4.0 * (2 * (npx + 96) + 1) * 2 + 4.0 * (2 * (npy + 96) + 1) * 2;          // FP32 sequences
+        b += 4.0 * 5 * smax * st + 20.0 * smax;                                        // FP32 workspace, flags
+        d += smax * pmax * (pc ? 1 : 3);                                                // partials
+    }
     const double total = 8 * d + b + desc + smax * 12;
     *bytes = (size_t)(total * 1.02) + (size_t)64 * 4096;
     return MGRIT_OK;

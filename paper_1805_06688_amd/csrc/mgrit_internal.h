@@ -64,6 +64,14 @@ typedef struct {
     const double* A2y;
 } Seqs;
 
+// FP32 roundings of the same sequences (inner solves of mixed precision).
+typedef struct {
+    const float* T1x;
+    const float* A2x;
+    const float* T1y;
+    const float* A2y;
+} Seqs32;
+
 // Device matrices of the fast-diagonalisation preconditioner (row-major):
 // Vx[k][i] = component k of eigenvector i (x), VxT its transpose, likewise y;
 // lx, ly the generalised eigenvalues.
@@ -98,9 +106,9 @@ int mgrit_fd_eigen(double rho, int n, double h, double K, double* V, double* lam
 
 // Kernel launchers (kernels.hip).  All return a hipError_t as int.  `tv`
 // selects the operator/preconditioner tile edge (0: 64, 1: 32).  Partial-sum
-// arrays hold pmax entries per slice; the producers write ntiles[tv] (tiled
-// kernels) or nchunk (vector kernels) of them, and each consumer is told how
-// many to sum.
+// arrays hold pmax entries per slice; the tiled kernels write one per 32 x 32
+// block (ntiles[1], whatever tv) and the vector kernels nchunk, and each
+// consumer is told how many to sum.
 // dot_mode: 0 none, 1 partial = sum v*out, 2 = sum out*out.
 int launch_apply(const Geom* g, const Seqs* sq, int tv, const ApplyDesc* desc, int S, const double* vbase,
                  double* outbase, const double* addbase, double sign, int dot_mode, double* partial,
@@ -132,10 +140,36 @@ int launch_cg_direction(const Geom* g, int S, const double* zws, double* pws, co
 // z = P^{-1} r (four batched dense products), partial r.z; active may be NULL.
 int launch_fd_apply(const Geom* g, const FdMats* fd, int tv, const PropDesc* desc, int S, const double* rws,
                     double* zws, double* t1, double* t2, double* partial_rz, const int* active, void* stream);
-// Same with BF16 products and FP32 accumulation (64-tiles; t1, t2 hold S padded BF16 slices;
-// ntiles[0] partials of r.z).
+// Same with BF16 products and FP32 accumulation (64-tiles; t1, t2 hold S padded BF16 slices).
 int launch_fdb_apply(const Geom* g, const FdMatsB* fd, const PropDesc* desc, int S, const double* rws, double* zws,
                      void* t1, void* t2, double* partial_rz, const int* active, void* stream);
+// ---- mixed precision (inner FP32 solves of an iterative refinement; FP32 workspaces
+// hold slice s at s * stride) ----
+// Same preconditioner on FP32 r32 / z32; z32 is also copied to zcopy when given.
+int launch_fdb_apply32(const Geom* g, const FdMatsB* fd, const PropDesc* desc, int S, const float* r32, float* z32,
+                       float* zcopy, void* t1, void* t2, double* partial_rz, const int* active, void* stream);
+// q32 = M p32 + theta_lhs A p32 (FP32 matrix cores) for active slices, partial p.q.
+int launch_apply32(const Geom* g, const Seqs32* sq, int tv, const PropDesc* desc, int S, const float* p32,
+                   float* q32, double* partial_pq, const int* active, void* stream);
+// Start of a refinement step from the FP64 residual: flags, scale ||r||, inner tolerance
+// eta^2 = max(rtol^2 ||b||^2 / ||r||^2, eta_min2), r32 = r / ||r||, d32 = 0, and p32 = r32
+// with partial r32.r32 when p32 != NULL; first: x = 0 where b = 0, counts reset.
+int launch_mx_begin(const Geom* g, const PropDesc* desc, int S, double* xbase, const double* rws,
+                    const double* partial_bb, const double* partial_rr, int np, double rtol2, double eta_min2,
+                    int first, double* bb, double* scale, double* eta2, int* oact, int* iact, int* iters, float* r32,
+                    float* d32, float* p32, double* partial_rr32, void* stream);
+// alpha = rho / p.q; d32 += alpha p32, r32 -= alpha q32; partial r32.r32.
+int launch_mx_update(const Geom* g, int S, float* d32, float* r32, const float* p32, const float* q32,
+                     const double* partial_rho, int nrho, const double* partial_pq, int npq, double* partial_rr_new,
+                     const int* active, void* stream);
+// p32 = z32 + (rho_new / rho) p32; next flags from ||r32||^2 <= eta2[s] and the total count.
+int launch_mx_direction(const Geom* g, int S, const float* z32, float* p32, const double* partial_rho, int nrho,
+                        const double* partial_rho_new, int nrho_new, const double* partial_rr_new, const double* eta2,
+                        int maxit, const int* active, int* active_next, int* iters, void* stream);
+// x += scale[s] d32 where oact[s].
+int launch_mx_refine(const Geom* g, const PropDesc* desc, int S, double* xbase, const float* d32,
+                     const double* scale, const int* oact, void* stream);
+
 // x[s] += G[s] for slices with g >= 0.
 int launch_add_g(const Geom* g, const PropDesc* desc, int S, double* xbase, const double* gbase, void* stream);
 // y[yi[s]] += a * x[xi[s]]; when partial != NULL, partial of ||y||^2 after the update (nchunk entries).

@@ -17,7 +17,7 @@ OK, EINVAL, ENOMEM, EHIP, ENOCONV, EDIVERGED = 0, -1, -2, -3, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 RELAX = {"F": 0, "FCF": 1}
 COARSE = {"cn": 0, "be": 1, "cn2": 2, "opt": 3}
-PRECISION = {"fp64": 0}
+PRECISION = {"fp64": 0, "mixed": 1, "mixed-coarse": 2}
 PRECOND = {"none": 0, "fd": 1, "fd-bf16": 2}
 TILE = {"auto": 0, "rule": 1, "64": 2, "32": 3}
 
@@ -36,13 +36,13 @@ class _Options(ctypes.Structure):
                 ("cg_maxit", ctypes.c_int), ("precond", ctypes.c_int), ("cg_rtol_adapt", ctypes.c_double),
                 ("warm_start", ctypes.c_int),
                 ("divergence_factor", ctypes.c_double), ("tile_policy", ctypes.c_int),
-                ("cg_rtol_coarse", ctypes.c_double)]
+                ("cg_rtol_coarse", ctypes.c_double), ("inner_rtol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("levels", ctypes.c_int),
                 ("phi_applications", ctypes.c_longlong), ("cg_iterations", ctypes.c_longlong),
-                ("residual_history", ctypes.c_double * 64)]
+                ("residual_history", ctypes.c_double * 64), ("refinements", ctypes.c_longlong)]
 
     def history(self):
         n = min(64, self.iterations + 1)
@@ -212,8 +212,9 @@ def make_problem(beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0)):
 
 def make_options(m=8, max_levels=30, relax="FCF", coarse="cn", precision="fp64", max_iter=100, tol_abs=1e-9,
                  tol_rel=0.0, cg_rtol=1e-9, cg_maxit=10000, precond="none", cg_rtol_adapt=0.0, warm_start=True,
-                 divergence_factor=0.0, tile="auto", cg_rtol_coarse=0.0):
+                 divergence_factor=0.0, tile="auto", cg_rtol_coarse=0.0, inner_rtol=0.0):
     o = default_options()
+    o.inner_rtol = float(inner_rtol)
     o.tile_policy = TILE[str(tile)]
     o.cg_rtol_coarse = float(cg_rtol_coarse)
     o.m, o.max_levels, o.max_iter, o.cg_maxit = int(m), int(max_levels), int(max_iter), int(cg_maxit)

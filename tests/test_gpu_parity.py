@@ -353,3 +353,56 @@ def test_loose_coarse_cg_keeps_fixed_point():
             assert rel(host(U), ref) <= 1e-10, rc_coarse
             its[rc_coarse] = (st.iterations, st.cg_iterations)
     assert its[1e-3][1] < its[0.0][1]
+
+
+@pytest.mark.parametrize("level,coarse,pc", [(0, "cn", "fd-bf16"), (1, "opt", "fd-bf16"), (0, "cn", "none"),
+                                             (1, "be", "none")])
+def test_mixed_precision_propagate_matches_oracle(level, coarse, pc):
+    """Iterative refinement with FP32 inner PCG reaches the FP64 propagator."""
+    mg = _mg()
+    beta, gamma, Kx, Ky, Mx, My = 0.7, 0.85, 1.0, 2.0, 90, 75
+    prob = fem.Problem(beta, gamma, Kx, Ky, Mx, My)
+    op = fem.Operator(prob)
+    t = wl.random_grid(16, 21)
+    o = omgrit.MGRIT(op, t, 4, max_levels=3, coarse=coarse, cg_rtol=1e-14)
+    steps = [1, 3, 4] if level else [1, 8, 16]
+    u = wl.random_slices(51, 3, prob.nx, prob.ny)
+    g = wl.random_slices(52, 3, prob.nx, prob.ny)
+    with mg.Solver(beta, gamma, Kx, Ky, Mx, My, t, m=4, max_levels=3, coarse=coarse, cg_rtol=1e-13,
+                   precond=pc, precision="mixed") as s:
+        out = host(s.propagate(level, steps, dev(u), dev(g)))
+    solver = propagator.CGSolver(op, 1e-14, 20000)
+    for i, k in enumerate(steps):
+        if level == 0:
+            ref = propagator.cn_step(op, solver, t[k] - t[k - 1], u[i], g[i])
+        else:
+            ref = o.psi(1, k, u[i]) + g[i]
+        assert rel(out[i], ref) <= 1e-10, (i, rel(out[i], ref))
+
+
+@pytest.mark.parametrize("precision", ["mixed", "mixed-coarse"])
+def test_mixed_precision_solve_reaches_sequential(precision):
+    mg = _mg()
+    prob, t, F, psi0 = _random_problem(12, 64, beta=0.75, gamma=0.85, Mx=72, My=66, Kx=2.0, Ky=1.0)
+    op = fem.Operator(prob)
+    ref = propagator.sequential(op, propagator.CGSolver(op, 1e-14), t, F, psi0)
+    with mg.Solver(prob.beta, prob.gamma, 2.0, 1.0, prob.Mx, prob.My, t, m=4, max_levels=3, coarse="opt",
+                   precond="fd-bf16", cg_rtol=1e-13, cg_rtol_coarse=1e-3, tol_abs=0.0, tol_rel=1e-12, max_iter=40,
+                   precision=precision) as s:
+        U, st, rc = s.solve(dev(F), dev(psi0))
+        assert rc == 0
+        assert st.refinements > 0
+        assert rel(host(U), ref) <= 1e-10
+        Useq, st2, _ = s.sequential(dev(F), dev(psi0))
+        assert rel(host(Useq), ref) <= 1e-10
+        assert (st2.refinements > 0) == (precision == "mixed")
+
+
+def test_mixed_precision_zero_data():
+    mg = _mg()
+    prob, t, F, psi0 = _random_problem(4, 16)
+    with mg.Solver(prob.beta, prob.gamma, 1.0, 1.0, prob.Mx, prob.My, t, m=4, max_levels=2, precision="mixed",
+                   precond="fd-bf16") as s:
+        U, st, rc = s.solve(dev(np.zeros_like(F)), dev(np.zeros_like(psi0)))
+        assert not torch.any(U != 0) and not torch.isnan(U).any()
+        assert st.refinements == 0
