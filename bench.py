@@ -115,6 +115,7 @@ def main():
     ap.add_argument("--max-levels", type=int, default=3)
     ap.add_argument("--tile", default="auto", help="operator tile policy: auto | rule | 64 | 32")
     ap.add_argument("--precision", default="fp64", help="fp64 | mixed | mixed-coarse")
+    ap.add_argument("--graphs", action="store_true", help="replay CG iteration pairs as HIP graphs")
     ap.add_argument("--inner-rtol", type=float, default=0.0, help="mixed precision: inner FP32 tolerance floor")
     ap.add_argument("--cg-rtol-coarse", type=float, default=1e-3,
                     help="CG tolerance on the coarse levels (0: --cg-rtol)")
@@ -163,11 +164,17 @@ def main():
         seq_err = float(torch.linalg.norm(Useq - Uref) / torch.linalg.norm(Uref))
         del Useq
 
-    s = mgrit.Solver(*common, m=W["m"], max_levels=args.max_levels, coarse=args.coarse, cg_rtol=args.cg_rtol,
+    stream = None
+    if args.graphs:                       # graph capture needs a stream of its own
+        import ctypes
+        side = torch.cuda.Stream()
+        stream = ctypes.c_void_p(side.cuda_stream)
+    torch.cuda.synchronize()
+    s = mgrit.Solver(*common, stream=stream, m=W["m"], max_levels=args.max_levels, coarse=args.coarse, cg_rtol=args.cg_rtol,
                      cg_maxit=100000,
                      tol_abs=0.0, tol_rel=args.tol_rel, max_iter=40, precond=args.precond,
                      cg_rtol_adapt=args.cg_adapt, tile=args.tile, cg_rtol_coarse=args.cg_rtol_coarse,
-                     precision=args.precision, inner_rtol=args.inner_rtol)
+                     precision=args.precision, inner_rtol=args.inner_rtol, graphs=args.graphs)
     U = torch.empty((Nt + 1) * nx * ny, dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
         s.solve(Fd, pd, out=U)
@@ -225,6 +232,7 @@ def main():
                       "tol_rel": args.tol_rel, "cg_rtol_adapt": args.cg_adapt, "tile": args.tile,
                       "cg_rtol_coarse": args.cg_rtol_coarse, "precision": args.precision,
                       "inner_rtol": args.inner_rtol, "refinements_per_solve": st.refinements,
+                      "graphs": args.graphs,
                       "mgrit_iterations": st.iterations, "phi_per_solve": st.phi_applications,
                       "cg_iterations_per_solve": st.cg_iterations, "rel_l2_err_vs_fp64_sequential": err,
                       "sequential_dof_per_s": dof / seq_s if seq_s else None, "sequential_rel_l2_err": seq_err,

@@ -126,6 +126,8 @@ typedef struct {
                             /* this changes the MGRIT iteration count, not the solution); */
                             /* 0: cg_rtol                                                  */
     double inner_rtol;      /* mixed precision: floor of the inner FP32 tolerance (0: 1e-5) */
+    int graphs;             /* 1: replay pairs of CG iterations as HIP graphs captured on   */
+                            /* first use (needs a non-NULL stream; results are unchanged)   */
 } mgrit_options;
 
 typedef struct {
@@ -143,7 +145,8 @@ typedef struct mgrit_handle mgrit_handle;
 /* Fill `opt` with defaults: m = 8, max_levels = 30, FCF, CN, FP64, max_iter = 100,
  * tol_abs = 1e-9, tol_rel = 0, cg_rtol = 1e-9 (the paper's tolerances, Section 3.2),
  * cg_maxit = 10000, precond = NONE, cg_rtol_adapt = 0, warm_start = 1,
- * divergence_factor = 0, tile_policy = AUTO, cg_rtol_coarse = 0, inner_rtol = 0. */
+ * divergence_factor = 0, tile_policy = AUTO, cg_rtol_coarse = 0, inner_rtol = 0,
+ * graphs = 0. */
 void mgrit_default_options(mgrit_options* opt);
 
 /* Validate the problem, evaluate the Toeplitz generating sequences of Section 2

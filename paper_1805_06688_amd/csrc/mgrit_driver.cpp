@@ -24,8 +24,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "../../include/mgrit.h"
@@ -135,6 +137,18 @@ struct mgrit_handle {
     int cur_level = 0;              // level of the passes being run
     std::map<int, int> tile_of;     // tile variant chosen per batch width (autotuned)
     std::map<int, int> tile_of32;   // the same for the FP32 inner operator
+    // captured pairs of CG iterations, keyed by every argument of their launches
+    struct GraphKey {
+        const void* d;
+        const void* x;
+        int S, tv, nrho, nrho_next, maxit, parity, kind;
+        double rtol2;
+        bool operator<(const GraphKey& o) const {
+            return std::tie(d, x, S, tv, nrho, nrho_next, maxit, parity, kind, rtol2) <
+                   std::tie(o.d, o.x, o.S, o.tv, o.nrho, o.nrho_next, o.maxit, o.parity, o.kind, o.rtol2);
+        }
+    };
+    std::map<GraphKey, hipGraphExec_t> graphs;
     hipEvent_t tune_ev[5] = {};
     // instrumentation of the CG operator kernel
     bool prof_on = false;
@@ -602,6 +616,48 @@ int tile_variant(mgrit_handle* h, const Pass* ps, int S, int* tv, bool fp32 = fa
     return 0;
 }
 
+// Launches n CG iterations starting at flag parity cur.  With graphs on, pairs
+// of iterations (which leave the parity unchanged) are captured once per set
+// of launch arguments and replayed as one HIP graph; a single iteration and
+// the first one of a solve without preconditioner (its rho partials differ)
+// are launched directly.
+int launch_iterations(mgrit_handle* h, mgrit_handle::GraphKey key, int n, int& cur, int& nrho,
+                      const std::function<int(int, int)>& iter) {
+    const bool graphs = h->opt.graphs && h->stream && !h->prof_on;
+    while (n > 0) {
+        if (graphs && n >= 2 && nrho == key.nrho_next) {
+            key.parity = cur;
+            key.nrho = nrho;
+            auto it = h->graphs.find(key);
+            if (it == h->graphs.end()) {
+                hipGraph_t graph = nullptr;
+                HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+                int rc = iter(cur, nrho);
+                if (!rc) rc = iter(cur ^ 1, nrho);
+                const hipError_t e = hipStreamEndCapture(h->stream, &graph);
+                if (rc) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return rc;
+                }
+                if (e != hipSuccess) return fail(MGRIT_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+                hipGraphExec_t exec = nullptr;
+                const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e2 != hipSuccess) return fail(MGRIT_EHIP, "graph instantiation failed: %s", hipGetErrorString(e2));
+                it = h->graphs.emplace(key, exec).first;
+            }
+            HIPCHK(hipGraphLaunch(it->second, h->stream));
+            n -= 2;
+        } else {
+            CHK(iter(cur, nrho));
+            cur ^= 1;
+            nrho = key.nrho_next;
+            n -= 1;
+        }
+    }
+    return 0;
+}
+
 int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase, const double* fbase,
                    const double* gbase, const double* x0base, int warm);
 
@@ -655,19 +711,21 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
         bool any = false;
         for (int s = 0; s < S; ++s) any |= h->h_act[s] != 0;
         if (!any || it >= maxit) break;
-        for (int c = 0; c < chunk && it < maxit; ++c, ++it) {
-            const int nxt = cur ^ 1;
+        const int n = std::min(chunk, maxit - it);
+        auto iter = [&](int c0, int nr) -> int {
+            const int nxt = c0 ^ 1;
             if (h->prof_on) CHK(prof_record(h, tv));
-            HIPCHK(launch_cg_apply(g, &h->seqs, tv, ps.d, S, h->p, h->q, h->ppq, h->act[cur], st));
+            HIPCHK(launch_cg_apply(g, &h->seqs, tv, ps.d, S, h->p, h->q, h->ppq, h->act[c0], st));
             if (h->prof_on) CHK(prof_record(h, tv));
-            HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, prho[cur], nrho, h->ppq, nt, h->prr[nxt],
-                                    h->act[cur], st));
-            if (pc) HIPCHK(precondition(h->prz[nxt], h->act[cur]));
-            HIPCHK(launch_cg_direction(g, S, zws, h->p, prho[cur], nrho, prho[nxt], nrho_next, h->prr[nxt], h->bb,
-                                       rtol2, maxit, h->act[cur], h->act[nxt], h->iters, st));
-            cur = nxt;
-            nrho = nrho_next;
-        }
+            HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, prho[c0], nr, h->ppq, nt, h->prr[nxt],
+                                    h->act[c0], st));
+            if (pc) HIPCHK(precondition(h->prz[nxt], h->act[c0]));
+            HIPCHK(launch_cg_direction(g, S, zws, h->p, prho[c0], nr, prho[nxt], nrho_next, h->prr[nxt], h->bb,
+                                       rtol2, maxit, h->act[c0], h->act[nxt], h->iters, st));
+            return 0;
+        };
+        CHK(launch_iterations(h, {ps.d, xbase, S, tv, nrho, nrho_next, maxit, 0, 0, rtol2}, n, cur, nrho, iter));
+        it += n;
         chunk = ps.last_iters > 0 ? 2 : std::min(chunk * 2, 32);
     }
     HIPCHK(launch_add_g(g, ps.d, S, xbase, gbase, st));
@@ -737,21 +795,24 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
             bool any = false;
             for (int s = 0; s < S; ++s) any |= h->h_act[s] != 0;
             if (!any || it >= maxit) break;
-            for (int c = 0; c < chunk && it < maxit; ++c, ++it) {
-                const int nxt = cur ^ 1;
+            const int n = std::min(chunk, maxit - it);
+            auto iter = [&](int c0, int nr) -> int {
+                const int nxt = c0 ^ 1;
                 if (h->prof_on) CHK(prof_record(h, 2 + tv32));
-                HIPCHK(launch_apply32(g, &h->seqs32, tv32, ps.d, S, h->p32, h->q32, h->ppq, h->act[cur], st));
+                HIPCHK(launch_apply32(g, &h->seqs32, tv32, ps.d, S, h->p32, h->q32, h->ppq, h->act[c0], st));
                 if (h->prof_on) CHK(prof_record(h, 2 + tv32));
-                HIPCHK(launch_mx_update(g, S, h->d32, h->r32, h->p32, h->q32, prho[cur], nrho, h->ppq, nt,
-                                        h->prr[nxt], h->act[cur], st));
+                HIPCHK(launch_mx_update(g, S, h->d32, h->r32, h->p32, h->q32, prho[c0], nr, h->ppq, nt,
+                                        h->prr[nxt], h->act[c0], st));
                 if (pc)
                     HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, nullptr, h->tb1, h->tb2,
-                                              h->prz[nxt], h->act[cur], st));
-                HIPCHK(launch_mx_direction(g, S, zws, h->p32, prho[cur], nrho, prho[nxt], nrho_next, h->prr[nxt],
-                                           h->mx_eta2, maxit, h->act[cur], h->act[nxt], h->iters, st));
-                cur = nxt;
-                nrho = nrho_next;
-            }
+                                              h->prz[nxt], h->act[c0], st));
+                HIPCHK(launch_mx_direction(g, S, zws, h->p32, prho[c0], nr, prho[nxt], nrho_next, h->prr[nxt],
+                                           h->mx_eta2, maxit, h->act[c0], h->act[nxt], h->iters, st));
+                return 0;
+            };
+            CHK(launch_iterations(h, {ps.d, nullptr, S, tv32, nrho, nrho_next, maxit, 0, 1, 0.0}, n, cur, nrho,
+                                  iter));
+            it += n;
             chunk = 2;
         }
         if (outer == 0) ps.last_inner = it;
@@ -979,6 +1040,7 @@ void mgrit_default_options(mgrit_options* o) {
     o->tile_policy = MGRIT_TILE_AUTO;
     o->cg_rtol_coarse = 0.0;
     o->inner_rtol = 0.0;
+    o->graphs = 0;
 }
 
 const char* mgrit_last_error(void) { return g_err; }
@@ -1009,6 +1071,7 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
     if (o.precision != MGRIT_PREC_FP64 && o.precond == MGRIT_PRECOND_FD)
         return fail(MGRIT_EINVAL, "mixed precision takes precond NONE or FD_BF16");
     if (!(o.inner_rtol >= 0.0 && o.inner_rtol < 1.0)) return fail(MGRIT_EINVAL, "bad inner_rtol");
+    if (o.graphs != 0 && o.graphs != 1) return fail(MGRIT_EINVAL, "graphs must be 0 or 1");
     if (o.precond < MGRIT_PRECOND_NONE || o.precond > MGRIT_PRECOND_FD_BF16)
         return fail(MGRIT_EINVAL, "unknown preconditioner");
     if (!(o.cg_rtol_coarse >= 0.0 && o.cg_rtol_coarse < 1.0)) return fail(MGRIT_EINVAL, "bad cg_rtol_coarse");
@@ -1062,6 +1125,7 @@ void mgrit_destroy(mgrit_handle* h) {
     for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : h->tune_ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     if (h->h_act) (void)hipHostFree(h->h_act);
     if (h->h_iters) (void)hipHostFree(h->h_iters);
     if (h->h_norm) (void)hipHostFree(h->h_norm);

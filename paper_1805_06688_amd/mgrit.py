@@ -36,7 +36,8 @@ class _Options(ctypes.Structure):
                 ("cg_maxit", ctypes.c_int), ("precond", ctypes.c_int), ("cg_rtol_adapt", ctypes.c_double),
                 ("warm_start", ctypes.c_int),
                 ("divergence_factor", ctypes.c_double), ("tile_policy", ctypes.c_int),
-                ("cg_rtol_coarse", ctypes.c_double), ("inner_rtol", ctypes.c_double)]
+                ("cg_rtol_coarse", ctypes.c_double), ("inner_rtol", ctypes.c_double),
+                ("graphs", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -212,8 +213,9 @@ def make_problem(beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0)):
 
 def make_options(m=8, max_levels=30, relax="FCF", coarse="cn", precision="fp64", max_iter=100, tol_abs=1e-9,
                  tol_rel=0.0, cg_rtol=1e-9, cg_maxit=10000, precond="none", cg_rtol_adapt=0.0, warm_start=True,
-                 divergence_factor=0.0, tile="auto", cg_rtol_coarse=0.0, inner_rtol=0.0):
+                 divergence_factor=0.0, tile="auto", cg_rtol_coarse=0.0, inner_rtol=0.0, graphs=False):
     o = default_options()
+    o.graphs = 1 if graphs else 0
     o.inner_rtol = float(inner_rtol)
     o.tile_policy = TILE[str(tile)]
     o.cg_rtol_coarse = float(cg_rtol_coarse)

@@ -406,3 +406,32 @@ def test_mixed_precision_zero_data():
         U, st, rc = s.solve(dev(np.zeros_like(F)), dev(np.zeros_like(psi0)))
         assert not torch.any(U != 0) and not torch.isnan(U).any()
         assert st.refinements == 0
+
+
+@pytest.mark.parametrize("precision,pc", [("fp64", "fd-bf16"), ("fp64", "none"), ("mixed", "fd-bf16")])
+def test_graph_replay_matches_direct_launches(precision, pc):
+    """Pairs of CG iterations replayed as captured HIP graphs give bitwise the results of direct launches, on
+    every replay (three solves per handle, with other GPU work and synchronisation between them)."""
+    import ctypes
+    mg = _mg()
+    prob, t, F, psi0 = _random_problem(13, 32, beta=0.7, gamma=0.9, Mx=80, My=60, Kx=1.0, Ky=1.5)
+    Fd, pd = dev(F), dev(psi0)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    res = {}
+    for graphs in (False, True):
+        outs = []
+        with mg.Solver(prob.beta, prob.gamma, 1.0, 1.5, prob.Mx, prob.My, t, stream=ctypes.c_void_p(side.cuda_stream),
+                       m=4, max_levels=3, coarse="opt", precond=pc, precision=precision, cg_rtol=1e-12,
+                       cg_rtol_coarse=1e-3, tol_abs=0.0, tol_rel=1e-10, max_iter=30, graphs=graphs) as s:
+            for rep in range(3):
+                U, st, rc = s.solve(Fd, pd)
+                side.synchronize()
+                assert rc == 0
+                outs.append((U.clone(), st.cg_iterations, st.iterations))
+                junk = torch.randn(1 << 20, device="cuda").sum()      # eager work between replays
+                torch.cuda.synchronize()
+                assert torch.isfinite(junk)
+        res[graphs] = outs
+    for (Ua, ca, ia), (Ub, cb, ib) in zip(res[False], res[True]):
+        assert torch.equal(Ua, Ub) and ca == cb and ia == ib
