@@ -64,7 +64,7 @@ struct Pass {
     std::vector<PropDesc> h;
     PropDesc* d = nullptr;
     mutable int last_iters = 0;   // CG iterations the slowest slice needed last time (launch schedule)
-    mutable int last_inner = 0;   // the same for the first inner solve of mixed precision
+    mutable int last_inner[4] = {0, 0, 0, 0};   // the same for the inner solves of mixed precision, per step
 };
 
 struct Batch {
@@ -127,7 +127,8 @@ struct mgrit_handle {
     long long refine_count = 0;             // refinement steps summed over slices
     int* act[2] = {nullptr, nullptr};
     int* iters = nullptr;
-    int* h_act = nullptr;                    // pinned
+    int* h_act = nullptr;                    // pinned, two buffers of Smax flags
+    hipEvent_t flag_ev[2] = {};
     int* h_iters = nullptr;                  // pinned
     double* h_norm = nullptr;                // pinned
     long long phi_count = 0, cg_count = 0;
@@ -536,7 +537,8 @@ int alloc_workspace(mgrit_handle* h, int S) {
             CHK(dalloc(h, &h->prz[1], S * nt));
         }
     }
-    HIPCHK(hipHostMalloc((void**)&h->h_act, S * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&h->h_act, 2 * S * sizeof(int), hipHostMallocDefault));
+    for (hipEvent_t& e : h->flag_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPCHK(hipHostMalloc((void**)&h->h_iters, S * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&h->h_norm, S * nt * sizeof(double), hipHostMallocDefault));
     return 0;
@@ -658,6 +660,54 @@ int launch_iterations(mgrit_handle* h, mgrit_handle::GraphKey key, int n, int& c
     return 0;
 }
 
+// Runs CG iterations in chunks (n_first, then one at a time) until no slice
+// is active or maxit iterations were launched.  The host reads the flags of
+// one chunk while the next is already queued, so the GPU does not wait for
+// the check; the one iteration queued after the last slice converged finds
+// every slice inactive and does nothing.  sync_first: wait for the flags at
+// the start before queueing anything (when all slices are likely converged).
+// *n_active0: active slices at the start.
+int run_checked(mgrit_handle* h, int S, int n_first, int maxit, bool sync_first, int& cur, int& it,
+                int* n_active0, const std::function<int(int)>& launch_chunk) {
+    auto queue_flags = [&](int k) -> int {
+        HIPCHK(hipMemcpyAsync(h->h_act + (size_t)k * h->Smax, h->act[cur], S * sizeof(int), hipMemcpyDeviceToHost,
+                              h->stream));
+        HIPCHK(hipEventRecord(h->flag_ev[k], h->stream));
+        return 0;
+    };
+    auto count = [&](int k) -> int {
+        const int* f = h->h_act + (size_t)k * h->Smax;
+        int nact = 0;
+        for (int s = 0; s < S; ++s) nact += f[s] != 0;
+        return nact;
+    };
+    CHK(queue_flags(0));
+    if (sync_first) {
+        HIPCHK(hipEventSynchronize(h->flag_ev[0]));
+        const int nact = count(0);
+        if (n_active0) *n_active0 = nact;
+        n_active0 = nullptr;
+        if (nact == 0) return 0;
+    }
+    int k = 0, n = std::min(n_first, maxit - it);
+    while (true) {
+        const bool launched = n > 0;
+        if (launched) {
+            CHK(launch_chunk(n));
+            it += n;
+            CHK(queue_flags(k ^ 1));
+        }
+        HIPCHK(hipEventSynchronize(h->flag_ev[k]));
+        const int nact = count(k);
+        if (n_active0) *n_active0 = nact;
+        n_active0 = nullptr;
+        if (nact == 0 || !launched) break;
+        k ^= 1;
+        n = std::min(1, maxit - it);
+    }
+    return 0;
+}
+
 int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase, const double* fbase,
                    const double* gbase, const double* x0base, int warm);
 
@@ -700,37 +750,29 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     int nrho = nt;                               // entries of the current rho partials
     const int nrho_next = pc ? nt : nc;
     const int maxit = h->opt.cg_maxit;
-    // Iterations are launched in chunks between host checks of the active
-    // flags: the first chunk covers what this pass needed last time, later
-    // chunks are short, so few launches find every slice converged.
-    int chunk = ps.last_iters > 0 ? std::max(1, ps.last_iters - 1) : (pc ? 8 : 16);
-    while (true) {
-        HIPCHK(hipMemcpyAsync(h->h_act, h->act[cur], S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-        if (h->prof_on) CHK(prof_drain(h));
-        bool any = false;
-        for (int s = 0; s < S; ++s) any |= h->h_act[s] != 0;
-        if (!any || it >= maxit) break;
-        const int n = std::min(chunk, maxit - it);
-        auto iter = [&](int c0, int nr) -> int {
-            const int nxt = c0 ^ 1;
-            if (h->prof_on) CHK(prof_record(h, tv));
-            HIPCHK(launch_cg_apply(g, &h->seqs, tv, ps.d, S, h->p, h->q, h->ppq, h->act[c0], st));
-            if (h->prof_on) CHK(prof_record(h, tv));
-            HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, prho[c0], nr, h->ppq, nt, h->prr[nxt],
-                                    h->act[c0], st));
-            if (pc) HIPCHK(precondition(h->prz[nxt], h->act[c0]));
-            HIPCHK(launch_cg_direction(g, S, zws, h->p, prho[c0], nr, prho[nxt], nrho_next, h->prr[nxt], h->bb,
-                                       rtol2, maxit, h->act[c0], h->act[nxt], h->iters, st));
-            return 0;
-        };
-        CHK(launch_iterations(h, {ps.d, xbase, S, tv, nrho, nrho_next, maxit, 0, 0, rtol2}, n, cur, nrho, iter));
-        it += n;
-        chunk = ps.last_iters > 0 ? 2 : std::min(chunk * 2, 32);
-    }
+    // The first chunk covers what this pass needed last time, later chunks are
+    // short, so few launches find every slice converged.
+    const int first = ps.last_iters > 0 ? std::max(1, ps.last_iters - 1) : (pc ? 8 : 16);
+    auto iter = [&](int c0, int nr) -> int {
+        const int nxt = c0 ^ 1;
+        if (h->prof_on) CHK(prof_record(h, tv));
+        HIPCHK(launch_cg_apply(g, &h->seqs, tv, ps.d, S, h->p, h->q, h->ppq, h->act[c0], st));
+        if (h->prof_on) CHK(prof_record(h, tv));
+        HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, prho[c0], nr, h->ppq, nt, h->prr[nxt],
+                                h->act[c0], st));
+        if (pc) HIPCHK(precondition(h->prz[nxt], h->act[c0]));
+        HIPCHK(launch_cg_direction(g, S, zws, h->p, prho[c0], nr, prho[nxt], nrho_next, h->prr[nxt], h->bb, rtol2,
+                                   maxit, h->act[c0], h->act[nxt], h->iters, st));
+        return 0;
+    };
+    auto chunk = [&](int n) -> int {
+        return launch_iterations(h, {ps.d, xbase, S, tv, nrho, nrho_next, maxit, 0, 0, rtol2}, n, cur, nrho, iter);
+    };
+    CHK(run_checked(h, S, first, maxit, false, cur, it, nullptr, chunk));
     HIPCHK(launch_add_g(g, ps.d, S, xbase, gbase, st));
     HIPCHK(hipMemcpyAsync(h->h_iters, h->iters, S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
+    if (h->prof_on) CHK(prof_drain(h));
     long long its = 0;
     int most = 0;
     for (int s = 0; s < S; ++s) {
@@ -774,54 +816,45 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
         HIPCHK(launch_mx_begin(g, ps.d, S, xbase, h->r, h->pbb, h->pout, nt, rtol2, eta * eta, outer == 0 ? 1 : 0,
                                h->bb, h->mx_scale, h->mx_eta2, h->mx_oact, h->act[0], h->iters, h->r32, h->d32,
                                pc ? nullptr : h->p32, h->prr[0], st));
-        HIPCHK(hipMemcpyAsync(h->h_act, h->mx_oact, S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-        int nact = 0;
-        for (int s = 0; s < S; ++s) nact += h->h_act[s] != 0;
-        if (nact == 0) break;
-        steps += nact;
         if (tv32 < 0) CHK(tile_variant(h, &ps, S, &tv32, true));
         if (pc)
             HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, h->p32, h->tb1, h->tb2, h->prz[0],
                                       h->act[0], st));
-        int cur = 0, it = 0;
+        int cur = 0, it = 0, nact = 0;
         int nrho = pc ? nt : nc;
         const int nrho_next = pc ? nt : nc;
-        int chunk = (outer == 0 && ps.last_inner > 0) ? std::max(1, ps.last_inner - 1) : 6;
-        while (true) {
-            HIPCHK(hipMemcpyAsync(h->h_act, h->act[cur], S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
-            HIPCHK(hipStreamSynchronize(h->stream));
-            if (h->prof_on) CHK(prof_drain(h));
-            bool any = false;
-            for (int s = 0; s < S; ++s) any |= h->h_act[s] != 0;
-            if (!any || it >= maxit) break;
-            const int n = std::min(chunk, maxit - it);
-            auto iter = [&](int c0, int nr) -> int {
-                const int nxt = c0 ^ 1;
-                if (h->prof_on) CHK(prof_record(h, 2 + tv32));
-                HIPCHK(launch_apply32(g, &h->seqs32, tv32, ps.d, S, h->p32, h->q32, h->ppq, h->act[c0], st));
-                if (h->prof_on) CHK(prof_record(h, 2 + tv32));
-                HIPCHK(launch_mx_update(g, S, h->d32, h->r32, h->p32, h->q32, prho[c0], nr, h->ppq, nt,
-                                        h->prr[nxt], h->act[c0], st));
-                if (pc)
-                    HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, nullptr, h->tb1, h->tb2,
-                                              h->prz[nxt], h->act[c0], st));
-                HIPCHK(launch_mx_direction(g, S, zws, h->p32, prho[c0], nr, prho[nxt], nrho_next, h->prr[nxt],
-                                           h->mx_eta2, maxit, h->act[c0], h->act[nxt], h->iters, st));
-                return 0;
-            };
-            CHK(launch_iterations(h, {ps.d, nullptr, S, tv32, nrho, nrho_next, maxit, 0, 1, 0.0}, n, cur, nrho,
-                                  iter));
-            it += n;
-            chunk = 2;
-        }
-        if (outer == 0) ps.last_inner = it;
+        auto iter = [&](int c0, int nr) -> int {
+            const int nxt = c0 ^ 1;
+            if (h->prof_on) CHK(prof_record(h, 2 + tv32));
+            HIPCHK(launch_apply32(g, &h->seqs32, tv32, ps.d, S, h->p32, h->q32, h->ppq, h->act[c0], st));
+            if (h->prof_on) CHK(prof_record(h, 2 + tv32));
+            HIPCHK(launch_mx_update(g, S, h->d32, h->r32, h->p32, h->q32, prho[c0], nr, h->ppq, nt, h->prr[nxt],
+                                    h->act[c0], st));
+            if (pc)
+                HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, nullptr, h->tb1, h->tb2, h->prz[nxt],
+                                          h->act[c0], st));
+            HIPCHK(launch_mx_direction(g, S, zws, h->p32, prho[c0], nr, prho[nxt], nrho_next, h->prr[nxt],
+                                       h->mx_eta2, maxit, h->act[c0], h->act[nxt], h->iters, st));
+            return 0;
+        };
+        auto chunk = [&](int n) -> int {
+            return launch_iterations(h, {ps.d, nullptr, S, tv32, nrho, nrho_next, maxit, 0, 1, 0.0}, n, cur, nrho,
+                                     iter);
+        };
+        // the flags at the start are the outer ones: none active ends the refinement
+        const int li = ps.last_inner[std::min(outer, 3)];
+        const int first = li > 0 ? std::max(1, li - 1) : 6;
+        CHK(run_checked(h, S, first, maxit, outer > 0, cur, it, &nact, chunk));
+        if (nact == 0) break;
+        steps += nact;
+        ps.last_inner[std::min(outer, 3)] = it;
         HIPCHK(launch_mx_refine(g, ps.d, S, xbase, h->d32, h->mx_scale, h->mx_oact, st));
         HIPCHK(launch_init_residual(g, &h->seqs, tv, ps.d, S, xbase, h->b, h->r, h->pout, st));
     }
     HIPCHK(launch_add_g(g, ps.d, S, xbase, gbase, st));
     HIPCHK(hipMemcpyAsync(h->h_iters, h->iters, S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
+    if (h->prof_on) CHK(prof_drain(h));
     long long its = 0;
     for (int s = 0; s < S; ++s) its += h->h_iters[s];
     h->cg_count += its;
@@ -1127,6 +1160,8 @@ void mgrit_destroy(mgrit_handle* h) {
         if (e) (void)hipEventDestroy(e);
     for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     if (h->h_act) (void)hipHostFree(h->h_act);
+    for (hipEvent_t e : h->flag_ev)
+        if (e) (void)hipEventDestroy(e);
     if (h->h_iters) (void)hipHostFree(h->h_iters);
     if (h->h_norm) (void)hipHostFree(h->h_norm);
     delete h;
