@@ -83,6 +83,16 @@ extern "C" {
  * FP64, so the solution is the FP64 one. */
 #define MGRIT_PRECOND_FD_BF16 2
 
+/* How the operator M_h + theta A_h is applied.  DENSE: the Toeplitz products
+ * as dense contractions on the matrix cores (tiled kernels).  FFT: each
+ * Toeplitz product along a grid line as a circulant convolution of length 512
+ * by FFT (n_x, n_y <= 256; EINVAL otherwise), O(n^2 log n) per slice instead
+ * of O(n^3); results agree with DENSE to rounding.  AUTO: FFT where it
+ * applies, else DENSE. */
+#define MGRIT_OP_AUTO  0
+#define MGRIT_OP_DENSE 1
+#define MGRIT_OP_FFT   2
+
 /* Tile edge of the operator kernels (64 or 32 nodes).  AUTO times both on the
  * first batch of each width and keeps the faster; RULE takes 64 when the batch
  * holds at least 512 such tiles.  The choice changes speed only: results are
@@ -128,6 +138,7 @@ typedef struct {
     double inner_rtol;      /* mixed precision: floor of the inner FP32 tolerance (0: 1e-5) */
     int graphs;             /* 1: replay pairs of CG iterations as HIP graphs captured on   */
                             /* first use (needs a non-NULL stream; results are unchanged)   */
+    int op;                 /* MGRIT_OP_*                                                */
 } mgrit_options;
 
 typedef struct {
@@ -146,7 +157,7 @@ typedef struct mgrit_handle mgrit_handle;
  * tol_abs = 1e-9, tol_rel = 0, cg_rtol = 1e-9 (the paper's tolerances, Section 3.2),
  * cg_maxit = 10000, precond = NONE, cg_rtol_adapt = 0, warm_start = 1,
  * divergence_factor = 0, tile_policy = AUTO, cg_rtol_coarse = 0, inner_rtol = 0,
- * graphs = 0. */
+ * graphs = 0, op = DENSE. */
 void mgrit_default_options(mgrit_options* opt);
 
 /* Validate the problem, evaluate the Toeplitz generating sequences of Section 2

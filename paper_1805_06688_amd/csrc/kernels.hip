@@ -895,6 +895,298 @@ __global__ __launch_bounds__(NT) void k_zero_slices(Geom g, int S, const int* id
     for (long long e = lo + threadIdx.x; e < hi; e += NT) y[e] = 0.0;
 }
 
+// ---- the operator by FFT: Toeplitz products as circulant convolutions ----
+// A Toeplitz product along a grid line is a linear convolution with a kernel
+// of 2n - 1 taps; embedded in a circulant of length FL >= 2n - 1 it becomes a
+// product of spectra.  The pass over x (line j = the n_x nodes of row j) forms
+//   X_j = c1 * v_j + c2 * v_{j+1} + c3 * v_{j-1}
+// with c1, c2, c3 the kernels of A_1, A_2 and A_2^T; the pass over y does the
+// same along columns with the y kernels.  Two real lines travel as one
+// complex transform (real and imaginary part), and two output lines are
+// packed the same way for the inverse transform.  Transforms are radix-8
+// Stockham FFTs of FL = 512 points, one wavefront per transform, 8 points per
+// lane.  The x pass writes theta X to a workspace; the y pass adds theta Y and
+// applies the epilogue of the operator (mass stencil, sign, added vector,
+// dot-product partial) as the tiled kernels do.
+constexpr int FL = 512;
+constexpr int FJ = 14;               // output lines per workgroup
+constexpr int FNT = 512;             // threads per workgroup: 8 waves, one input pair each
+constexpr int FPAD = FL + FL / 8;    // padded LDS length of one transform
+
+template <typename T>
+struct cpx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) {
+    return {a.x + b.x, a.y + b.y};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) {
+    return {a.x - b.x, a.y - b.y};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cmi(cpx<T> a) {   // a * (-i)
+    return {a.y, -a.x};
+}
+__device__ __forceinline__ int fpidx(int k) { return k + (k >> 3); }
+
+// Forward DFT of 8 points in registers (two radix-2 splittings in frequency).
+template <typename T>
+__device__ __forceinline__ void dft8(cpx<T>* a) {
+    const T h = (T)0.70710678118654752440;
+    const cpx<T> b0 = cadd(a[0], a[4]), b1 = cadd(a[1], a[5]), b2 = cadd(a[2], a[6]), b3 = cadd(a[3], a[7]);
+    const cpx<T> b4 = csub(a[0], a[4]), d5 = csub(a[1], a[5]), d6 = csub(a[2], a[6]), d7 = csub(a[3], a[7]);
+    const cpx<T> b5 = {h * (d5.x + d5.y), h * (d5.y - d5.x)};     // * exp(-i pi / 4)
+    const cpx<T> b6 = cmi(d6);                                    // * exp(-i pi / 2)
+    const cpx<T> b7 = {h * (d7.y - d7.x), -h * (d7.x + d7.y)};    // * exp(-3 i pi / 4)
+    const cpx<T> c0 = cadd(b0, b2), c2 = csub(b0, b2), c1 = cadd(b1, b3), c3 = cmi(csub(b1, b3));
+    const cpx<T> c4 = cadd(b4, b6), c6 = csub(b4, b6), c5 = cadd(b5, b7), c7 = cmi(csub(b5, b7));
+    a[0] = cadd(c0, c1);
+    a[4] = csub(c0, c1);
+    a[2] = cadd(c2, c3);
+    a[6] = csub(c2, c3);
+    a[1] = cadd(c4, c5);
+    a[5] = csub(c4, c5);
+    a[3] = cadd(c6, c7);
+    a[7] = csub(c6, c7);
+}
+
+// a[r] *= w^r, r = 1..7
+template <typename T>
+__device__ __forceinline__ void twiddle8(cpx<T>* a, cpx<T> w) {
+    cpx<T> wr = w;
+#pragma unroll
+    for (int r = 1; r < 8; ++r) {
+        a[r] = cmul(a[r], wr);
+        if (r < 7) wr = cmul(wr, w);
+    }
+}
+
+// Forward FFT of FL points with a[r] = x[lane + 64 r] on entry and
+// a[r] = X[lane + 64 r] on return; buf is this wave's FPAD-entry LDS region
+// (only this wave touches it), tw[k] = exp(-2 pi i k / FL).
+template <typename T>
+__device__ __forceinline__ void fft512(cpx<T>* a, cpx<T>* buf, const cpx<T>* __restrict__ tw, int lane) {
+    dft8(a);                                              // sub-transforms of length 1 -> 8
+#pragma unroll
+    for (int r = 0; r < 8; ++r) buf[fpidx(8 * lane + r)] = a[r];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) a[r] = buf[fpidx(lane + 64 * r)];
+    twiddle8(a, tw[(lane & 7) * 8]);                      // 8 -> 64
+    dft8(a);
+    const int d1 = (lane >> 3) * 64 + (lane & 7);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) buf[fpidx(d1 + 8 * r)] = a[r];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) a[r] = buf[fpidx(lane + 64 * r)];
+    twiddle8(a, tw[lane]);                                // 64 -> 512
+    dft8(a);
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Sum over a 512-thread block in a fixed order.
+__device__ __forceinline__ double block_sum8(double v, double* red) {
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return ((red[0] + red[1]) + (red[2] + red[3])) + ((red[4] + red[5]) + (red[6] + red[7]));
+}
+
+// Slice operands of one operator use (MODE as in k_prop_apply: 0 right-hand
+// side, 1 initial residual, 2 CG product; 3 the ApplyDesc form of k_apply).
+template <typename T, int MODE>
+__device__ __forceinline__ void fft_operands(const Geom& g, const void* desc, int s, const T* vbase, const T* wsin,
+                                             const T* addbase, T* outbase, const T*& v, const T*& add, T*& out,
+                                             double& theta) {
+    const long long so = (long long)s * g.stride;
+    if (MODE == 3) {
+        const ApplyDesc d = ((const ApplyDesc*)desc)[s];
+        v = vbase + d.v * g.stride;
+        add = (addbase && d.add >= 0) ? addbase + d.add * g.stride : nullptr;
+        out = outbase + d.out * g.stride;
+        theta = d.theta;
+        return;
+    }
+    const PropDesc d = ((const PropDesc*)desc)[s];
+    if (MODE == 0) {
+        v = vbase + d.u * g.stride;
+        add = (addbase && d.f >= 0) ? addbase + d.f * g.stride : nullptr;
+        theta = d.theta_rhs;
+    } else if (MODE == 1) {
+        v = vbase + d.x * g.stride;
+        add = wsin + so;
+        theta = d.theta_lhs;
+    } else {
+        v = wsin + so;
+        add = nullptr;
+        theta = d.theta_lhs;
+    }
+    out = outbase + so;
+}
+
+// One line pass of the FFT operator.  DIR 0: lines along x, writes
+// pbuf = theta X.  DIR 1: lines along y; out = add + sign (M v + pbuf + theta Y)
+// and, with dot_mode, the block's partial of v.out (1) or out.out (2).
+template <typename T, int DIR, int MODE>
+__global__ __launch_bounds__(FNT) void k_fft_line(Geom g, FftPlan pl, const void* __restrict__ desc, int S,
+                                                  const T* vbase, const T* wsin, const T* addbase, T* outbase,
+                                                  T* pbuf, double sign_d, int dot_mode, double* partial,
+                                                  const int* active) {
+    const int nb = DIR == 0 ? pl.nbx : pl.nby;
+    int s, blk;
+    decode_block(nb, S, s, blk);
+    if (s < 0) return;
+    if (MODE == 2 && active && !active[s]) return;
+    __shared__ __attribute__((aligned(16))) cpx<T> lds[8 * FPAD];
+    __shared__ double red[8];
+    const T* v;
+    const T* add;
+    T* out;
+    double theta_d;
+    fft_operands<T, MODE>(g, desc, s, vbase, wsin, addbase, outbase, v, add, out, theta_d);
+    const T theta = (T)theta_d;
+    T* P = pbuf + (long long)s * g.stride;
+    const int nx = g.nx, ny = g.ny;
+    const int n = DIR == 0 ? nx : ny;        // line length
+    const int nl = DIR == 0 ? ny : nx;       // number of lines
+    const int l0 = blk * FJ;                 // first output line
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const cpx<T>* tw = (const cpx<T>*)(sizeof(T) == 8 ? (const void*)pl.tw : (const void*)pl.tw32);
+    const cpx<T>* K = (const cpx<T>*)(sizeof(T) == 8 ? (const void*)(DIR == 0 ? pl.kx : pl.ky)
+                                                      : (const void*)(DIR == 0 ? pl.kx32 : pl.ky32));
+    cpx<T>* buf = lds + wave * FPAD;
+
+    // ---- load the input pair of this wave: lines la = l0 - 1 + 2 wave and la + 1 ----
+    const int la = l0 - 1 + 2 * wave, lb = la + 1;
+    cpx<T> a[8];
+    if (DIR == 0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int pos = lane + 64 * r;
+            a[r].x = (la >= 0 && la < nl && pos < n) ? v[(long long)la * nx + pos] : T(0);
+            a[r].y = (lb >= 0 && lb < nl && pos < n) ? v[(long long)lb * nx + pos] : T(0);
+        }
+    } else {
+        // columns l0 - 1 .. l0 + 14 of every row, staged through LDS (row segments are contiguous)
+        T* stg = (T*)lds;
+        for (int idx = tid; idx < ny * 16; idx += FNT) {
+            const int pos = idx >> 4, c = idx & 15, col = l0 - 1 + c;
+            stg[pos * 17 + c] = (col >= 0 && col < nx) ? v[(long long)pos * nx + col] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int pos = lane + 64 * r;
+            a[r].x = pos < n ? stg[pos * 17 + 2 * wave] : T(0);
+            a[r].y = pos < n ? stg[pos * 17 + 2 * wave + 1] : T(0);
+        }
+        __syncthreads();
+    }
+    fft512(a, buf, tw, lane);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) buf[fpidx(lane + 64 * r)] = a[r];
+    __syncthreads();
+
+    // ---- spectra of the output pair (lines oa = l0 + 2 wave, ob = oa + 1) ----
+    const int oa = l0 + 2 * wave, ob = oa + 1;
+    const bool work = wave < 7 && oa < nl;
+    if (work) {
+        const cpx<T>* Z1 = buf;              // lines oa - 1, oa
+        const cpx<T>* Z2 = buf + FPAD;       // lines oa + 1, oa + 2
+        const T half = (T)0.5;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int k = lane + 64 * r, kk = (FL - k) & (FL - 1);
+            const cpx<T> z1 = Z1[fpidx(k)], z1c = Z1[fpidx(kk)], z2 = Z2[fpidx(k)], z2c = Z2[fpidx(kk)];
+            // unpack: first line (z + conj z(-k)) / 2, second line (z - conj z(-k)) / (2 i)
+            const cpx<T> vm = {half * (z1.x + z1c.x), half * (z1.y - z1c.y)};
+            const cpx<T> v0 = {half * (z1.y + z1c.y), half * (z1c.x - z1.x)};
+            const cpx<T> vp = {half * (z2.x + z2c.x), half * (z2.y - z2c.y)};
+            const cpx<T> vq = {half * (z2.y + z2c.y), half * (z2c.x - z2.x)};
+            const cpx<T> c1 = K[k], c2 = K[FL + k], c3 = K[2 * FL + k];
+            const cpx<T> xa = cadd(cadd(cmul(c1, v0), cmul(c2, vp)), cmul(c3, vm));
+            const cpx<T> xb = cadd(cadd(cmul(c1, vp), cmul(c2, vq)), cmul(c3, v0));
+            // W = xa + i xb; the inverse transform is conj(FFT(conj W))
+            a[r] = {xa.x - xb.y, -(xa.y + xb.x)};
+        }
+    }
+    __syncthreads();
+    if (work) fft512(a, buf, tw, lane);      // a[r] = conj of the packed output at lane + 64 r
+
+    if (DIR == 0) {
+        if (work) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int pos = lane + 64 * r;
+                if (pos < n) {
+                    P[(long long)oa * nx + pos] = theta * a[r].x;
+                    if (ob < nl) P[(long long)ob * nx + pos] = -theta * a[r].y;
+                }
+            }
+        }
+        return;
+    }
+    // ---- y pass: stage theta Y as [row][column] and apply the epilogue ----
+    __syncthreads();
+    T* stg = (T*)lds;
+    if (work) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int pos = lane + 64 * r;
+            if (pos < n) {
+                stg[pos * 15 + 2 * wave] = theta * a[r].x;
+                stg[pos * 15 + 2 * wave + 1] = -theta * a[r].y;
+            }
+        }
+    }
+    __syncthreads();
+    const T mass = (T)g.mass, sign = (T)sign_d;
+    double dot = 0.0;
+    for (int idx = tid; idx < ny * FJ; idx += FNT) {
+        const int j = idx / FJ, c = idx - j * FJ, i = l0 + c;
+        if (i >= nx) continue;
+        const long long o = (long long)j * nx + i;
+        const T cv = v[o];
+        const bool hl = i > 0, hr = i + 1 < nx, hd = j > 0, hu = j + 1 < ny;
+        T m7 = T(6) * cv;
+        m7 += hl ? v[o - 1] : T(0);
+        m7 += hr ? v[o + 1] : T(0);
+        m7 += hd ? v[o - nx] : T(0);
+        m7 += hu ? v[o + nx] : T(0);
+        m7 += (hr && hu) ? v[o + nx + 1] : T(0);
+        m7 += (hl && hd) ? v[o - nx - 1] : T(0);
+        T val = sign * (mass * m7 + (P[o] + stg[j * 15 + c]));
+        if (add) val += add[o];
+        out[o] = val;
+        if (dot_mode == 1) dot += (double)cv * (double)val;
+        else if (dot_mode == 2) dot += (double)val * (double)val;
+    }
+    if (dot_mode) {
+        dot = block_sum8(dot, red);
+        if (tid == 0) partial[(long long)s * g.pmax + blk] = dot;
+    }
+}
+
+template <typename T, int MODE>
+void fft_op(const Geom* g, const FftPlan* pl, const void* desc, int S, const T* vbase, const T* wsin,
+            const T* addbase, T* outbase, T* pbuf, double sign, int dot_mode, double* partial, const int* active,
+            hipStream_t st) {
+    hipLaunchKernelGGL((k_fft_line<T, 0, MODE>), dim3(grid_blocks(pl->nbx, S)), dim3(FNT), 0, st, *g, *pl, desc, S,
+                       vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
+    hipLaunchKernelGGL((k_fft_line<T, 1, MODE>), dim3(grid_blocks(pl->nby, S)), dim3(FNT), 0, st, *g, *pl, desc, S,
+                       vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
+}
+
 template <int TT>
 void fd_chain(const Geom* g, const FdMats* fd, const PropDesc* desc, int S, const double* rws, double* zws,
               double* t1, double* t2, double* partial_rz, const int* active, hipStream_t st) {
@@ -1110,6 +1402,48 @@ int launch_axpy_slices(const Geom* g, int S, const int* yi, double* ybase, const
     if (S <= 0) return 0;
     hipLaunchKernelGGL(k_axpy_slices, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, S, yi,
                        ybase, xi, xbase, a, partial);
+    return (int)hipGetLastError();
+}
+
+// ---- operator by FFT (see k_fft_line); pbuf: S slices of workspace ----
+int launch_fft_apply(const Geom* g, const FftPlan* pl, const ApplyDesc* desc, int S, const double* vbase,
+                     double* outbase, const double* addbase, double sign, int dot_mode, double* partial,
+                     double* pbuf, void* stream) {
+    if (S <= 0) return 0;
+    fft_op<double, 3>(g, pl, desc, S, vbase, nullptr, addbase, outbase, pbuf, sign, dot_mode, partial, nullptr,
+                      (hipStream_t)stream);
+    return (int)hipGetLastError();
+}
+
+int launch_fft_rhs(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const double* ubase,
+                   const double* fbase, double* bws, double* partial_bb, double* pbuf, void* stream) {
+    if (S <= 0) return 0;
+    fft_op<double, 0>(g, pl, desc, S, ubase, nullptr, fbase, bws, pbuf, 1.0, 2, partial_bb, nullptr,
+                      (hipStream_t)stream);
+    return (int)hipGetLastError();
+}
+
+int launch_fft_init_residual(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const double* xbase,
+                             const double* bws, double* rws, double* partial_rr, double* pbuf, void* stream) {
+    if (S <= 0) return 0;
+    fft_op<double, 1>(g, pl, desc, S, xbase, bws, nullptr, rws, pbuf, -1.0, 2, partial_rr, nullptr,
+                      (hipStream_t)stream);
+    return (int)hipGetLastError();
+}
+
+int launch_fft_cg_apply(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const double* pws,
+                        double* qws, double* partial_pq, const int* active, double* pbuf, void* stream) {
+    if (S <= 0) return 0;
+    fft_op<double, 2>(g, pl, desc, S, nullptr, pws, nullptr, qws, pbuf, 1.0, 1, partial_pq, active,
+                      (hipStream_t)stream);
+    return (int)hipGetLastError();
+}
+
+int launch_fft_apply32(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const float* p32, float* q32,
+                       double* partial_pq, const int* active, float* pbuf, void* stream) {
+    if (S <= 0) return 0;
+    fft_op<float, 2>(g, pl, desc, S, nullptr, p32, nullptr, q32, pbuf, 1.0, 1, partial_pq, active,
+                     (hipStream_t)stream);
     return (int)hipGetLastError();
 }
 

@@ -106,6 +106,12 @@ struct mgrit_handle {
     double* d_seq = nullptr;                 // T1x | A2x | T1y | A2y
     float* d_seq32 = nullptr;                // FP32 copy (mixed precision)
     Seqs32 seqs32{};
+    // operator by FFT: tables, the x-pass workspaces, partials per slice
+    bool use_fft = false;
+    FftPlan plan{};
+    double* pfft = nullptr;
+    float* pfft32 = nullptr;
+    int nop = 0;                             // operator partials per slice
     std::vector<double> host_seq_x, host_seq_y;
     double cx = 0, cy = 0;
     std::vector<Level> lv;
@@ -413,6 +419,80 @@ int build_sequences(mgrit_handle* h) {
     return 0;
 }
 
+// Tables of the FFT operator.  Kernels of one direction (sequences t, u, w of
+// length n, scaled): c1(m) = t(|m|) for A_1; c2(m) = A2(-m) for A_2 (applied
+// to the next line) and c3(m) = A2(m) for A_2^T (the previous line), with
+// A2(d) = u(d) for d >= 0 and w(-d) for d < 0, so that the product along a
+// line is sum_k c(i - k) v(k).  Each kernel is embedded in a circulant of
+// length L (c(m) at m mod L, |m| < n) and transformed by a direct DFT in
+// extended precision; the spectra are divided by L for the inverse.
+int build_fft_plan(mgrit_handle* h) {
+    const int L = MGRIT_FFT_LEN;
+    const Geom& g = h->geom;
+    std::vector<long double> cs(L), sn(L);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 0; k < L; ++k) {
+        cs[k] = cosl(2.0L * pi * k / L);
+        sn[k] = -sinl(2.0L * pi * k / L);
+    }
+    std::vector<double> tw(2 * L);
+    for (int k = 0; k < L; ++k) {
+        tw[2 * k] = (double)cs[k];
+        tw[2 * k + 1] = (double)sn[k];
+    }
+    auto spectra = [&](const std::vector<double>& seq, int n, std::vector<double>& out) {
+        const double* t = &seq[0];
+        const double* u = &seq[n];
+        const double* w = &seq[2 * n];
+        auto A2 = [&](int d) { return d >= 0 ? u[d] : w[-d]; };
+        out.assign(3 * 2 * (size_t)L, 0.0);
+        for (int c = 0; c < 3; ++c) {
+            std::vector<long double> e(L, 0.0L);
+            for (int m = -(n - 1); m <= n - 1; ++m) {
+                const double val = c == 0 ? t[std::abs(m)] : (c == 1 ? A2(-m) : A2(m));
+                e[(m + L) % L] = val;
+            }
+            for (int k = 0; k < L; ++k) {
+                long double re = 0.0L, im = 0.0L;
+                for (int m = 0; m < L; ++m) {
+                    if (e[m] == 0.0L) continue;
+                    const int q = (int)(((long long)m * k) % L);
+                    re += e[m] * cs[q];
+                    im += e[m] * sn[q];
+                }
+                out[(size_t)2 * (c * L + k)] = (double)(re / L);
+                out[(size_t)2 * (c * L + k) + 1] = (double)(im / L);
+            }
+        }
+    };
+    std::vector<double> kx, ky;
+    spectra(h->host_seq_x, g.nx, kx);
+    spectra(h->host_seq_y, g.ny, ky);
+    double* d = nullptr;
+    CHK(dalloc(h, &d, tw.size() + kx.size() + ky.size()));
+    HIPCHK(hipMemcpy(d, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d + tw.size(), kx.data(), kx.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d + tw.size() + kx.size(), ky.data(), ky.size() * sizeof(double), hipMemcpyHostToDevice));
+    h->plan.tw = d;
+    h->plan.kx = d + tw.size();
+    h->plan.ky = d + tw.size() + kx.size();
+    if (h->opt.precision != MGRIT_PREC_FP64) {
+        std::vector<float> f;
+        for (double v : tw) f.push_back((float)v);
+        for (double v : kx) f.push_back((float)v);
+        for (double v : ky) f.push_back((float)v);
+        float* d32 = nullptr;
+        CHK(dalloc(h, &d32, f.size()));
+        HIPCHK(hipMemcpy(d32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+        h->plan.tw32 = d32;
+        h->plan.kx32 = d32 + tw.size();
+        h->plan.ky32 = d32 + tw.size() + kx.size();
+    }
+    h->plan.nbx = (g.ny + MGRIT_FFT_LINES - 1) / MGRIT_FFT_LINES;
+    h->plan.nby = (g.nx + MGRIT_FFT_LINES - 1) / MGRIT_FFT_LINES;
+    return 0;
+}
+
 // FP64 -> BF16 bit pattern, round to nearest even (finite inputs).
 unsigned short to_bf16(double v) {
     const float f = (float)v;
@@ -522,6 +602,10 @@ int alloc_workspace(mgrit_handle* h, int S) {
     CHK(dalloc(h, &h->act[0], S));
     CHK(dalloc(h, &h->act[1], S));
     CHK(dalloc(h, &h->iters, S));
+    if (h->use_fft) {
+        CHK(dalloc(h, &h->pfft, S * st));
+        if (h->opt.precision != MGRIT_PREC_FP64) CHK(dalloc(h, &h->pfft32, S * st));
+    }
     if (h->opt.precision != MGRIT_PREC_FP64) {
         CHK(dalloc(h, &h->r32, S * st));
         CHK(dalloc(h, &h->z32, S * st));
@@ -568,6 +652,32 @@ int prof_drain(mgrit_handle* h) {
     return 0;
 }
 
+// Operator launches: the tiled matrix-core kernels or the two FFT passes.
+int op_rhs(mgrit_handle* h, int tv, const Pass& ps, const double* ubase, const double* fbase) {
+    if (h->use_fft)
+        return launch_fft_rhs(&h->geom, &h->plan, ps.d, ps.S, ubase, fbase, h->b, h->pbb, h->pfft, h->stream);
+    return launch_rhs(&h->geom, &h->seqs, tv, ps.d, ps.S, ubase, fbase, h->b, h->pbb, h->stream);
+}
+
+int op_resid(mgrit_handle* h, int tv, const Pass& ps, const double* xbase, double* partial) {
+    if (h->use_fft)
+        return launch_fft_init_residual(&h->geom, &h->plan, ps.d, ps.S, xbase, h->b, h->r, partial, h->pfft,
+                                        h->stream);
+    return launch_init_residual(&h->geom, &h->seqs, tv, ps.d, ps.S, xbase, h->b, h->r, partial, h->stream);
+}
+
+int op_cg(mgrit_handle* h, int tv, const Pass& ps, const double* pin, double* qout, const int* act) {
+    if (h->use_fft)
+        return launch_fft_cg_apply(&h->geom, &h->plan, ps.d, ps.S, pin, qout, h->ppq, act, h->pfft, h->stream);
+    return launch_cg_apply(&h->geom, &h->seqs, tv, ps.d, ps.S, pin, qout, h->ppq, act, h->stream);
+}
+
+int op_cg32(mgrit_handle* h, int tv, const Pass& ps, const float* pin, float* qout, const int* act) {
+    if (h->use_fft)
+        return launch_fft_apply32(&h->geom, &h->plan, ps.d, ps.S, pin, qout, h->ppq, act, h->pfft32, h->stream);
+    return launch_apply32(&h->geom, &h->seqs32, tv, ps.d, ps.S, pin, qout, h->ppq, act, h->stream);
+}
+
 // Operator tile edge for a batch of S slices (0: 64, 1: 32).  RULE: 64 when
 // the batch fills the chip with such tiles.  AUTO: the first pass of each
 // batch width times the CG operator kernel in both variants on the pass's
@@ -577,6 +687,10 @@ int prof_drain(mgrit_handle* h) {
 // kernel sums its dot products per 32 x 32 block in one fixed order.
 int tile_variant(mgrit_handle* h, const Pass* ps, int S, int* tv, bool fp32 = false) {
     const int rule = (long long)S * h->geom.ntiles[0] >= 512 ? 0 : 1;
+    if (h->use_fft) {                                   // the FFT passes have no tiles
+        *tv = 0;
+        return 0;
+    }
     switch (h->opt.tile_policy) {
         case MGRIT_TILE_64: *tv = 0; return 0;
         case MGRIT_TILE_32: *tv = 1; return 0;
@@ -730,25 +844,25 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     CHK(tile_variant(h, nullptr, S, &tv));
     // Tiled kernels leave one partial sum per 32 x 32 block whatever their tile
     // size, so the reductions (and the iterates) do not depend on tv.
-    const int nt = g->ntiles[1], nc = g->nchunk;
+    const int nop = h->nop, npc = g->ntiles[1], nc = g->nchunk;   // partials: operator, preconditioner, vectors
     auto precondition = [&](double* prz_out, const int* act) -> int {
         if (pk == MGRIT_PRECOND_FD)
             return launch_fd_apply(g, &h->fd, tv, ps.d, S, h->r, h->z, h->t1, h->t2, prz_out, act, st);
         return launch_fdb_apply(g, &h->fdb, ps.d, S, h->r, h->z, h->tb1, h->tb2, prz_out, act, st);
     };
-    HIPCHK(launch_rhs(g, &h->seqs, tv, ps.d, S, ubase, fbase, h->b, h->pbb, st));
+    HIPCHK(op_rhs(h, tv, ps, ubase, fbase));
     CHK(tile_variant(h, &ps, S, &tv));
     HIPCHK(launch_cg_init_x(g, ps.d, S, ubase, x0base, (x0base && warm && h->opt.warm_start) ? 1 : 0, xbase, st));
-    HIPCHK(launch_init_residual(g, &h->seqs, tv, ps.d, S, xbase, h->b, h->r, h->prr[0], st));
+    HIPCHK(op_resid(h, tv, ps, xbase, h->prr[0]));
     if (pc) HIPCHK(precondition(h->prz[0], nullptr));
     double* zws = pc ? h->z : h->r;
     double** prho = pc ? h->prz : h->prr;        // rho = r.z (r.r without preconditioner)
-    HIPCHK(launch_cg_start(g, ps.d, S, ubase, xbase, zws, h->p, h->pbb, nt, h->prr[0], nt, rtol2, h->bb, h->act[0],
+    HIPCHK(launch_cg_start(g, ps.d, S, ubase, xbase, zws, h->p, h->pbb, nop, h->prr[0], nop, rtol2, h->bb, h->act[0],
                            h->iters, st));
     int cur = 0;
     int it = 0;
-    int nrho = nt;                               // entries of the current rho partials
-    const int nrho_next = pc ? nt : nc;
+    int nrho = pc ? npc : nop;                               // entries of the current rho partials
+    const int nrho_next = pc ? npc : nc;
     const int maxit = h->opt.cg_maxit;
     // The first chunk covers what this pass needed last time, later chunks are
     // short, so few launches find every slice converged.
@@ -756,9 +870,9 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     auto iter = [&](int c0, int nr) -> int {
         const int nxt = c0 ^ 1;
         if (h->prof_on) CHK(prof_record(h, tv));
-        HIPCHK(launch_cg_apply(g, &h->seqs, tv, ps.d, S, h->p, h->q, h->ppq, h->act[c0], st));
+        HIPCHK(op_cg(h, tv, ps, h->p, h->q, h->act[c0]));
         if (h->prof_on) CHK(prof_record(h, tv));
-        HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, prho[c0], nr, h->ppq, nt, h->prr[nxt],
+        HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, prho[c0], nr, h->ppq, nop, h->prr[nxt],
                                 h->act[c0], st));
         if (pc) HIPCHK(precondition(h->prz[nxt], h->act[c0]));
         HIPCHK(launch_cg_direction(g, S, zws, h->p, prho[c0], nr, prho[nxt], nrho_next, h->prr[nxt], h->bb, rtol2,
@@ -801,19 +915,19 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
     const double rtol2 = rtol * rtol;
     const double eta = h->opt.inner_rtol > 0.0 ? h->opt.inner_rtol : 1e-5;
     const bool pc = h->opt.precond == MGRIT_PRECOND_FD_BF16;
-    const int nt = g->ntiles[1], nc = g->nchunk;
+    const int nop = h->nop, npc = g->ntiles[1], nc = g->nchunk;
     const int maxit = h->opt.cg_maxit;
     int tv = 0, tv32 = -1;
     CHK(tile_variant(h, nullptr, S, &tv));
-    HIPCHK(launch_rhs(g, &h->seqs, tv, ps.d, S, ubase, fbase, h->b, h->pbb, st));
+    HIPCHK(op_rhs(h, tv, ps, ubase, fbase));
     CHK(tile_variant(h, &ps, S, &tv));
     HIPCHK(launch_cg_init_x(g, ps.d, S, ubase, x0base, (x0base && warm && h->opt.warm_start) ? 1 : 0, xbase, st));
-    HIPCHK(launch_init_residual(g, &h->seqs, tv, ps.d, S, xbase, h->b, h->r, h->pout, st));
+    HIPCHK(op_resid(h, tv, ps, xbase, h->pout));
     float* zws = pc ? h->z32 : h->r32;
     double** prho = pc ? h->prz : h->prr;        // rho = r.z (r.r without preconditioner)
     int steps = 0;
     for (int outer = 0; outer < 32; ++outer) {
-        HIPCHK(launch_mx_begin(g, ps.d, S, xbase, h->r, h->pbb, h->pout, nt, rtol2, eta * eta, outer == 0 ? 1 : 0,
+        HIPCHK(launch_mx_begin(g, ps.d, S, xbase, h->r, h->pbb, h->pout, nop, rtol2, eta * eta, outer == 0 ? 1 : 0,
                                h->bb, h->mx_scale, h->mx_eta2, h->mx_oact, h->act[0], h->iters, h->r32, h->d32,
                                pc ? nullptr : h->p32, h->prr[0], st));
         if (tv32 < 0) CHK(tile_variant(h, &ps, S, &tv32, true));
@@ -821,14 +935,14 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
             HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, h->p32, h->tb1, h->tb2, h->prz[0],
                                       h->act[0], st));
         int cur = 0, it = 0, nact = 0;
-        int nrho = pc ? nt : nc;
-        const int nrho_next = pc ? nt : nc;
+        int nrho = pc ? npc : nc;
+        const int nrho_next = pc ? npc : nc;
         auto iter = [&](int c0, int nr) -> int {
             const int nxt = c0 ^ 1;
             if (h->prof_on) CHK(prof_record(h, 2 + tv32));
-            HIPCHK(launch_apply32(g, &h->seqs32, tv32, ps.d, S, h->p32, h->q32, h->ppq, h->act[c0], st));
+            HIPCHK(op_cg32(h, tv32, ps, h->p32, h->q32, h->act[c0]));
             if (h->prof_on) CHK(prof_record(h, 2 + tv32));
-            HIPCHK(launch_mx_update(g, S, h->d32, h->r32, h->p32, h->q32, prho[c0], nr, h->ppq, nt, h->prr[nxt],
+            HIPCHK(launch_mx_update(g, S, h->d32, h->r32, h->p32, h->q32, prho[c0], nr, h->ppq, nop, h->prr[nxt],
                                     h->act[c0], st));
             if (pc)
                 HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, nullptr, h->tb1, h->tb2, h->prz[nxt],
@@ -849,7 +963,7 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
         steps += nact;
         ps.last_inner[std::min(outer, 3)] = it;
         HIPCHK(launch_mx_refine(g, ps.d, S, xbase, h->d32, h->mx_scale, h->mx_oact, st));
-        HIPCHK(launch_init_residual(g, &h->seqs, tv, ps.d, S, xbase, h->b, h->r, h->pout, st));
+        HIPCHK(op_resid(h, tv, ps, xbase, h->pout));
     }
     HIPCHK(launch_add_g(g, ps.d, S, xbase, gbase, st));
     HIPCHK(hipMemcpyAsync(h->h_iters, h->iters, S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -1074,6 +1188,7 @@ void mgrit_default_options(mgrit_options* o) {
     o->cg_rtol_coarse = 0.0;
     o->inner_rtol = 0.0;
     o->graphs = 0;
+    o->op = MGRIT_OP_DENSE;
 }
 
 const char* mgrit_last_error(void) { return g_err; }
@@ -1105,6 +1220,7 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
         return fail(MGRIT_EINVAL, "mixed precision takes precond NONE or FD_BF16");
     if (!(o.inner_rtol >= 0.0 && o.inner_rtol < 1.0)) return fail(MGRIT_EINVAL, "bad inner_rtol");
     if (o.graphs != 0 && o.graphs != 1) return fail(MGRIT_EINVAL, "graphs must be 0 or 1");
+    if (o.op < MGRIT_OP_AUTO || o.op > MGRIT_OP_FFT) return fail(MGRIT_EINVAL, "unknown operator kind");
     if (o.precond < MGRIT_PRECOND_NONE || o.precond > MGRIT_PRECOND_FD_BF16)
         return fail(MGRIT_EINVAL, "unknown preconditioner");
     if (!(o.cg_rtol_coarse >= 0.0 && o.cg_rtol_coarse < 1.0)) return fail(MGRIT_EINVAL, "bad cg_rtol_coarse");
@@ -1135,10 +1251,19 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
     g.stride = nx * ny;
     g.nchunk = (int)((g.stride + MGRIT_CHUNK - 1) / MGRIT_CHUNK);
     g.pmax = std::max(g.ntiles[1], g.nchunk);
+    const bool fft_fits = 2 * nx - 1 <= MGRIT_FFT_LEN && 2 * ny - 1 <= MGRIT_FFT_LEN;
+    if (o.op == MGRIT_OP_FFT && !fft_fits) {
+        delete h;
+        return fail(MGRIT_EINVAL, "the FFT operator takes n_x, n_y <= %d", (MGRIT_FFT_LEN + 1) / 2);
+    }
+    h->use_fft = o.op == MGRIT_OP_FFT || (o.op == MGRIT_OP_AUTO && fft_fits);
+    if (h->use_fft) g.pmax = std::max(g.pmax, (int)((nx + MGRIT_FFT_LINES - 1) / MGRIT_FFT_LINES));
+    h->nop = h->use_fft ? (int)((nx + MGRIT_FFT_LINES - 1) / MGRIT_FFT_LINES) : g.ntiles[1];
     g.seq_off_x = g.tiles_x[0] * 64 + 64 + MGRIT_KC;
     g.seq_off_y = g.tiles_y[0] * 64 + 64 + MGRIT_KC;
     g.mass = ((p.b - p.a) / p.Mx) * ((p.d - p.c) / p.My) / 12.0;
     int rc = build_sequences(h);
+    if (!rc && h->use_fft) rc = build_fft_plan(h);
     if (!rc && o.precond != MGRIT_PRECOND_NONE) rc = build_fd(h);
     if (!rc) rc = build_levels(h);
     if (!rc) rc = alloc_workspace(h, h->Smax);
@@ -1328,8 +1453,14 @@ int mgrit_apply(mgrit_handle* h, int nslices, const double* theta, double sign, 
     HIPCHK(hipMemcpyAsync(dd, hd.data(), nslices * sizeof(ApplyDesc), hipMemcpyHostToDevice, h->stream));
     int tv = 0;
     CHK(tile_variant(h, nullptr, nslices, &tv));
-    HIPCHK(launch_apply(&h->geom, &h->seqs, tv, (const ApplyDesc*)dd, nslices, dv, dout, da,
-                        sign, 0, nullptr, nullptr, (void*)h->stream));
+    if (h->use_fft) {
+        for (int s0 = 0; s0 < nslices; s0 += h->Smax)        // the x-pass workspace holds Smax slices
+            HIPCHK(launch_fft_apply(&h->geom, &h->plan, (const ApplyDesc*)dd + s0, std::min(h->Smax, nslices - s0),
+                                    dv, dout, da, sign, 0, nullptr, h->pfft, (void*)h->stream));
+    } else {
+        HIPCHK(launch_apply(&h->geom, &h->seqs, tv, (const ApplyDesc*)dd, nslices, dv, dout, da, sign, 0, nullptr,
+                            nullptr, (void*)h->stream));
+    }
     if (mem == MGRIT_MEM_HOST)
         HIPCHK(hipMemcpyAsync(out, dout, nslices * st * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -1401,6 +1532,12 @@ int mgrit_footprint(const mgrit_problem* p, const mgrit_options* o, int mem, siz
     if (pc) d += 2 * nx * nx + 2 * ny * ny + nx + ny;
     if (o->precond == MGRIT_PRECOND_FD_BF16) b += 4 * npx * npx + 4 * npy * npy + 4 * (npx + npy) + 4 * smax * npx * npy;
     if (mem == MGRIT_MEM_HOST) d += (2.0 * p->Nt + 2) * st;
+    const bool fft = o->op == MGRIT_OP_FFT ||
+                     (o->op == MGRIT_OP_AUTO && 2 * nx - 1 <= MGRIT_FFT_LEN && 2 * ny - 1 <= MGRIT_FFT_LEN);
+    if (fft) {
+        d += smax * st + 14.0 * MGRIT_FFT_LEN + smax * std::ceil(nx / MGRIT_FFT_LINES) * 7;   // x-pass ws, tables
+        if (o->precision != MGRIT_PREC_FP64) b += 4.0 * smax * st + 4.0 * 14 * MGRIT_FFT_LEN;
+    }
     if (o->precision != MGRIT_PREC_FP64) {
         b += 4.0 * (2 * (npx + 96) + 1) * 2 + 4.0 * (2 * (npy + 96) + 1) * 2;          // FP32 sequences
         b += 4.0 * 5 * smax * st + 20.0 * smax;                                        // FP32 workspace, flags

@@ -72,6 +72,23 @@ typedef struct {
     const float* A2y;
 } Seqs32;
 
+// Tables of the FFT operator (transform length 512, so n_x, n_y <= 256):
+// tw[k] = exp(-2 pi i k / 512) and, per direction, the spectra of the three
+// circulant-embedded kernels (A_1, A_2, A_2^T, scaled by K c and divided by
+// 512) as 3 x 512 interleaved complex values; FP32 copies for mixed precision.
+// nbx, nby: workgroups per slice of the x and y line passes (ceil(n / 14)).
+typedef struct {
+    const double* tw;
+    const double* kx;
+    const double* ky;
+    const float* tw32;
+    const float* kx32;
+    const float* ky32;
+    int nbx, nby;
+} FftPlan;
+#define MGRIT_FFT_LEN 512
+#define MGRIT_FFT_LINES 14
+
 // Device matrices of the fast-diagonalisation preconditioner (row-major):
 // Vx[k][i] = component k of eigenvector i (x), VxT its transpose, likewise y;
 // lx, ly the generalised eigenvalues.
@@ -169,6 +186,20 @@ int launch_mx_direction(const Geom* g, int S, const float* z32, float* p32, cons
 // x += scale[s] d32 where oact[s].
 int launch_mx_refine(const Geom* g, const PropDesc* desc, int S, double* xbase, const float* d32,
                      const double* scale, const int* oact, void* stream);
+
+// ---- operator by FFT (same results as the tiled kernels up to rounding; one
+// partial per workgroup of the y pass, nby per slice; pbuf: S slices) ----
+int launch_fft_apply(const Geom* g, const FftPlan* pl, const ApplyDesc* desc, int S, const double* vbase,
+                     double* outbase, const double* addbase, double sign, int dot_mode, double* partial,
+                     double* pbuf, void* stream);
+int launch_fft_rhs(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const double* ubase,
+                   const double* fbase, double* bws, double* partial_bb, double* pbuf, void* stream);
+int launch_fft_init_residual(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const double* xbase,
+                             const double* bws, double* rws, double* partial_rr, double* pbuf, void* stream);
+int launch_fft_cg_apply(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const double* pws,
+                        double* qws, double* partial_pq, const int* active, double* pbuf, void* stream);
+int launch_fft_apply32(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const float* p32, float* q32,
+                       double* partial_pq, const int* active, float* pbuf, void* stream);
 
 // x[s] += G[s] for slices with g >= 0.
 int launch_add_g(const Geom* g, const PropDesc* desc, int S, double* xbase, const double* gbase, void* stream);

@@ -20,6 +20,7 @@ COARSE = {"cn": 0, "be": 1, "cn2": 2, "opt": 3}
 PRECISION = {"fp64": 0, "mixed": 1, "mixed-coarse": 2}
 PRECOND = {"none": 0, "fd": 1, "fd-bf16": 2}
 TILE = {"auto": 0, "rule": 1, "64": 2, "32": 3}
+OPERATOR = {"auto": 0, "dense": 1, "fft": 2}
 
 
 class _Problem(ctypes.Structure):
@@ -37,7 +38,7 @@ class _Options(ctypes.Structure):
                 ("warm_start", ctypes.c_int),
                 ("divergence_factor", ctypes.c_double), ("tile_policy", ctypes.c_int),
                 ("cg_rtol_coarse", ctypes.c_double), ("inner_rtol", ctypes.c_double),
-                ("graphs", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("op", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -213,8 +214,10 @@ def make_problem(beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0)):
 
 def make_options(m=8, max_levels=30, relax="FCF", coarse="cn", precision="fp64", max_iter=100, tol_abs=1e-9,
                  tol_rel=0.0, cg_rtol=1e-9, cg_maxit=10000, precond="none", cg_rtol_adapt=0.0, warm_start=True,
-                 divergence_factor=0.0, tile="auto", cg_rtol_coarse=0.0, inner_rtol=0.0, graphs=False):
+                 divergence_factor=0.0, tile="auto", cg_rtol_coarse=0.0, inner_rtol=0.0, graphs=False,
+                 op="dense"):
     o = default_options()
+    o.op = OPERATOR[op]
     o.graphs = 1 if graphs else 0
     o.inner_rtol = float(inner_rtol)
     o.tile_policy = TILE[str(tile)]

@@ -435,3 +435,74 @@ def test_graph_replay_matches_direct_launches(precision, pc):
         res[graphs] = outs
     for (Ua, ca, ia), (Ub, cb, ib) in zip(res[False], res[True]):
         assert torch.equal(Ua, Ub) and ca == cb and ia == ib
+
+
+@pytest.mark.parametrize("geo", GEOMS)
+def test_fft_operator_apply_matches_oracle(geo):
+    """The operator by circulant-embedded FFTs equals the dense Toeplitz products to rounding."""
+    beta, gamma, Kx, Ky, Mx, My, dom = geo
+    mg = _mg()
+    prob = fem.Problem(beta, gamma, Kx, Ky, Mx, My, *dom)
+    op = fem.Operator(prob)
+    S = 5
+    v = wl.random_slices(11, S, prob.nx, prob.ny)
+    add = wl.random_slices(12, S, prob.nx, prob.ny)
+    theta = np.array([0.0, 1e-3, 0.5, -0.25, 7.0])
+    with mg.Solver(beta, gamma, Kx, Ky, Mx, My, wl.uniform_grid(8), domain=dom, m=2, op="fft") as s:
+        for sign, use_add in ((1.0, False), (-1.0, True)):
+            out = host(s.apply(theta, dev(v), sign=sign, add=dev(add) if use_add else None))
+            for k in range(S):
+                ref = sign * (op.apply_M(v[k]) + theta[k] * op.apply_A(v[k])) + (add[k] if use_add else 0.0)
+                assert np.abs(out[k] - ref).max() <= 1e-13 * np.abs(ref).max(), (k, sign)
+
+
+@pytest.mark.parametrize("level,coarse,precision", [(0, "cn", "fp64"), (1, "opt", "fp64"), (0, "cn", "mixed"),
+                                                    (1, "opt", "mixed")])
+def test_fft_operator_propagate_matches_oracle(level, coarse, precision):
+    mg = _mg()
+    beta, gamma, Kx, Ky, Mx, My = 0.65, 0.9, 2.0, 0.5, 97, 70
+    prob = fem.Problem(beta, gamma, Kx, Ky, Mx, My)
+    op = fem.Operator(prob)
+    t = wl.random_grid(24, 13)
+    o = omgrit.MGRIT(op, t, 4, max_levels=3, coarse=coarse, cg_rtol=1e-14)
+    steps = [1, 2, 5] if level else [1, 9, 24]
+    u = wl.random_slices(41, 3, prob.nx, prob.ny)
+    g = wl.random_slices(42, 3, prob.nx, prob.ny)
+    with mg.Solver(beta, gamma, Kx, Ky, Mx, My, t, m=4, max_levels=3, coarse=coarse, cg_rtol=1e-13,
+                   precond="fd-bf16", precision=precision, op="fft") as s:
+        out = host(s.propagate(level, steps, dev(u), dev(g)))
+    solver = propagator.CGSolver(op, 1e-14, 20000)
+    for i, k in enumerate(steps):
+        ref = propagator.cn_step(op, solver, t[k] - t[k - 1], u[i], g[i]) if level == 0 else o.psi(1, k, u[i]) + g[i]
+        assert rel(out[i], ref) <= 1e-10, (i, rel(out[i], ref))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fft_operator_solve_reaches_sequential(precision):
+    mg = _mg()
+    prob, t, F, psi0 = _random_problem(14, 64, beta=0.75, gamma=0.85, Mx=72, My=66, Kx=2.0, Ky=1.0)
+    op = fem.Operator(prob)
+    ref = propagator.sequential(op, propagator.CGSolver(op, 1e-14), t, F, psi0)
+    with mg.Solver(prob.beta, prob.gamma, 2.0, 1.0, prob.Mx, prob.My, t, m=4, max_levels=3, coarse="opt",
+                   precond="fd-bf16", cg_rtol=1e-13, cg_rtol_coarse=1e-3, tol_abs=0.0, tol_rel=1e-12, max_iter=40,
+                   precision=precision, op="fft") as s:
+        U, st, rc = s.solve(dev(F), dev(psi0))
+        assert rc == 0
+        assert rel(host(U), ref) <= 1e-10
+
+
+def test_fft_operator_full_size_sampled():
+    """255 x 255 (the largest FFT grid, 19 x 19 workgroups per pass, ragged last one): a batch of 130 slices
+    through the FFT operator equals the tiled operator (itself checked against the oracle)."""
+    mg = _mg()
+    W = wl.FP64_VCYCLE_255
+    nx = W["Mx"] - 1
+    v = dev(wl.random_slices(7, 130, nx, nx))
+    theta = np.linspace(-1.0, 3.0, 130)
+    common = (W["beta"], W["gamma"], W["Kx"], W["Ky"], W["Mx"], W["My"], wl.uniform_grid(16))
+    with mg.Solver(*common, m=4, op="fft") as s:
+        a = s.apply(theta, v)
+    with mg.Solver(*common, m=4, op="dense") as s:
+        b = s.apply(theta, v)
+    err = float((a - b).abs().max() / b.abs().max())
+    assert err <= 1e-13, err
