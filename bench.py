@@ -29,8 +29,10 @@ sys.path.insert(0, ROOT)
 METRIC = "space-time DOF/s at 1e-8 rel. error vs FP64 sequential"
 FP64_PEAK_TFLOPS = 78.6          # MI355X dense FP64 (matrix and vector)
 FP32_PEAK_TFLOPS = 157.3         # MI355X dense FP32 (matrix)
-HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
+HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_prop_apply64_fp64_vcycle_255_traffic.json")
+FFT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fft_line_vcycle_255_traffic.json")
 
 
 def cpu_baseline(W, t, F, psi0, steps, cg_rtol):
@@ -114,9 +116,9 @@ def main():
     ap.add_argument("--precond", default="fd-bf16")
     ap.add_argument("--max-levels", type=int, default=3)
     ap.add_argument("--tile", default="auto", help="operator tile policy: auto | rule | 64 | 32")
-    ap.add_argument("--precision", default="fp64", help="fp64 | mixed | mixed-coarse")
+    ap.add_argument("--precision", default="mixed", help="fp64 | mixed | mixed-coarse")
     ap.add_argument("--graphs", action="store_true", help="replay CG iteration pairs as HIP graphs")
-    ap.add_argument("--op", default="dense", help="operator: dense (matrix-core Toeplitz products) | fft | auto")
+    ap.add_argument("--op", default="auto", help="operator: dense (matrix-core Toeplitz products) | fft | auto")
     ap.add_argument("--inner-rtol", type=float, default=0.0, help="mixed precision: inner FP32 tolerance floor")
     ap.add_argument("--cg-rtol-coarse", type=float, default=1e-3,
                     help="CG tolerance on the coarse levels (0: --cg-rtol)")
@@ -194,36 +196,57 @@ def main():
 
     dof = nx * ny * Nt
     per_step = elapsed / args.steps
-    flops_per_apply = 6.0 * nx * nx * ny + 6.0 * nx * ny * ny
+    fft = args.op == "fft" or (args.op == "auto" and 2 * max(nx, ny) - 1 <= 512)
+    if fft:
+        # one operator application by FFT: per direction ceil(n_lines / 2) packed output pairs, each one
+        # forward and one inverse 512-point radix-8 transform (20736 flops as the kernel computes them) and
+        # the spectral combination with the three kernels (76 flops per frequency, 512 frequencies)
+        flops_per_apply = float(((ny + 1) // 2 + (nx + 1) // 2) * (2 * 20736 + 76 * 512))
+        names = ["k_fft_line<double,0,2> + <double,1,2> (CG operator by FFT, x and y passes, FP64)", "",
+                 "k_fft_line<float,0,2> + <float,1,2> (inner CG operator of mixed precision by FFT, FP32)", ""]
+        bound = "alu"
+        peaks = [FP64_PEAK_TFLOPS, FP64_PEAK_TFLOPS, FP32_VECTOR_PEAK_TFLOPS, FP32_VECTOR_PEAK_TFLOPS]
+        tfile = FFT_TRAFFIC_FILE
+    else:
+        # dense Toeplitz products: three factors per direction, 2 n flops per entry and factor
+        flops_per_apply = 6.0 * nx * nx * ny + 6.0 * nx * ny * ny
+        names = ["k_prop_apply<64,2> (CG operator, FP64 MFMA, 64-point tiles)",
+                 "k_prop_apply<32,2> (CG operator, FP64 MFMA, 32-point tiles)",
+                 "k_apply32<64> (inner CG operator of mixed precision, FP32 MFMA, 64-point tiles)",
+                 "k_apply32<32> (inner CG operator of mixed precision, FP32 MFMA, 32-point tiles)"]
+        bound = "mfma"
+        peaks = [FP64_PEAK_TFLOPS, FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS, FP32_PEAK_TFLOPS]
+        tfile = TRAFFIC_FILE
 
     def achieved(v):
         ms, n, sl = prof[v]
         return flops_per_apply * sl / (ms * 1e-3) / 1e12 if ms > 0 else None
 
     from paper_1805_06688_amd import profiling
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
-            tr = json.load(fh)
-        if tr.get("source_hash") == profiling.source_hash():
-            traffic = tr.get("bytes_per_launch")
     # dominant kernel: the operator variant with the most kernel time
-    names = ["k_prop_apply<64,2> (CG operator, FP64 MFMA, 64-point tiles)",
-             "k_prop_apply<32,2> (CG operator, FP64 MFMA, 32-point tiles)",
-             "k_apply32<64> (inner CG operator of mixed precision, FP32 MFMA, 64-point tiles)",
-             "k_apply32<32> (inner CG operator of mixed precision, FP32 MFMA, 32-point tiles)"]
-    peaks = [FP64_PEAK_TFLOPS, FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS, FP32_PEAK_TFLOPS]
     v0 = max(range(4), key=lambda v: prof[v][0])
+    traffic = None
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            tr = json.load(fh)
+        if tr.get("source_hash") == profiling.source_hash() and tr.get("variant") == v0:
+            traffic = tr.get("bytes_per_launch")
     ms0, n0, sl0 = prof[v0]
     a0 = achieved(v0)
-    roofline = {"bound": "mfma", "kernel": names[v0], "achieved": a0, "peak": peaks[v0], "unit": "TFLOP/s",
-                "frac": a0 / peaks[v0] if a0 else None, "traffic": traffic if v0 == 0 else None,
+    roofline = {"bound": bound, "kernel": names[v0], "achieved": a0, "peak": peaks[v0], "unit": "TFLOP/s",
+                "frac": a0 / peaks[v0] if a0 else None, "traffic": traffic,
                 "avg_launch_ms": ms0 / n0 if n0 else None, "launches": n0,
                 "slice_applies_per_launch": sl0 / n0 if n0 else None, "flops_per_slice_apply": flops_per_apply,
                 "other_variants": [{"kernel": names[v].split(" (")[0], "achieved_tflops": achieved(v),
                                     "launches": prof[v][1], "total_ms": prof[v][0],
                                     "avg_launch_ms": prof[v][0] / prof[v][1] if prof[v][1] else None}
                                    for v in range(4) if v != v0 and prof[v][1]]}
+    if fft and sl0:
+        # the same launches against HBM: bytes the operator must move (read v, write the result)
+        word = 8 if v0 < 2 else 4
+        byt = 2.0 * word * nx * ny * sl0 / n0
+        roofline["hbm_view"] = {"algorithmic_bytes_per_launch": byt,
+                                "achieved_GBps": byt / (ms0 / n0 * 1e-3) / 1e9, "peak_GBps": HBM_PEAK_GBPS}
     out = {"metric": METRIC, "value": dof / per_step, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": per_step * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f64+f32", "data": "synthetic",

@@ -157,7 +157,7 @@ typedef struct mgrit_handle mgrit_handle;
  * tol_abs = 1e-9, tol_rel = 0, cg_rtol = 1e-9 (the paper's tolerances, Section 3.2),
  * cg_maxit = 10000, precond = NONE, cg_rtol_adapt = 0, warm_start = 1,
  * divergence_factor = 0, tile_policy = AUTO, cg_rtol_coarse = 0, inner_rtol = 0,
- * graphs = 0, op = DENSE. */
+ * graphs = 0, op = AUTO. */
 void mgrit_default_options(mgrit_options* opt);
 
 /* Validate the problem, evaluate the Toeplitz generating sequences of Section 2

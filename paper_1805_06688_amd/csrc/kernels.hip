@@ -905,9 +905,11 @@ __global__ __launch_bounds__(NT) void k_zero_slices(Geom g, int S, const int* id
 // complex transform (real and imaginary part), and two output lines are
 // packed the same way for the inverse transform.  Transforms are radix-8
 // Stockham FFTs of FL = 512 points, one wavefront per transform, 8 points per
-// lane.  The x pass writes theta X to a workspace; the y pass adds theta Y and
-// applies the epilogue of the operator (mass stencil, sign, added vector,
-// dot-product partial) as the tiled kernels do.
+// lane.  The slice's theta scales the spectra, and the 7-point mass stencil
+// enters the x pass as three more (3-tap) kernels, so the x pass writes
+// M v + theta X to a workspace and the y pass adds theta Y and applies the
+// rest of the epilogue (sign, added vector, dot-product partial) as the tiled
+// kernels do.
 constexpr int FL = 512;
 constexpr int FJ = 14;               // output lines per workgroup
 constexpr int FNT = 512;             // threads per workgroup: 8 waves, one input pair each
@@ -1035,7 +1037,7 @@ __device__ __forceinline__ void fft_operands(const Geom& g, const void* desc, in
 }
 
 // One line pass of the FFT operator.  DIR 0: lines along x, writes
-// pbuf = theta X.  DIR 1: lines along y; out = add + sign (M v + pbuf + theta Y)
+// pbuf = M v + theta X.  DIR 1: lines along y; out = add + sign (pbuf + theta Y)
 // and, with dot_mode, the block's partial of v.out (1) or out.out (2).
 template <typename T, int DIR, int MODE>
 __global__ __launch_bounds__(FNT) void k_fft_line(Geom g, FftPlan pl, const void* __restrict__ desc, int S,
@@ -1055,6 +1057,8 @@ __global__ __launch_bounds__(FNT) void k_fft_line(Geom g, FftPlan pl, const void
     double theta_d;
     fft_operands<T, MODE>(g, desc, s, vbase, wsin, addbase, outbase, v, add, out, theta_d);
     const T theta = (T)theta_d;
+    const T sign = (T)sign_d;
+    constexpr int FE = (256 * FJ + FNT - 1) / FNT;   // epilogue elements per thread (n <= 256)
     T* P = pbuf + (long long)s * g.stride;
     const int nx = g.nx, ny = g.ny;
     const int n = DIR == 0 ? nx : ny;        // line length
@@ -1104,6 +1108,7 @@ __global__ __launch_bounds__(FNT) void k_fft_line(Geom g, FftPlan pl, const void
         const cpx<T>* Z1 = buf;              // lines oa - 1, oa
         const cpx<T>* Z2 = buf + FPAD;       // lines oa + 1, oa + 2
         const T half = (T)0.5;
+        const T mlen = (T)(g.mass / FL);     // spectra carry the 1 / FL of the inverse
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int k = lane + 64 * r, kk = (FL - k) & (FL - 1);
@@ -1113,7 +1118,20 @@ __global__ __launch_bounds__(FNT) void k_fft_line(Geom g, FftPlan pl, const void
             const cpx<T> v0 = {half * (z1.y + z1c.y), half * (z1c.x - z1.x)};
             const cpx<T> vp = {half * (z2.x + z2c.x), half * (z2.y - z2c.y)};
             const cpx<T> vq = {half * (z2.y + z2c.y), half * (z2c.x - z2.x)};
-            const cpx<T> c1 = K[k], c2 = K[FL + k], c3 = K[2 * FL + k];
+            cpx<T> c1 = K[k], c2 = K[FL + k], c3 = K[2 * FL + k];
+            c1 = {theta * c1.x, theta * c1.y};
+            c2 = {theta * c2.x, theta * c2.y};
+            c3 = {theta * c3.x, theta * c3.y};
+            if (DIR == 0) {
+                // the mass stencil as three more kernels of the x pass: 6 v + v(i-1) + v(i+1)
+                // on line j, v(i) + v(i+1) on line j+1, v(i) + v(i-1) on line j-1
+                const cpx<T> w = tw[k];
+                c1.x += mlen * (T(6) + T(2) * w.x);
+                c2.x += mlen * (T(1) + w.x);
+                c2.y -= mlen * w.y;
+                c3.x += mlen * (T(1) + w.x);
+                c3.y += mlen * w.y;
+            }
             const cpx<T> xa = cadd(cadd(cmul(c1, v0), cmul(c2, vp)), cmul(c3, vm));
             const cpx<T> xb = cadd(cadd(cmul(c1, vp), cmul(c2, vq)), cmul(c3, v0));
             // W = xa + i xb; the inverse transform is conj(FFT(conj W))
@@ -1129,8 +1147,8 @@ __global__ __launch_bounds__(FNT) void k_fft_line(Geom g, FftPlan pl, const void
             for (int r = 0; r < 8; ++r) {
                 const int pos = lane + 64 * r;
                 if (pos < n) {
-                    P[(long long)oa * nx + pos] = theta * a[r].x;
-                    if (ob < nl) P[(long long)ob * nx + pos] = -theta * a[r].y;
+                    P[(long long)oa * nx + pos] = a[r].x;
+                    if (ob < nl) P[(long long)ob * nx + pos] = -a[r].y;
                 }
             }
         }
@@ -1144,31 +1162,33 @@ __global__ __launch_bounds__(FNT) void k_fft_line(Geom g, FftPlan pl, const void
         for (int r = 0; r < 8; ++r) {
             const int pos = lane + 64 * r;
             if (pos < n) {
-                stg[pos * 15 + 2 * wave] = theta * a[r].x;
-                stg[pos * 15 + 2 * wave + 1] = -theta * a[r].y;
+                stg[pos * 15 + 2 * wave] = a[r].x;
+                stg[pos * 15 + 2 * wave + 1] = -a[r].y;
             }
         }
     }
-    __syncthreads();
-    const T mass = (T)g.mass, sign = (T)sign_d;
-    double dot = 0.0;
-    for (int idx = tid; idx < ny * FJ; idx += FNT) {
+    // operands of the epilogue, all loads issued before any store
+    T pv[FE], av[FE], cv[FE];
+#pragma unroll
+    for (int e = 0; e < FE; ++e) {
+        const int idx = tid + FNT * e;
         const int j = idx / FJ, c = idx - j * FJ, i = l0 + c;
-        if (i >= nx) continue;
+        const bool in = j < ny && i < nx;
         const long long o = (long long)j * nx + i;
-        const T cv = v[o];
-        const bool hl = i > 0, hr = i + 1 < nx, hd = j > 0, hu = j + 1 < ny;
-        T m7 = T(6) * cv;
-        m7 += hl ? v[o - 1] : T(0);
-        m7 += hr ? v[o + 1] : T(0);
-        m7 += hd ? v[o - nx] : T(0);
-        m7 += hu ? v[o + nx] : T(0);
-        m7 += (hr && hu) ? v[o + nx + 1] : T(0);
-        m7 += (hl && hd) ? v[o - nx - 1] : T(0);
-        T val = sign * (mass * m7 + (P[o] + stg[j * 15 + c]));
-        if (add) val += add[o];
-        out[o] = val;
-        if (dot_mode == 1) dot += (double)cv * (double)val;
+        pv[e] = in ? P[o] : T(0);
+        av[e] = (in && add) ? add[o] : T(0);
+        cv[e] = (in && dot_mode == 1) ? v[o] : T(0);
+    }
+    __syncthreads();
+    double dot = 0.0;
+#pragma unroll
+    for (int e = 0; e < FE; ++e) {
+        const int idx = tid + FNT * e;
+        const int j = idx / FJ, c = idx - j * FJ, i = l0 + c;
+        if (j >= ny || i >= nx) continue;
+        const T val = sign * (pv[e] + stg[j * 15 + c]) + av[e];
+        out[(long long)j * nx + i] = val;
+        if (dot_mode == 1) dot += (double)cv[e] * (double)val;
         else if (dot_mode == 2) dot += (double)val * (double)val;
     }
     if (dot_mode) {

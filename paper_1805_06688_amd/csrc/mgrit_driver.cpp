@@ -1188,7 +1188,7 @@ void mgrit_default_options(mgrit_options* o) {
     o->cg_rtol_coarse = 0.0;
     o->inner_rtol = 0.0;
     o->graphs = 0;
-    o->op = MGRIT_OP_DENSE;
+    o->op = MGRIT_OP_AUTO;
 }
 
 const char* mgrit_last_error(void) { return g_err; }

@@ -215,7 +215,7 @@ def make_problem(beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0)):
 def make_options(m=8, max_levels=30, relax="FCF", coarse="cn", precision="fp64", max_iter=100, tol_abs=1e-9,
                  tol_rel=0.0, cg_rtol=1e-9, cg_maxit=10000, precond="none", cg_rtol_adapt=0.0, warm_start=True,
                  divergence_factor=0.0, tile="auto", cg_rtol_coarse=0.0, inner_rtol=0.0, graphs=False,
-                 op="dense"):
+                 op="auto"):
     o = default_options()
     o.op = OPERATOR[op]
     o.graphs = 1 if graphs else 0

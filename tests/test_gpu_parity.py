@@ -58,7 +58,7 @@ def test_apply_matches_oracle(geo):
     v = wl.random_slices(11, S, prob.nx, prob.ny)
     add = wl.random_slices(12, S, prob.nx, prob.ny)
     theta = np.array([0.0, 1e-3, 0.5, -0.25, 7.0])
-    with mg.Solver(beta, gamma, Kx, Ky, Mx, My, wl.uniform_grid(8), domain=dom, m=2) as s:
+    with mg.Solver(beta, gamma, Kx, Ky, Mx, My, wl.uniform_grid(8), domain=dom, m=2, op="dense") as s:
         for sign, use_add in ((1.0, False), (-1.0, True)):
             out = host(s.apply(theta, dev(v), sign=sign, add=dev(add) if use_add else None))
             for k in range(S):
@@ -90,15 +90,16 @@ def test_propagate_level0_matches_oracle(geo):
     u = wl.random_slices(21, len(steps), prob.nx, prob.ny)
     F = wl.random_slices(22, len(steps), prob.nx, prob.ny)
     solver = propagator.CGSolver(op, 1e-14, 20000)
-    with mg.Solver(beta, gamma, Kx, Ky, Mx, My, t, domain=dom, m=2, cg_rtol=1e-14, cg_maxit=20000) as s:
+    with mg.Solver(beta, gamma, Kx, Ky, Mx, My, t, domain=dom, m=2, cg_rtol=1e-14, cg_maxit=20000, op="dense") as s:
         out = host(s.propagate(0, steps, dev(u), dev(F)))
     for i, k in enumerate(steps):
         ref = propagator.cn_step(op, solver, t[k] - t[k - 1], u[i], F[i])
         assert rel(out[i], ref) <= 1e-10, (i, k, rel(out[i], ref))
 
 
-@pytest.mark.parametrize("coarse", ["cn", "be", "cn2", "opt"])
-def test_propagate_coarse_level_matches_oracle(coarse):
+@pytest.mark.parametrize("coarse,opk", [("cn", "dense"), ("be", "dense"), ("cn2", "dense"), ("opt", "dense"),
+                                        ("cn", "fft"), ("opt", "fft")])
+def test_propagate_coarse_level_matches_oracle(coarse, opk):
     mg = _mg()
     beta, gamma, Kx, Ky, Mx, My = 0.75, 0.85, 2.0, 1.0, 70, 66
     prob = fem.Problem(beta, gamma, Kx, Ky, Mx, My)
@@ -109,7 +110,7 @@ def test_propagate_coarse_level_matches_oracle(coarse):
     steps = [1, 3, 8]
     u = wl.random_slices(31, 3, prob.nx, prob.ny)
     g = wl.random_slices(32, 3, prob.nx, prob.ny)
-    with mg.Solver(beta, gamma, Kx, Ky, Mx, My, t, m=m, max_levels=3, coarse=coarse, cg_rtol=1e-14) as s:
+    with mg.Solver(beta, gamma, Kx, Ky, Mx, My, t, m=m, max_levels=3, coarse=coarse, cg_rtol=1e-14, op=opk) as s:
         assert s.levels() == [32, 8, 2]
         out = host(s.propagate(1, steps, dev(u), dev(g)))
         out_nog = host(s.propagate(1, steps, dev(u)))
@@ -229,7 +230,7 @@ def test_full_size_apply_and_step_sampled():
     t = wl.uniform_grid(W["Nt"])
     u = wl.random_slices(5, 3, prob.nx, prob.ny)
     F = wl.random_slices(6, 3, prob.nx, prob.ny)
-    with mg.Solver(W["beta"], W["gamma"], W["Kx"], W["Ky"], W["Mx"], W["My"], t, m=W["m"], cg_rtol=1e-14) as s:
+    with mg.Solver(W["beta"], W["gamma"], W["Kx"], W["Ky"], W["Mx"], W["My"], t, m=W["m"], cg_rtol=1e-14, op="dense") as s:
         theta = np.array([0.5 / 1024, 4.0 / 1024, 0.0])
         out = host(s.apply(theta, dev(u)))
         steps = [1, 500, 1024]
@@ -257,7 +258,7 @@ def test_preconditioned_propagate_matches_oracle(level, coarse, pc):
     u = wl.random_slices(41, 3, prob.nx, prob.ny)
     g = wl.random_slices(42, 3, prob.nx, prob.ny)
     with mg.Solver(beta, gamma, Kx, Ky, Mx, My, t, m=4, max_levels=3, coarse=coarse, cg_rtol=1e-14,
-                   precond=pc) as s:
+                   precond=pc, op="dense") as s:
         out = host(s.propagate(level, steps, dev(u), dev(g)))
     solver = propagator.CGSolver(op, 1e-14, 20000)
     for i, k in enumerate(steps):
@@ -324,7 +325,8 @@ def test_tile_policy_changes_speed_only(pc):
     out = {}
     for tile in ("64", "32", "rule", "auto"):
         with mg.Solver(prob.beta, prob.gamma, 1.5, 1.0, prob.Mx, prob.My, t, m=4, max_levels=3, coarse="opt",
-                       precond=pc, cg_rtol=1e-12, tol_abs=0.0, tol_rel=1e-10, max_iter=30, tile=tile) as s:
+                       precond=pc, cg_rtol=1e-12, tol_abs=0.0, tol_rel=1e-10, max_iter=30, tile=tile,
+                       op="dense") as s:
             U, st, rc = s.solve(dev(F), dev(psi0))
             assert rc == 0
             out[tile] = (U.clone(), st.cg_iterations, st.iterations, st.history())
@@ -369,7 +371,7 @@ def test_mixed_precision_propagate_matches_oracle(level, coarse, pc):
     u = wl.random_slices(51, 3, prob.nx, prob.ny)
     g = wl.random_slices(52, 3, prob.nx, prob.ny)
     with mg.Solver(beta, gamma, Kx, Ky, Mx, My, t, m=4, max_levels=3, coarse=coarse, cg_rtol=1e-13,
-                   precond=pc, precision="mixed") as s:
+                   precond=pc, precision="mixed", op="dense") as s:
         out = host(s.propagate(level, steps, dev(u), dev(g)))
     solver = propagator.CGSolver(op, 1e-14, 20000)
     for i, k in enumerate(steps):
