@@ -39,7 +39,34 @@ def copy(mib=512, reps=8):
     print(f"copied {mib} MiB x {reps}: {mib * 1024} KiB read and {mib * 1024} KiB written per dispatch")
 
 
+def _demangle_template(name):
+    """Name and template arguments of a mangled kernel (bool, int, float and double arguments only)."""
+    m = re.match(r"_ZN12_GLOBAL__N_1(\d+)", name)
+    if not m:
+        return name
+    n = int(m.group(1))
+    rest = name[m.end():]
+    ident, rest = rest[:n], rest[n:]
+    if not rest.startswith("I"):
+        return ident
+    args, i = [], 1
+    while i < len(rest) and rest[i] != "E":
+        a = re.match(r"L([bi])(n?\d+)E", rest[i:])
+        if a:
+            v = a.group(2).replace("n", "-")
+            args.append(("true" if v == "1" else "false") if a.group(1) == "b" else v)
+            i += a.end()
+        elif rest[i] in "fd":
+            args.append("float" if rest[i] == "f" else "double")
+            i += 1
+        else:
+            return ident
+    return ident + "<" + ", ".join(args) + ">"
+
+
 def short_name(name):
+    if name.startswith("_Z"):
+        name = _demangle_template(name)
     name = name.replace("(anonymous namespace)::", "").replace("void ", "")
     return name.split("(")[0]
 
