@@ -119,6 +119,7 @@ def main():
     ap.add_argument("--tile", default="auto", help="operator tile policy: auto | rule | 64 | 32")
     ap.add_argument("--precision", default="mixed", help="fp64 | mixed | mixed-coarse")
     ap.add_argument("--graphs", action="store_true", help="replay CG iteration pairs as HIP graphs")
+    ap.add_argument("--coarse-relax", default=None, help="relaxation on levels >= 1: F | FCF (default: FCF)")
     ap.add_argument("--op", default="auto", help="operator: dense (matrix-core Toeplitz products) | fft | auto")
     ap.add_argument("--inner-rtol", type=float, default=0.0, help="mixed precision: inner FP32 tolerance floor")
     ap.add_argument("--cg-rtol-coarse", type=float, default=1e-3,
@@ -178,7 +179,8 @@ def main():
                      cg_maxit=100000,
                      tol_abs=0.0, tol_rel=args.tol_rel, max_iter=40, precond=args.precond,
                      cg_rtol_adapt=args.cg_adapt, tile=args.tile, cg_rtol_coarse=args.cg_rtol_coarse,
-                     precision=args.precision, inner_rtol=args.inner_rtol, graphs=args.graphs, op=args.op)
+                     precision=args.precision, inner_rtol=args.inner_rtol, graphs=args.graphs, op=args.op,
+                     coarse_relax=args.coarse_relax)
     U = torch.empty((Nt + 1) * nx * ny, dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
         s.solve(Fd, pd, out=U)
@@ -258,6 +260,7 @@ def main():
                       "cg_rtol_coarse": args.cg_rtol_coarse, "precision": args.precision,
                       "inner_rtol": args.inner_rtol, "refinements_per_solve": st.refinements,
                       "graphs": args.graphs, "operator": args.op,
+                      "coarse_relax": args.coarse_relax or "FCF",
                       "mgrit_iterations": st.iterations, "phi_per_solve": st.phi_applications,
                       "cg_iterations_per_solve": st.cg_iterations, "rel_l2_err_vs_fp64_sequential": err,
                       "sequential_dof_per_s": dof / seq_s if seq_s else None, "sequential_rel_l2_err": seq_err,

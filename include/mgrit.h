@@ -139,6 +139,7 @@ typedef struct {
     int graphs;             /* 1: replay pairs of CG iterations as HIP graphs captured on   */
                             /* first use (needs a non-NULL stream; results are unchanged)   */
     int op;                 /* MGRIT_OP_*                                                */
+    int coarse_relax;       /* relaxation on levels >= 1: MGRIT_RELAX_* (-1: as relax)   */
 } mgrit_options;
 
 typedef struct {
@@ -157,7 +158,7 @@ typedef struct mgrit_handle mgrit_handle;
  * tol_abs = 1e-9, tol_rel = 0, cg_rtol = 1e-9 (the paper's tolerances, Section 3.2),
  * cg_maxit = 10000, precond = NONE, cg_rtol_adapt = 0, warm_start = 1,
  * divergence_factor = 0, tile_policy = AUTO, cg_rtol_coarse = 0, inner_rtol = 0,
- * graphs = 0, op = AUTO. */
+ * graphs = 0, op = AUTO, coarse_relax = -1. */
 void mgrit_default_options(mgrit_options* opt);
 
 /* Validate the problem, evaluate the Toeplitz generating sequences of Section 2

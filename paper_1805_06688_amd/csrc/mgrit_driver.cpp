@@ -1010,7 +1010,8 @@ int f_relax(mgrit_handle* h, int l, int warm) {
 // warm: the level's state already holds an iterate (not the zero start).
 int relax(mgrit_handle* h, int l, int warm) {
     CHK(f_relax(h, l, warm));
-    if (h->opt.relax == MGRIT_RELAX_FCF) {
+    const int kind = (l > 0 && h->opt.coarse_relax >= 0) ? h->opt.coarse_relax : h->opt.relax;
+    if (kind == MGRIT_RELAX_FCF) {
         CHK(run_batch(h, l, h->lv[l].crelax, nullptr, warm));
         CHK(f_relax(h, l, 1));
     }
@@ -1189,6 +1190,7 @@ void mgrit_default_options(mgrit_options* o) {
     o->inner_rtol = 0.0;
     o->graphs = 0;
     o->op = MGRIT_OP_AUTO;
+    o->coarse_relax = -1;
 }
 
 const char* mgrit_last_error(void) { return g_err; }
@@ -1221,6 +1223,8 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
     if (!(o.inner_rtol >= 0.0 && o.inner_rtol < 1.0)) return fail(MGRIT_EINVAL, "bad inner_rtol");
     if (o.graphs != 0 && o.graphs != 1) return fail(MGRIT_EINVAL, "graphs must be 0 or 1");
     if (o.op < MGRIT_OP_AUTO || o.op > MGRIT_OP_FFT) return fail(MGRIT_EINVAL, "unknown operator kind");
+    if (o.coarse_relax != -1 && o.coarse_relax != MGRIT_RELAX_F && o.coarse_relax != MGRIT_RELAX_FCF)
+        return fail(MGRIT_EINVAL, "unknown coarse relaxation");
     if (o.precond < MGRIT_PRECOND_NONE || o.precond > MGRIT_PRECOND_FD_BF16)
         return fail(MGRIT_EINVAL, "unknown preconditioner");
     if (!(o.cg_rtol_coarse >= 0.0 && o.cg_rtol_coarse < 1.0)) return fail(MGRIT_EINVAL, "bad cg_rtol_coarse");

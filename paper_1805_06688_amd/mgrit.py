@@ -38,7 +38,7 @@ class _Options(ctypes.Structure):
                 ("warm_start", ctypes.c_int),
                 ("divergence_factor", ctypes.c_double), ("tile_policy", ctypes.c_int),
                 ("cg_rtol_coarse", ctypes.c_double), ("inner_rtol", ctypes.c_double),
-                ("graphs", ctypes.c_int), ("op", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("op", ctypes.c_int), ("coarse_relax", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -215,8 +215,9 @@ def make_problem(beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0)):
 def make_options(m=8, max_levels=30, relax="FCF", coarse="cn", precision="fp64", max_iter=100, tol_abs=1e-9,
                  tol_rel=0.0, cg_rtol=1e-9, cg_maxit=10000, precond="none", cg_rtol_adapt=0.0, warm_start=True,
                  divergence_factor=0.0, tile="auto", cg_rtol_coarse=0.0, inner_rtol=0.0, graphs=False,
-                 op="auto"):
+                 op="auto", coarse_relax=None):
     o = default_options()
+    o.coarse_relax = -1 if coarse_relax is None else RELAX[coarse_relax]
     o.op = OPERATOR[op]
     o.graphs = 1 if graphs else 0
     o.inner_rtol = float(inner_rtol)

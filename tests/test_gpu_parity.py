@@ -508,3 +508,17 @@ def test_fft_operator_full_size_sampled():
         b = s.apply(theta, v)
     err = float((a - b).abs().max() / b.abs().max())
     assert err <= 1e-13, err
+
+
+def test_coarse_f_relaxation_keeps_fixed_point():
+    """F-relaxation on the coarse levels (FCF on level 0) changes the convergence, not the solution."""
+    mg = _mg()
+    prob, t, F, psi0 = _random_problem(15, 64, beta=0.7, gamma=0.8, Mx=60, My=52, Kx=1.0, Ky=1.0)
+    op = fem.Operator(prob)
+    ref = propagator.sequential(op, propagator.CGSolver(op, 1e-14), t, F, psi0)
+    with mg.Solver(prob.beta, prob.gamma, 1.0, 1.0, prob.Mx, prob.My, t, m=4, max_levels=3, coarse="opt",
+                   precond="fd-bf16", cg_rtol=1e-13, tol_abs=0.0, tol_rel=1e-12, max_iter=40,
+                   coarse_relax="F") as s:
+        U, st, rc = s.solve(dev(F), dev(psi0))
+    assert rc == 0
+    assert rel(host(U), ref) <= 1e-10
