@@ -1040,10 +1040,9 @@ __device__ __forceinline__ void fft_operands(const Geom& g, const void* desc, in
 // pbuf = M v + theta X.  DIR 1: lines along y; out = add + sign (pbuf + theta Y)
 // and, with dot_mode, the block's partial of v.out (1) or out.out (2).
 template <typename T, int DIR, int MODE>
-__global__ __launch_bounds__(FNT) void k_fft_line(Geom g, FftPlan pl, const void* __restrict__ desc, int S,
-                                                  const T* vbase, const T* wsin, const T* addbase, T* outbase,
-                                                  T* pbuf, double sign_d, int dot_mode, double* partial,
-                                                  const int* active) {
+__device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const void* __restrict__ desc, int S,
+                                         const T* vbase, const T* wsin, const T* addbase, T* outbase, T* pbuf,
+                                         double sign_d, int dot_mode, double* partial, const int* active) {
     const int nb = DIR == 0 ? pl.nbx : pl.nby;
     int s, blk;
     decode_block(nb, S, s, blk);
@@ -1167,29 +1166,33 @@ __global__ __launch_bounds__(FNT) void k_fft_line(Geom g, FftPlan pl, const void
             }
         }
     }
-    // operands of the epilogue, all loads issued before any store
-    T pv[FE], av[FE], cv[FE];
-#pragma unroll
-    for (int e = 0; e < FE; ++e) {
-        const int idx = tid + FNT * e;
-        const int j = idx / FJ, c = idx - j * FJ, i = l0 + c;
-        const bool in = j < ny && i < nx;
-        const long long o = (long long)j * nx + i;
-        pv[e] = in ? P[o] : T(0);
-        av[e] = (in && add) ? add[o] : T(0);
-        cv[e] = (in && dot_mode == 1) ? v[o] : T(0);
-    }
     __syncthreads();
+    // epilogue in groups of FG elements per thread: the loads of a group are issued before its stores
+    constexpr int FG = 4;
     double dot = 0.0;
+#pragma unroll 1
+    for (int e0 = 0; e0 < FE; e0 += FG) {
+        T pv[FG], av[FG], cv[FG];
 #pragma unroll
-    for (int e = 0; e < FE; ++e) {
-        const int idx = tid + FNT * e;
-        const int j = idx / FJ, c = idx - j * FJ, i = l0 + c;
-        if (j >= ny || i >= nx) continue;
-        const T val = sign * (pv[e] + stg[j * 15 + c]) + av[e];
-        out[(long long)j * nx + i] = val;
-        if (dot_mode == 1) dot += (double)cv[e] * (double)val;
-        else if (dot_mode == 2) dot += (double)val * (double)val;
+        for (int q = 0; q < FG; ++q) {
+            const int idx = tid + FNT * (e0 + q);
+            const int j = idx / FJ, c = idx - j * FJ, i = l0 + c;
+            const bool in = e0 + q < FE && j < ny && i < nx;
+            const long long o = (long long)j * nx + i;
+            pv[q] = in ? P[o] : T(0);
+            av[q] = (in && add) ? add[o] : T(0);
+            cv[q] = (in && dot_mode == 1) ? v[o] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < FG; ++q) {
+            const int idx = tid + FNT * (e0 + q);
+            const int j = idx / FJ, c = idx - j * FJ, i = l0 + c;
+            if (e0 + q >= FE || j >= ny || i >= nx) continue;
+            const T val = sign * (pv[q] + stg[j * 15 + c]) + av[q];
+            out[(long long)j * nx + i] = val;
+            if (dot_mode == 1) dot += (double)cv[q] * (double)val;
+            else if (dot_mode == 2) dot += (double)val * (double)val;
+        }
     }
     if (dot_mode) {
         dot = block_sum8(dot, red);
@@ -1197,14 +1200,39 @@ __global__ __launch_bounds__(FNT) void k_fft_line(Geom g, FftPlan pl, const void
     }
 }
 
+template <typename T, int DIR, int MODE>
+__global__ __launch_bounds__(FNT) void k_fft_line(Geom g, FftPlan pl, const void* __restrict__ desc, int S,
+                                                  const T* vbase, const T* wsin, const T* addbase, T* outbase,
+                                                  T* pbuf, double sign_d, int dot_mode, double* partial,
+                                                  const int* active) {
+    fft_line<T, DIR, MODE>(g, pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign_d, dot_mode, partial, active);
+}
+
+// the FP32 instance with a register budget of three workgroups per compute unit
+template <int DIR, int MODE>
+__global__ __launch_bounds__(FNT, 6) void k_fft_line32(Geom g, FftPlan pl, const void* __restrict__ desc, int S,
+                                                       const float* vbase, const float* wsin, const float* addbase,
+                                                       float* outbase, float* pbuf, double sign_d, int dot_mode,
+                                                       double* partial, const int* active) {
+    fft_line<float, DIR, MODE>(g, pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign_d, dot_mode, partial,
+                               active);
+}
+
 template <typename T, int MODE>
 void fft_op(const Geom* g, const FftPlan* pl, const void* desc, int S, const T* vbase, const T* wsin,
             const T* addbase, T* outbase, T* pbuf, double sign, int dot_mode, double* partial, const int* active,
             hipStream_t st) {
-    hipLaunchKernelGGL((k_fft_line<T, 0, MODE>), dim3(grid_blocks(pl->nbx, S)), dim3(FNT), 0, st, *g, *pl, desc, S,
-                       vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
-    hipLaunchKernelGGL((k_fft_line<T, 1, MODE>), dim3(grid_blocks(pl->nby, S)), dim3(FNT), 0, st, *g, *pl, desc, S,
-                       vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
+    if constexpr (sizeof(T) == 4) {
+        hipLaunchKernelGGL((k_fft_line32<0, MODE>), dim3(grid_blocks(pl->nbx, S)), dim3(FNT), 0, st, *g, *pl, desc,
+                           S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
+        hipLaunchKernelGGL((k_fft_line32<1, MODE>), dim3(grid_blocks(pl->nby, S)), dim3(FNT), 0, st, *g, *pl, desc,
+                           S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
+    } else {
+        hipLaunchKernelGGL((k_fft_line<T, 0, MODE>), dim3(grid_blocks(pl->nbx, S)), dim3(FNT), 0, st, *g, *pl, desc,
+                           S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
+        hipLaunchKernelGGL((k_fft_line<T, 1, MODE>), dim3(grid_blocks(pl->nby, S)), dim3(FNT), 0, st, *g, *pl, desc,
+                           S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
+    }
 }
 
 template <int TT>

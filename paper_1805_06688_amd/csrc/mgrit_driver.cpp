@@ -963,6 +963,11 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
         steps += nact;
         ps.last_inner[std::min(outer, 3)] = it;
         HIPCHK(launch_mx_refine(g, ps.d, S, xbase, h->d32, h->mx_scale, h->mx_oact, st));
+        // A loose pass tolerance (at least 100 x the FP32 floor: coarse-level corrections) is met by
+        // the first inner solve, whose target is then the pass tolerance itself and whose residual
+        // agrees with the FP64 one to FP32 rounding: the FP64 check is skipped.  Tight tolerances
+        // (level 0, the fixed point) are always confirmed in FP64.
+        if (outer == 0 && rtol >= 100.0 * eta) break;
         HIPCHK(op_resid(h, tv, ps, xbase, h->pout));
     }
     HIPCHK(launch_add_g(g, ps.d, S, xbase, gbase, st));
