@@ -197,6 +197,27 @@ def main():
     err = None if Uref is None else float(torch.linalg.norm(U.view(Nt + 1, ny, nx) - Uref) / torch.linalg.norm(Uref))
     s.close()
 
+    # the plain FP64 form of the same solver (same options, FP64 inner solves), beside the chosen form
+    forms = None
+    if args.precision != "fp64" and not args.skip_reference:
+        with mgrit.Solver(*common, m=W["m"], max_levels=args.max_levels, coarse=args.coarse, cg_rtol=args.cg_rtol,
+                          cg_maxit=100000, tol_abs=0.0, tol_rel=args.tol_rel, max_iter=40, precond=args.precond,
+                          cg_rtol_coarse=args.cg_rtol_coarse, op=args.op, coarse_relax=args.coarse_relax) as s64:
+            U64 = torch.empty_like(U)
+            s64.solve(Fd, pd, out=U64)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                _, st64, rc64 = s64.solve(Fd, pd, out=U64)
+            torch.cuda.synchronize()
+            t64 = (time.perf_counter() - t1) / args.steps
+        err64 = float(torch.linalg.norm(U64.view(Nt + 1, ny, nx) - Uref) / torch.linalg.norm(Uref))
+        forms = {"fp64": {"dof_per_s": nx * ny * Nt / t64, "ms_per_step": t64 * 1e3, "rel_l2_err": err64,
+                          "mgrit_iterations": st64.iterations, "rc": rc64},
+                 args.precision: {"dof_per_s": nx * ny * Nt / (elapsed / args.steps),
+                                  "ms_per_step": elapsed / args.steps * 1e3, "rel_l2_err": err}}
+        del U64
+
     dof = nx * ny * Nt
     per_step = elapsed / args.steps
     fft = args.op == "fft" or (args.op == "auto" and 2 * max(nx, ny) - 1 <= 512)
@@ -266,6 +287,8 @@ def main():
                       "sequential_dof_per_s": dof / seq_s if seq_s else None, "sequential_rel_l2_err": seq_err,
                       "parallelism": "time (MGRIT), one GPU"},
            "roofline": roofline}
+    if forms:
+        out["forms"] = forms
     if not args.no_serving and not args.skip_reference:
         out["serving"] = serving(mgrit, wl, torch, 32, 4.0, 4, 64)
         out["many_instance"] = many_instance(mgrit, wl, torch, 16, 4)

@@ -65,6 +65,15 @@ FP64_TWOLEVEL_31 = dict(name="fp64-twolevel-31x31x64", beta=0.7, gamma=0.8, Kx=1
                         T=1.0, m=4, levels=2, amp=1.0)
 
 
+# The mixed-precision workload: 511 x 511 nodes, 4096 graded steps t_n = (n / N)^2 (time-dependent
+# propagators), beta, gamma ~ U(0.55, 0.95) from seed 3, K = 1, m = 8; F ~ N(0,1), psi_0 ~ U[0,1].
+def mixed_511(seed=3):
+    rng = np.random.default_rng(seed)
+    beta, gamma = (float(v) for v in rng.uniform(0.55, 0.95, 2))
+    return dict(name="mixed-511x511x4096-graded", beta=beta, gamma=gamma, Kx=1.0, Ky=1.0, Mx=512, My=512, Nt=4096,
+                T=1.0, m=8, seed=seed)
+
+
 def serving_trace(seed, n_requests, rate, n_range=(63, 255), nt_range=(64, 512), m=8):
     """Poisson arrivals (rate per second) of solves with n_x, n_y ~ U{n_range}, N_t ~ U{nt_range}
     (a multiple of m), beta, gamma ~ U(0.55, 0.95), K = 1, T = 1, uniform grid; F ~ N(0,1), psi_0 ~ U[0,1].

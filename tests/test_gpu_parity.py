@@ -522,3 +522,54 @@ def test_coarse_f_relaxation_keeps_fixed_point():
         U, st, rc = s.solve(dev(F), dev(psi0))
     assert rc == 0
     assert rel(host(U), ref) <= 1e-10
+
+
+def test_mixed_511_full_size_sampled():
+    """The 511 x 511 mixed-precision geometry (graded grid of 4096 steps; dense operator, FP32 matrix cores in
+    the inner solves): operator on sampled slices against the oracle; propagator steps of the mixed form equal
+    the FP64 form, and the oracle's operator confirms the FP64 step by its residual."""
+    mg = _mg()
+    W = wl.mixed_511()
+    prob = fem.Problem(W["beta"], W["gamma"], W["Kx"], W["Ky"], W["Mx"], W["My"])
+    op = fem.Operator(prob)
+    t = wl.graded_grid(W["Nt"])
+    u = wl.random_slices(7, 3, prob.nx, prob.ny)
+    F = wl.random_slices(8, 3, prob.nx, prob.ny)
+    steps = [1, 2048, 4096]
+    common = (W["beta"], W["gamma"], W["Kx"], W["Ky"], W["Mx"], W["My"], t)
+    opts = dict(m=W["m"], max_levels=3, coarse="opt", precond="fd-bf16", cg_rtol=1e-12)
+    with mg.Solver(*common, precision="fp64", **opts) as s:
+        theta = np.array([0.5 * (t[1] - t[0]), 0.5 * (t[-1] - t[-2]), 0.0])
+        out = host(s.apply(theta, dev(u)))
+        p64 = host(s.propagate(0, steps, dev(u), dev(F)))
+    with mg.Solver(*common, precision="mixed", **opts) as s:
+        p32 = host(s.propagate(0, steps, dev(u), dev(F)))
+    for k in range(3):
+        ref = op.apply_M(u[k]) + theta[k] * op.apply_A(u[k])
+        assert np.abs(out[k] - ref).max() <= 1e-13 * np.abs(ref).max()
+    for i, k in enumerate(steps):
+        tau = t[k] - t[k - 1]
+        rhs = op.apply_M(u[i]) - 0.5 * tau * op.apply_A(u[i]) + F[i]
+        res = op.apply_M(p64[i]) + 0.5 * tau * op.apply_A(p64[i]) - rhs
+        assert np.linalg.norm(res) <= 1e-11 * np.linalg.norm(rhs), (k, np.linalg.norm(res) / np.linalg.norm(rhs))
+        assert rel(p32[i], p64[i]) <= 1e-10, (k, rel(p32[i], p64[i]))
+
+
+def test_mixed_511_mgrit_reaches_fp64_sequential():
+    """511 x 511, graded grid (128 steps here), mixed-precision MGRIT against FP64 sequential stepping:
+    relative l2 <= 1e-8 (the bar of the mixed form)."""
+    mg = _mg()
+    W = wl.mixed_511()
+    Nt = 128
+    t = wl.graded_grid(Nt)
+    n = W["Mx"] - 1
+    F, psi0 = wl.random_inputs(W["seed"], Nt, n, n)
+    common = (W["beta"], W["gamma"], W["Kx"], W["Ky"], W["Mx"], W["My"], t)
+    with mg.Solver(*common, m=W["m"], precond="fd-bf16", cg_rtol=1e-13) as s:
+        ref, _, _ = s.sequential(dev(F), dev(psi0))
+    with mg.Solver(*common, m=W["m"], max_levels=3, coarse="opt", precond="fd-bf16", precision="mixed",
+                   cg_rtol=3e-10, cg_rtol_coarse=1e-3, tol_abs=0.0, tol_rel=1e-9, max_iter=40) as s:
+        U, st, rc = s.solve(dev(F), dev(psi0))
+    assert rc == 0
+    err = float(torch.linalg.norm(U - ref) / torch.linalg.norm(ref))
+    assert err <= 1e-8, err
