@@ -227,7 +227,7 @@ def main():
         # the spectral combination with the three kernels (76 flops per frequency, 512 frequencies)
         flops_per_apply = float(((ny + 1) // 2 + (nx + 1) // 2) * (2 * 20736 + 76 * 512))
         names = ["k_fft_line<double,0,2> + <double,1,2> (CG operator by FFT, x and y passes, FP64)", "",
-                 "k_fft_line<float,0,2> + <float,1,2> (inner CG operator of mixed precision by FFT, FP32)", ""]
+                 "k_fft_line32<0,2> + <1,2> (inner CG operator of mixed precision by FFT, FP32)", ""]
         bound = "alu"
         peaks = [FP64_PEAK_TFLOPS, FP64_PEAK_TFLOPS, FP32_VECTOR_PEAK_TFLOPS, FP32_VECTOR_PEAK_TFLOPS]
         tfile = FFT_TRAFFIC_FILE

@@ -573,3 +573,22 @@ def test_mixed_511_mgrit_reaches_fp64_sequential():
     assert rc == 0
     err = float(torch.linalg.norm(U - ref) / torch.linalg.norm(ref))
     assert err <= 1e-8, err
+
+
+@pytest.mark.parametrize("Mx,My,expect_fft", [(257, 40, True), (258, 40, False), (40, 257, True), (33, 258, False)])
+def test_operator_at_the_fft_size_limit(Mx, My, expect_fft):
+    """n = 256 is the largest grid line the 512-point transforms take (2n - 1 <= 512); one more node falls back
+    to the dense products under op = auto.  Both sides of the limit match the oracle."""
+    mg = _mg()
+    prob = fem.Problem(0.6, 0.9, 1.0, 2.0, Mx, My)
+    op = fem.Operator(prob)
+    v = wl.random_slices(21, 3, prob.nx, prob.ny)
+    theta = np.array([0.0, 0.01, 3.0])
+    with mg.Solver(0.6, 0.9, 1.0, 2.0, Mx, My, wl.uniform_grid(4), m=2) as s:
+        out = host(s.apply(theta, dev(v)))
+    for k in range(3):
+        ref = op.apply_M(v[k]) + theta[k] * op.apply_A(v[k])
+        assert np.abs(out[k] - ref).max() <= 1e-13 * np.abs(ref).max(), k
+    if not expect_fft:
+        with pytest.raises(mg.MgritError):
+            mg.Solver(0.6, 0.9, 1.0, 2.0, Mx, My, wl.uniform_grid(4), m=2, op="fft")
