@@ -119,6 +119,7 @@ def main():
     ap.add_argument("--tile", default="auto", help="operator tile policy: auto | rule | 64 | 32")
     ap.add_argument("--precision", default="mixed", help="fp64 | mixed | mixed-coarse")
     ap.add_argument("--graphs", action="store_true", help="replay CG iteration pairs as HIP graphs")
+    ap.add_argument("--relax", default="FCF", help="relaxation on level 0: F | FCF")
     ap.add_argument("--coarse-relax", default=None, help="relaxation on levels >= 1: F | FCF (default: FCF)")
     ap.add_argument("--op", default="auto", help="operator: dense (matrix-core Toeplitz products) | fft | auto")
     ap.add_argument("--inner-rtol", type=float, default=0.0, help="mixed precision: inner FP32 tolerance floor")
@@ -180,7 +181,7 @@ def main():
                      tol_abs=0.0, tol_rel=args.tol_rel, max_iter=40, precond=args.precond,
                      cg_rtol_adapt=args.cg_adapt, tile=args.tile, cg_rtol_coarse=args.cg_rtol_coarse,
                      precision=args.precision, inner_rtol=args.inner_rtol, graphs=args.graphs, op=args.op,
-                     coarse_relax=args.coarse_relax)
+                     coarse_relax=args.coarse_relax, relax=args.relax)
     U = torch.empty((Nt + 1) * nx * ny, dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
         s.solve(Fd, pd, out=U)
@@ -202,7 +203,8 @@ def main():
     if args.precision != "fp64" and not args.skip_reference:
         with mgrit.Solver(*common, m=W["m"], max_levels=args.max_levels, coarse=args.coarse, cg_rtol=args.cg_rtol,
                           cg_maxit=100000, tol_abs=0.0, tol_rel=args.tol_rel, max_iter=40, precond=args.precond,
-                          cg_rtol_coarse=args.cg_rtol_coarse, op=args.op, coarse_relax=args.coarse_relax) as s64:
+                          cg_rtol_coarse=args.cg_rtol_coarse, op=args.op, coarse_relax=args.coarse_relax,
+                          relax=args.relax) as s64:
             U64 = torch.empty_like(U)
             s64.solve(Fd, pd, out=U64)
             torch.cuda.synchronize()
@@ -275,7 +277,7 @@ def main():
            "warmup": args.warmup, "ms_per_step": per_step * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f64+f32", "data": "synthetic",
            "config": {"workload": W["name"], "nx": nx, "ny": ny, "Nt": Nt, "beta": W["beta"], "gamma": W["gamma"],
-                      "Kx": W["Kx"], "Ky": W["Ky"], "m": W["m"], "levels": levels, "relax": "FCF",
+                      "Kx": W["Kx"], "Ky": W["Ky"], "m": W["m"], "levels": levels, "relax": args.relax,
                       "coarse": args.coarse, "precond": args.precond, "cg_rtol": args.cg_rtol,
                       "tol_rel": args.tol_rel, "cg_rtol_adapt": args.cg_adapt, "tile": args.tile,
                       "cg_rtol_coarse": args.cg_rtol_coarse, "precision": args.precision,
