@@ -88,9 +88,9 @@ extern "C" {
 /* How the operator M_h + theta A_h is applied.  DENSE: the Toeplitz products
  * as dense contractions on the matrix cores (tiled kernels).  FFT: each
  * Toeplitz product along a grid line as a circulant convolution of length 512
- * by FFT (n_x, n_y <= 256; EINVAL otherwise), O(n^2 log n) per slice instead
- * of O(n^3); results agree with DENSE to rounding.  AUTO: FFT where it
- * applies, else DENSE. */
+ * (n_x, n_y <= 256) or 1024 (n_x, n_y <= 512; EINVAL beyond) by FFT,
+ * O(n^2 log n) per slice instead of O(n^3); results agree with DENSE to
+ * rounding.  AUTO: FFT where it applies, else DENSE. */
 #define MGRIT_OP_AUTO  0
 #define MGRIT_OP_DENSE 1
 #define MGRIT_OP_FFT   2

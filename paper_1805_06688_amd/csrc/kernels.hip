@@ -903,17 +903,21 @@ __global__ __launch_bounds__(NT) void k_zero_slices(Geom g, int S, const int* id
 // with c1, c2, c3 the kernels of A_1, A_2 and A_2^T; the pass over y does the
 // same along columns with the y kernels.  Two real lines travel as one
 // complex transform (real and imaginary part), and two output lines are
-// packed the same way for the inverse transform.  Transforms are radix-8
-// Stockham FFTs of FL = 512 points, one wavefront per transform, 8 points per
-// lane.  The slice's theta scales the spectra, and the 7-point mass stencil
+// packed the same way for the inverse transform.  Transforms are Stockham
+// FFTs of L = 512 points (three radix-8 passes) or 1024 points (radix 16, 8,
+// 8), one wavefront per transform, L / 64 points per lane.  The slice's theta scales the spectra, and the 7-point mass stencil
 // enters the x pass as three more (3-tap) kernels, so the x pass writes
 // M v + theta X to a workspace and the y pass adds theta Y and applies the
 // rest of the epilogue (sign, added vector, dot-product partial) as the tiled
 // kernels do.
-constexpr int FL = 512;
 constexpr int FJ = 14;               // output lines per workgroup
 constexpr int FNT = 512;             // threads per workgroup: 8 waves, one input pair each
-constexpr int FPAD = FL + FL / 8;    // padded LDS length of one transform
+template <int L>
+struct FftLen {
+    static constexpr int NP = L / 64;                     // points per lane
+    static constexpr int PAD = L + L / 8;                 // padded LDS length of one transform
+    static constexpr int FE = (L / 2 * FJ + FNT - 1) / FNT;   // epilogue elements per thread (n <= L / 2)
+};
 
 template <typename T>
 struct cpx {
@@ -995,6 +999,82 @@ __device__ __forceinline__ void fft512(cpx<T>* a, cpx<T>* buf, const cpx<T>* __r
     __builtin_amdgcn_wave_barrier();
 }
 
+// Forward DFT of 16 points: a[n] +- a[n + 8] (the odd half times exp(-2 pi i n / 16)),
+// then two DFTs of 8; even outputs from the first, odd from the second.
+template <typename T>
+__device__ __forceinline__ void dft16(cpx<T>* a) {
+    const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173, h = (T)0.70710678118654752440;
+    const cpx<T> w[8] = {{T(1), T(0)}, {c1, -s1}, {h, -h}, {s1, -c1}, {T(0), T(-1)}, {-s1, -c1}, {-h, -h}, {-c1, -s1}};
+    cpx<T> b[8], c[8];
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+        b[n] = cadd(a[n], a[n + 8]);
+        c[n] = cmul(csub(a[n], a[n + 8]), w[n]);
+    }
+    dft8(b);
+    dft8(c);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        a[2 * k] = b[k];
+        a[2 * k + 1] = c[k];
+    }
+}
+
+// Forward FFT of 1024 points, a[m] = x[lane + 64 m] on entry and X[lane + 64 m] on return
+// (m < 16): a radix-16 pass, then two radix-8 passes of two butterflies per lane
+// (butterflies j = lane and lane + 64).
+template <typename T>
+__device__ __forceinline__ void fft1024(cpx<T>* a, cpx<T>* buf, const cpx<T>* __restrict__ tw, int lane) {
+    dft16(a);                                             // length 1 -> 16
+#pragma unroll
+    for (int r = 0; r < 16; ++r) buf[fpidx(16 * lane + r)] = a[r];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {                // 16 -> 128
+        const int j = lane + 64 * half;
+        cpx<T>* v = a + 8 * half;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = buf[fpidx(j + 128 * r)];
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int j = lane + 64 * half;
+        cpx<T>* v = a + 8 * half;
+        twiddle8(v, tw[(j & 15) * 8]);
+        dft8(v);
+        const int d = (j >> 4) * 128 + (j & 15);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) buf[fpidx(d + 16 * r)] = v[r];
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {                // 128 -> 1024
+        const int j = lane + 64 * half;
+        cpx<T>* v = a + 8 * half;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = buf[fpidx(j + 128 * r)];
+        twiddle8(v, tw[j]);
+        dft8(v);
+    }
+    // butterfly `half` holds X[lane + 64 half + 128 r] in a[8 half + r]: interleave to a[m], m = 2 r + half
+    cpx<T> t[16];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        t[2 * r] = a[r];
+        t[2 * r + 1] = a[8 + r];
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) a[m] = t[m];
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T, int L>
+__device__ __forceinline__ void fft(cpx<T>* a, cpx<T>* buf, const cpx<T>* __restrict__ tw, int lane) {
+    if constexpr (L == 512) fft512(a, buf, tw, lane);
+    else fft1024(a, buf, tw, lane);
+}
+
 // Sum over a 512-thread block in a fixed order.
 __device__ __forceinline__ double block_sum8(double v, double* red) {
     v = wave_sum(v);
@@ -1039,7 +1119,7 @@ __device__ __forceinline__ void fft_operands(const Geom& g, const void* desc, in
 // One line pass of the FFT operator.  DIR 0: lines along x, writes
 // pbuf = M v + theta X.  DIR 1: lines along y; out = add + sign (pbuf + theta Y)
 // and, with dot_mode, the block's partial of v.out (1) or out.out (2).
-template <typename T, int DIR, int MODE>
+template <typename T, int DIR, int MODE, int L>
 __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const void* __restrict__ desc, int S,
                                          const T* vbase, const T* wsin, const T* addbase, T* outbase, T* pbuf,
                                          double sign_d, int dot_mode, double* partial, const int* active) {
@@ -1048,6 +1128,7 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
     decode_block(nb, S, s, blk);
     if (s < 0) return;
     if (MODE == 2 && active && !active[s]) return;
+    constexpr int NP = FftLen<L>::NP, FPAD = FftLen<L>::PAD, FL = L;
     __shared__ __attribute__((aligned(16))) cpx<T> lds[8 * FPAD];
     __shared__ double red[8];
     const T* v;
@@ -1057,7 +1138,7 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
     fft_operands<T, MODE>(g, desc, s, vbase, wsin, addbase, outbase, v, add, out, theta_d);
     const T theta = (T)theta_d;
     const T sign = (T)sign_d;
-    constexpr int FE = (256 * FJ + FNT - 1) / FNT;   // epilogue elements per thread (n <= 256)
+    constexpr int FE = FftLen<L>::FE;
     T* P = pbuf + (long long)s * g.stride;
     const int nx = g.nx, ny = g.ny;
     const int n = DIR == 0 ? nx : ny;        // line length
@@ -1071,10 +1152,10 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
 
     // ---- load the input pair of this wave: lines la = l0 - 1 + 2 wave and la + 1 ----
     const int la = l0 - 1 + 2 * wave, lb = la + 1;
-    cpx<T> a[8];
+    cpx<T> a[NP];
     if (DIR == 0) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < NP; ++r) {
             const int pos = lane + 64 * r;
             a[r].x = (la >= 0 && la < nl && pos < n) ? v[(long long)la * nx + pos] : T(0);
             a[r].y = (lb >= 0 && lb < nl && pos < n) ? v[(long long)lb * nx + pos] : T(0);
@@ -1088,16 +1169,16 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < NP; ++r) {
             const int pos = lane + 64 * r;
             a[r].x = pos < n ? stg[pos * 17 + 2 * wave] : T(0);
             a[r].y = pos < n ? stg[pos * 17 + 2 * wave + 1] : T(0);
         }
         __syncthreads();
     }
-    fft512(a, buf, tw, lane);
+    fft<T, L>(a, buf, tw, lane);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) buf[fpidx(lane + 64 * r)] = a[r];
+    for (int r = 0; r < NP; ++r) buf[fpidx(lane + 64 * r)] = a[r];
     __syncthreads();
 
     // ---- spectra of the output pair (lines oa = l0 + 2 wave, ob = oa + 1) ----
@@ -1109,7 +1190,7 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
         const T half = (T)0.5;
         const T mlen = (T)(g.mass / FL);     // spectra carry the 1 / FL of the inverse
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < NP; ++r) {
             const int k = lane + 64 * r, kk = (FL - k) & (FL - 1);
             const cpx<T> z1 = Z1[fpidx(k)], z1c = Z1[fpidx(kk)], z2 = Z2[fpidx(k)], z2c = Z2[fpidx(kk)];
             // unpack: first line (z + conj z(-k)) / 2, second line (z - conj z(-k)) / (2 i)
@@ -1138,12 +1219,12 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
         }
     }
     __syncthreads();
-    if (work) fft512(a, buf, tw, lane);      // a[r] = conj of the packed output at lane + 64 r
+    if (work) fft<T, L>(a, buf, tw, lane);      // a[r] = conj of the packed output at lane + 64 r
 
     if (DIR == 0) {
         if (work) {
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
+            for (int r = 0; r < NP; ++r) {
                 const int pos = lane + 64 * r;
                 if (pos < n) {
                     P[(long long)oa * nx + pos] = a[r].x;
@@ -1158,7 +1239,7 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
     T* stg = (T*)lds;
     if (work) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < NP; ++r) {
             const int pos = lane + 64 * r;
             if (pos < n) {
                 stg[pos * 15 + 2 * wave] = a[r].x;
@@ -1200,39 +1281,53 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
     }
 }
 
-template <typename T, int DIR, int MODE>
+template <typename T, int DIR, int MODE, int L>
 __global__ __launch_bounds__(FNT) void k_fft_line(Geom g, FftPlan pl, const void* __restrict__ desc, int S,
                                                   const T* vbase, const T* wsin, const T* addbase, T* outbase,
                                                   T* pbuf, double sign_d, int dot_mode, double* partial,
                                                   const int* active) {
-    fft_line<T, DIR, MODE>(g, pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign_d, dot_mode, partial, active);
+    fft_line<T, DIR, MODE, L>(g, pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign_d, dot_mode, partial,
+                              active);
 }
 
-// the FP32 instance with a register budget of three workgroups per compute unit
-template <int DIR, int MODE>
-__global__ __launch_bounds__(FNT, 6) void k_fft_line32(Geom g, FftPlan pl, const void* __restrict__ desc, int S,
-                                                       const float* vbase, const float* wsin, const float* addbase,
-                                                       float* outbase, float* pbuf, double sign_d, int dot_mode,
-                                                       double* partial, const int* active) {
-    fft_line<float, DIR, MODE>(g, pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign_d, dot_mode, partial,
-                               active);
+// the FP32 instance with a register budget of three (L = 512) or two workgroups per compute unit
+template <int DIR, int MODE, int L>
+__global__ __launch_bounds__(FNT, L == 512 ? 6 : 4) void k_fft_line32(Geom g, FftPlan pl, const void* __restrict__ desc,
+                                                                      int S, const float* vbase, const float* wsin,
+                                                                      const float* addbase, float* outbase,
+                                                                      float* pbuf, double sign_d, int dot_mode,
+                                                                      double* partial, const int* active) {
+    fft_line<float, DIR, MODE, L>(g, pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign_d, dot_mode, partial,
+                                  active);
+}
+
+template <typename T, int MODE, int L>
+void fft_op_len(const Geom* g, const FftPlan* pl, const void* desc, int S, const T* vbase, const T* wsin,
+                const T* addbase, T* outbase, T* pbuf, double sign, int dot_mode, double* partial,
+                const int* active, hipStream_t st) {
+    if constexpr (sizeof(T) == 4) {
+        hipLaunchKernelGGL((k_fft_line32<0, MODE, L>), dim3(grid_blocks(pl->nbx, S)), dim3(FNT), 0, st, *g, *pl,
+                           desc, S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
+        hipLaunchKernelGGL((k_fft_line32<1, MODE, L>), dim3(grid_blocks(pl->nby, S)), dim3(FNT), 0, st, *g, *pl,
+                           desc, S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
+    } else {
+        hipLaunchKernelGGL((k_fft_line<T, 0, MODE, L>), dim3(grid_blocks(pl->nbx, S)), dim3(FNT), 0, st, *g, *pl,
+                           desc, S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
+        hipLaunchKernelGGL((k_fft_line<T, 1, MODE, L>), dim3(grid_blocks(pl->nby, S)), dim3(FNT), 0, st, *g, *pl,
+                           desc, S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
+    }
 }
 
 template <typename T, int MODE>
 void fft_op(const Geom* g, const FftPlan* pl, const void* desc, int S, const T* vbase, const T* wsin,
             const T* addbase, T* outbase, T* pbuf, double sign, int dot_mode, double* partial, const int* active,
             hipStream_t st) {
-    if constexpr (sizeof(T) == 4) {
-        hipLaunchKernelGGL((k_fft_line32<0, MODE>), dim3(grid_blocks(pl->nbx, S)), dim3(FNT), 0, st, *g, *pl, desc,
-                           S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
-        hipLaunchKernelGGL((k_fft_line32<1, MODE>), dim3(grid_blocks(pl->nby, S)), dim3(FNT), 0, st, *g, *pl, desc,
-                           S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
-    } else {
-        hipLaunchKernelGGL((k_fft_line<T, 0, MODE>), dim3(grid_blocks(pl->nbx, S)), dim3(FNT), 0, st, *g, *pl, desc,
-                           S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
-        hipLaunchKernelGGL((k_fft_line<T, 1, MODE>), dim3(grid_blocks(pl->nby, S)), dim3(FNT), 0, st, *g, *pl, desc,
-                           S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
-    }
+    if (pl->L == 512)
+        fft_op_len<T, MODE, 512>(g, pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial,
+                                 active, st);
+    else
+        fft_op_len<T, MODE, 1024>(g, pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial,
+                                  active, st);
 }
 
 template <int TT>

@@ -427,8 +427,9 @@ int build_sequences(mgrit_handle* h) {
 // length L (c(m) at m mod L, |m| < n) and transformed by a direct DFT in
 // extended precision; the spectra are divided by L for the inverse.
 int build_fft_plan(mgrit_handle* h) {
-    const int L = MGRIT_FFT_LEN;
     const Geom& g = h->geom;
+    const int L = (2 * std::max(g.nx, g.ny) - 1 <= 512) ? 512 : 1024;
+    h->plan.L = L;
     std::vector<long double> cs(L), sn(L);
     const long double pi = 3.141592653589793238462643383279502884L;
     for (int k = 0; k < L; ++k) {

@@ -72,11 +72,12 @@ typedef struct {
     const float* A2y;
 } Seqs32;
 
-// Tables of the FFT operator (transform length 512, so n_x, n_y <= 256):
-// tw[k] = exp(-2 pi i k / 512) and, per direction, the spectra of the three
-// circulant-embedded kernels (A_1, A_2, A_2^T, scaled by K c and divided by
-// 512) as 3 x 512 interleaved complex values; FP32 copies for mixed precision.
-// nbx, nby: workgroups per slice of the x and y line passes (ceil(n / 14)).
+// Tables of the FFT operator (transform length L = 512 when 2 n - 1 <= 512 for
+// both directions, else 1024, so n_x, n_y <= 512): tw[k] = exp(-2 pi i k / L)
+// and, per direction, the spectra of the three circulant-embedded kernels
+// (A_1, A_2, A_2^T, scaled by K c and divided by L) as 3 x L interleaved complex
+// values; FP32 copies for mixed precision.  nbx, nby: workgroups per slice of
+// the x and y line passes (ceil(n / 14)).
 typedef struct {
     const double* tw;
     const double* kx;
@@ -85,8 +86,9 @@ typedef struct {
     const float* kx32;
     const float* ky32;
     int nbx, nby;
+    int L;
 } FftPlan;
-#define MGRIT_FFT_LEN 512
+#define MGRIT_FFT_LEN 1024
 #define MGRIT_FFT_LINES 14
 
 // Device matrices of the fast-diagonalisation preconditioner (row-major):

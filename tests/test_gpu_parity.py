@@ -524,7 +524,8 @@ def test_coarse_f_relaxation_keeps_fixed_point():
     assert rel(host(U), ref) <= 1e-10
 
 
-def test_mixed_511_full_size_sampled():
+@pytest.mark.parametrize("opk", ["auto", "dense"])
+def test_mixed_511_full_size_sampled(opk):
     """The 511 x 511 mixed-precision geometry (graded grid of 4096 steps; dense operator, FP32 matrix cores in
     the inner solves): operator on sampled slices against the oracle; propagator steps of the mixed form equal
     the FP64 form, and the oracle's operator confirms the FP64 step by its residual."""
@@ -537,7 +538,7 @@ def test_mixed_511_full_size_sampled():
     F = wl.random_slices(8, 3, prob.nx, prob.ny)
     steps = [1, 2048, 4096]
     common = (W["beta"], W["gamma"], W["Kx"], W["Ky"], W["Mx"], W["My"], t)
-    opts = dict(m=W["m"], max_levels=3, coarse="opt", precond="fd-bf16", cg_rtol=1e-12)
+    opts = dict(m=W["m"], max_levels=3, coarse="opt", precond="fd-bf16", cg_rtol=1e-12, op=opk)
     with mg.Solver(*common, precision="fp64", **opts) as s:
         theta = np.array([0.5 * (t[1] - t[0]), 0.5 * (t[-1] - t[-2]), 0.0])
         out = host(s.apply(theta, dev(u)))
@@ -575,10 +576,11 @@ def test_mixed_511_mgrit_reaches_fp64_sequential():
     assert err <= 1e-8, err
 
 
-@pytest.mark.parametrize("Mx,My,expect_fft", [(257, 40, True), (258, 40, False), (40, 257, True), (33, 258, False)])
-def test_operator_at_the_fft_size_limit(Mx, My, expect_fft):
-    """n = 256 is the largest grid line the 512-point transforms take (2n - 1 <= 512); one more node falls back
-    to the dense products under op = auto.  Both sides of the limit match the oracle."""
+@pytest.mark.parametrize("Mx,My,expect_fft", [(257, 40, True), (258, 40, True), (40, 513, True), (514, 33, False)])
+def test_operator_at_the_fft_size_limits(Mx, My, expect_fft):
+    """n = 256 is the largest grid line of the 512-point transforms (2n - 1 <= 512) and n = 512 of the 1024-point
+    ones; one more node falls back to the dense products under op = auto.  All sides of the limits match the
+    oracle."""
     mg = _mg()
     prob = fem.Problem(0.6, 0.9, 1.0, 2.0, Mx, My)
     op = fem.Operator(prob)

@@ -54,7 +54,7 @@ def test_host_scale_equals_oracle():
     (dict(domain=(1.0, 0.0, 0.0, 1.0)), -1), (dict(m=1), -1), (dict(max_levels=1), -1),
     (dict(t=[0.0, 0.5, 0.5, 1.0]), -1), (dict(t=[0.1, 0.5, 1.0]), -1), (dict(coarse="zz"), None),
     (dict(tile="48"), None), (dict(precision="mixed", precond="fd"), -1), (dict(inner_rtol=1.0), -1),
-    (dict(op="fft", Mx=300), -1),
+    (dict(op="fft", Mx=600), -1),
 ])
 def test_setup_rejects_invalid_arguments(kw, code):
     mg = _lib()
