@@ -709,9 +709,11 @@ __global__ __launch_bounds__(NT) void k_fd_gemm(Geom g, int S, const double* __r
 // accumulator element r of lane l holds D[4 (l/16) + r][l % 16].
 // Operands are zero-padded to npx x npy (multiples of 64) so the products need
 // no bounds checks except on the FP64 input r and the FP64 output z.
-// LEFT:  Y[s] = A X[s], A[i][k] row-major (ld npx)        RIGHT: Y[s] = X[s] B, B^T[j][k] row-major (ld npy)
+// LEFT:  Y[s] = A X[s], A[i][k] row-major (ld npx)        RIGHT: Y[s] = X[s] B, B^T[j][k] row-major (ld npy),
+//        X given transposed (X^T[i][k], ld npy)
 // IN 0: X = r [ny][nx] (RT = FP64, or FP32 in the inner solves of mixed precision);  IN 1: X = BF16 padded
-// EPI 0: Y BF16 padded; 1: scaled by 1 / (1 + theta (lx + ly)), BF16 padded; 2: Y = z [ny][nx] (RT) + r.z,
+// EPI 0: Y BF16 padded, transposed ([i][j], ld npy); 1: scaled by 1 / (1 + theta (lx + ly)), BF16 padded
+//        ([j][i], ld npx); 2: Y = z [ny][nx] (RT) + r.z,
 //        also copied to ycopy when given
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
@@ -723,6 +725,9 @@ union Pack8 {
     __bf16 h[8];
 };
 
+// The BF16 intermediates between the products are stored transposed ([i][j],
+// y fastest) after a product over x, so that the next product, over y, reads
+// its operand rows directly instead of transposing them through LDS.
 template <bool LEFT, int IN, int EPI, typename RT>
 __global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __restrict__ mat,
                                                  const void* __restrict__ xin, void* __restrict__ yout,
@@ -762,13 +767,10 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __
             if (LEFT) {
                 const int ii = idx >> 3, kv = idx & 7;
                 *(uint4*)&As[ii * BLD + 8 * kv] = *(const uint4*)&mat[(long long)(i0 + ii) * npx + k0 + 8 * kv];
-            } else {
-                const int kk = idx >> 3, iv = idx & 7;
+            } else {                                    // X^T[i][k], stored transposed by the product before
+                const int ii = idx >> 3, kv = idx & 7;
                 const __bf16* X = (const __bf16*)xin + sob;
-                Pack8 pk;
-                pk.u = *(const uint4*)&X[(long long)(k0 + kk) * npx + i0 + 8 * iv];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) As[(8 * iv + e) * BLD + kk] = pk.h[e];
+                *(uint4*)&As[ii * BLD + 8 * kv] = *(const uint4*)&X[(long long)(i0 + ii) * npy + k0 + 8 * kv];
             }
         }
         // B tile ([j][k])
@@ -817,6 +819,13 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __
                 epi[jl * 65 + il] = acc[fi][fj][r];
             }
     __syncthreads();
+    if (EPI == 0) {                                           // transposed BF16 output [i][j], y fastest
+        for (int idx = tid; idx < 64 * 64; idx += NT) {
+            const int il = idx >> 6, jl = idx & 63;
+            ((__bf16*)yout)[sob + (long long)(i0 + il) * npy + j0 + jl] = (__bf16)epi[jl * 65 + il];
+        }
+        return;
+    }
     const double theta = EPI == 1 ? desc[s].theta_lhs : 0.0;
 #pragma unroll
     for (int qd = 0; qd < 4; ++qd) {                          // per 32 x 32 quadrant, as in apply_tile
