@@ -761,36 +761,51 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = flt4{0.f, 0.f, 0.f, 0.f};
 
+    // Operands of chunk k0 + BK are loaded into registers while chunk k0 is multiplied
+    // (each thread: two 16-byte pieces of the A tile; two of the B tile, or 16 values of r).
+    const __bf16* Xb = (const __bf16*)xin + sob;
+    uint4 ra0, ra1, rb0, rb1;
+    float rr[LEFT && IN == 0 ? 16 : 1];
+#define FDB_LOAD(K0)                                                                                          \
+    {                                                                                                       \
+        const int r0 = tid >> 3, r1 = (tid + NT) >> 3, kv = tid & 7;                                        \
+        ra0 = LEFT ? *(const uint4*)&mat[(long long)(i0 + r0) * npx + (K0) + 8 * kv]                        \
+                   : *(const uint4*)&Xb[(long long)(i0 + r0) * npy + (K0) + 8 * kv];                        \
+        ra1 = LEFT ? *(const uint4*)&mat[(long long)(i0 + r1) * npx + (K0) + 8 * kv]                        \
+                   : *(const uint4*)&Xb[(long long)(i0 + r1) * npy + (K0) + 8 * kv];                        \
+        if (!(LEFT && IN == 0)) {                                                                           \
+            rb0 = LEFT ? *(const uint4*)&Xb[(long long)(j0 + r0) * npx + (K0) + 8 * kv]                     \
+                       : *(const uint4*)&mat[(long long)(j0 + r0) * npy + (K0) + 8 * kv];                   \
+            rb1 = LEFT ? *(const uint4*)&Xb[(long long)(j0 + r1) * npx + (K0) + 8 * kv]                     \
+                       : *(const uint4*)&mat[(long long)(j0 + r1) * npy + (K0) + 8 * kv];                   \
+        } else {                                                                                            \
+            const RT* X = rws + so;                                                                         \
+            _Pragma("unroll") for (int q = 0; q < (LEFT && IN == 0 ? 16 : 1); ++q) {                        \
+                const int idx = tid + NT * q, jj = idx >> 6, kk = idx & 63;                                 \
+                const int k = (K0) + kk, j = j0 + jj;                                                       \
+                rr[q] = (k < nx && j < ny) ? (float)X[(long long)j * nx + k] : 0.0f;                        \
+            }                                                                                               \
+        }                                                                                                   \
+    }
+    FDB_LOAD(0)
     for (int k0 = 0; k0 < K; k0 += BK) {
-        // A tile
-        for (int idx = tid; idx < 64 * 8; idx += NT) {
-            if (LEFT) {
-                const int ii = idx >> 3, kv = idx & 7;
-                *(uint4*)&As[ii * BLD + 8 * kv] = *(const uint4*)&mat[(long long)(i0 + ii) * npx + k0 + 8 * kv];
-            } else {                                    // X^T[i][k], stored transposed by the product before
-                const int ii = idx >> 3, kv = idx & 7;
-                const __bf16* X = (const __bf16*)xin + sob;
-                *(uint4*)&As[ii * BLD + 8 * kv] = *(const uint4*)&X[(long long)(i0 + ii) * npy + k0 + 8 * kv];
-            }
-        }
-        // B tile ([j][k])
-        if (LEFT && IN == 0) {
-            const RT* X = rws + so;
-            for (int idx = tid; idx < 64 * 64; idx += NT) {
-                const int jj = idx >> 6, kk = idx & 63;
-                const int k = k0 + kk, j = j0 + jj;
-                const float v = (k < nx && j < ny) ? (float)X[(long long)j * nx + k] : 0.0f;
-                Bs[jj * BLD + kk] = (__bf16)v;
-            }
-        } else {
-            for (int idx = tid; idx < 64 * 8; idx += NT) {
-                const int jj = idx >> 3, kv = idx & 7;
-                const __bf16* src = LEFT ? (const __bf16*)xin + sob + (long long)(j0 + jj) * npx + k0 + 8 * kv
-                                         : mat + (long long)(j0 + jj) * npy + k0 + 8 * kv;
-                *(uint4*)&Bs[jj * BLD + 8 * kv] = *(const uint4*)src;
+        {
+            const int r0 = tid >> 3, r1 = (tid + NT) >> 3, kv = tid & 7;
+            *(uint4*)&As[r0 * BLD + 8 * kv] = ra0;
+            *(uint4*)&As[r1 * BLD + 8 * kv] = ra1;
+            if (!(LEFT && IN == 0)) {
+                *(uint4*)&Bs[r0 * BLD + 8 * kv] = rb0;
+                *(uint4*)&Bs[r1 * BLD + 8 * kv] = rb1;
+            } else {
+#pragma unroll
+                for (int q = 0; q < (LEFT && IN == 0 ? 16 : 1); ++q) {
+                    const int idx = tid + NT * q, jj = idx >> 6, kk = idx & 63;
+                    Bs[jj * BLD + kk] = (__bf16)rr[q];
+                }
             }
         }
         __syncthreads();
+        if (k0 + BK < K) FDB_LOAD(k0 + BK)
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 32) {
             bf8 a[2], b[2];
@@ -807,6 +822,7 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __
         }
         __syncthreads();
     }
+#undef FDB_LOAD
     float* epi = (float*)raw;
 #pragma unroll
     for (int fi = 0; fi < 2; ++fi)
