@@ -1174,6 +1174,18 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
     const cpx<T>* K = (const cpx<T>*)(sizeof(T) == 8 ? (const void*)(DIR == 0 ? pl.kx : pl.ky)
                                                       : (const void*)(DIR == 0 ? pl.kx32 : pl.ky32));
     cpx<T>* buf = lds + wave * FPAD;
+    // FP32, 512 points: the kernel spectra and twiddles (4 x 512 values) are staged in LDS; their
+    // loads are issued together with those of the lines, so the combination step waits for nothing
+    constexpr bool KST = sizeof(T) == 4 && L == 512;
+    __shared__ __attribute__((aligned(16))) cpx<T> kst[KST ? 4 * L : 1];
+    cpx<T> kreg[KST ? 4 : 1];
+    if constexpr (KST) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + FNT * q;
+            kreg[q] = idx < 3 * L ? K[idx] : tw[idx - 3 * L];
+        }
+    }
 
     // ---- load the input pair of this wave: lines la = l0 - 1 + 2 wave and la + 1 ----
     const int la = l0 - 1 + 2 * wave, lb = la + 1;
@@ -1185,12 +1197,25 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
             a[r].x = (la >= 0 && la < nl && pos < n) ? v[(long long)la * nx + pos] : T(0);
             a[r].y = (lb >= 0 && lb < nl && pos < n) ? v[(long long)lb * nx + pos] : T(0);
         }
+        if constexpr (KST) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) kst[tid + FNT * q] = kreg[q];
+            __syncthreads();
+            K = kst;
+            tw = kst + 3 * L;
+        }
     } else {
         // columns l0 - 1 .. l0 + 14 of every row, staged through LDS (row segments are contiguous)
         T* stg = (T*)lds;
         for (int idx = tid; idx < ny * 16; idx += FNT) {
             const int pos = idx >> 4, c = idx & 15, col = l0 - 1 + c;
             stg[pos * 17 + c] = (col >= 0 && col < nx) ? v[(long long)pos * nx + col] : T(0);
+        }
+        if constexpr (KST) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) kst[tid + FNT * q] = kreg[q];
+            K = kst;
+            tw = kst + 3 * L;
         }
         __syncthreads();
 #pragma unroll
