@@ -843,10 +843,10 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __
         return;
     }
     const double theta = EPI == 1 ? desc[s].theta_lhs : 0.0;
+    double dot[4] = {0.0, 0.0, 0.0, 0.0};                     // per 32 x 32 quadrant, as in apply_tile
 #pragma unroll
-    for (int qd = 0; qd < 4; ++qd) {                          // per 32 x 32 quadrant, as in apply_tile
+    for (int qd = 0; qd < 4; ++qd) {
         const int qx = qd & 1, qy = qd >> 1;
-        double dot = 0.0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int idx = tid + NT * k;
@@ -859,17 +859,28 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __
                     const long long o = (long long)j * nx + i;
                     ((RT*)yout)[so + o] = (RT)v;
                     if (ycopy) ycopy[so + o] = (RT)v;
-                    dot += (double)v * (double)rws[so + o];
+                    dot[qd] += (double)v * (double)rws[so + o];
                 }
             } else {
                 ((__bf16*)yout)[sob + (long long)j * npx + i] = (__bf16)v;
             }
         }
-        if (EPI == 2) {
-            dot = block_sum(dot, red);
-            const int gx = i0 / 32 + qx, gy = j0 / 32 + qy;
-            if (threadIdx.x == 0 && gx < g.tiles_x[1] && gy < g.tiles_y[1])
-                partial[(long long)s * g.pmax + gx + g.tiles_x[1] * gy] = dot;
+    }
+    if (EPI == 2) {
+        // the four quadrant sums reduced together: wave sums, then waves 0..3 in the order of block_sum
+        __shared__ double red4[4][4];
+#pragma unroll
+        for (int qd = 0; qd < 4; ++qd) dot[qd] = wave_sum(dot[qd]);
+        if ((tid & 63) == 0) {
+#pragma unroll
+            for (int qd = 0; qd < 4; ++qd) red4[tid >> 6][qd] = dot[qd];
+        }
+        __syncthreads();
+        if (tid < 4) {
+            const int qd = tid, gx = i0 / 32 + (qd & 1), gy = j0 / 32 + (qd >> 1);
+            if (gx < g.tiles_x[1] && gy < g.tiles_y[1])
+                partial[(long long)s * g.pmax + gx + g.tiles_x[1] * gy] =
+                    (red4[0][qd] + red4[1][qd]) + (red4[2][qd] + red4[3][qd]);
         }
     }
 }
