@@ -66,9 +66,10 @@ extern "C" {
  * FP64 one (||r|| <= rtol ||b||); each refinement step solves B d = r / ||r||
  * by PCG in FP32 (operator on the FP32 matrix cores, FP32 vectors, FP64
  * reductions) to the relative tolerance max(rtol ||b|| / ||r||, inner_rtol).
- * The solution is the FP64 one to the CG tolerance; only a loose pass tolerance
- * (>= 100 x inner_rtol, as on coarse levels) is accepted after its single
- * refinement step without the FP64 confirmation.  MIXED_COARSE: FP64 on
+ * The solution is the FP64 one to the CG tolerance; a refinement step whose
+ * inner target was the pass tolerance itself (rtol ||b|| / ||r|| >= 10 x
+ * inner_rtol, e.g. the last step, or the only one at loose coarse-level
+ * tolerances) is accepted without recomputing the FP64 residual.  MIXED_COARSE: FP64 on
  * level 0 (and in sequential stepping), MIXED on the coarse levels.  Both take
  * precond NONE or FD_BF16. */
 #define MGRIT_PREC_MIXED        1

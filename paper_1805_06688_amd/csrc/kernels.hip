@@ -373,7 +373,8 @@ __global__ __launch_bounds__(NT) void k_apply32(Geom g, Seqs32 sq, const PropDes
 // and ||r||^2 per slice): outer flag ||r|| > rtol ||b||, scale ||r||, inner
 // tolerance eta^2 = max(rtol^2 ||b||^2 / ||r||^2, eta_min^2), r32 = r / ||r||,
 // d32 = 0 and, when p32 is given (no preconditioner), p32 = r32 with partial
-// r32.r32.  On the first step x = 0 where b = 0 and the counts restart.
+// r32.r32.  On the first step x = 0 where b = 0 and the counts restart.  The
+// inner flag is 2 instead of 1 when eta^2 >= 100 eta_min2.
 __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restrict__ desc, int S, double* xbase,
                                                  const double* rws, const double* partial_bb,
                                                  const double* partial_rr, int np, double rtol2, double eta_min2,
@@ -414,9 +415,12 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
     if (c == 0 && threadIdx.x == 0) {
         bb[s] = b2;
         oact[s] = active ? 1 : 0;
-        iact[s] = active ? 1 : 0;
+        const double e2 = active ? fmax(rtol2 * b2 / r2, eta_min2) : 0.0;
+        // 2: the inner target is the pass tolerance itself and at least 10 x the FP32 floor, so the
+        // inner solve's own test settles the slice (see the refinement loop)
+        iact[s] = active ? (e2 >= 1e2 * eta_min2 ? 2 : 1) : 0;
         scale[s] = active ? sqrt(r2) : 0.0;
-        eta2[s] = active ? fmax(rtol2 * b2 / r2, eta_min2) : 0.0;
+        eta2[s] = e2;
         if (first) iters[s] = 0;
     }
 }
