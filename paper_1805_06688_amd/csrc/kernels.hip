@@ -889,6 +889,116 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __
     }
 }
 
+// The same products for small batches (npx, npy <= 256): 32 x 32 output tiles covering the padded
+// extent, all of K loaded at once, the contraction split over the four waves (k-chunks of 32 dealt
+// round-robin) and summed through LDS in wave order; epilogues as in k_fdb_gemm, with one r.z partial per
+// 32 x 32 tile at the index k_fdb_gemm gives that quadrant.
+constexpr int SLD = 256 + 8;        // LDS row stride (BF16) of the [row][k] tiles
+
+template <bool LEFT, int IN, int EPI, typename RT>
+__global__ __launch_bounds__(NT) void k_fdb_gemm32(Geom g, int S, const __bf16* __restrict__ mat,
+                                                   const void* __restrict__ xin, void* __restrict__ yout,
+                                                   const PropDesc* __restrict__ desc, const float* __restrict__ lx,
+                                                   const float* __restrict__ ly, const RT* __restrict__ rws,
+                                                   RT* __restrict__ ycopy, double* partial, const int* active) {
+    const int npx = g.tiles_x[0] * 64, npy = g.tiles_y[0] * 64;
+    const int tx = npx / 32, ty = npy / 32;
+    int s, tile;
+    decode_block(tx * ty, S, s, tile);
+    if (s < 0) return;
+    if (active && !active[s]) return;
+    __shared__ __attribute__((aligned(16))) unsigned char raw[2 * 32 * SLD * 2 > 4 * 32 * 33 * 4 ? 2 * 32 * SLD * 2
+                                                                                                 : 4 * 32 * 33 * 4];
+    __shared__ double red[4];
+    __bf16* As = (__bf16*)raw;                 // [i][k]
+    __bf16* Bs = As + 32 * SLD;                // [j][k]
+    const int nx = g.nx, ny = g.ny;
+    const int i0 = (tile % tx) * 32, j0 = (tile / tx) * 32;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const long long sob = (long long)s * npx * npy;
+    const long long so = (long long)s * g.stride;
+    const int K = LEFT ? npx : npy;
+    const int kv8 = K >> 3;
+    const __bf16* Xb = (const __bf16*)xin + sob;
+    for (int idx = tid; idx < 32 * kv8; idx += NT) {             // A rows i, B rows j (16-byte pieces)
+        const int row = idx / kv8, kv = idx - row * kv8;
+        *(uint4*)&As[row * SLD + 8 * kv] = LEFT ? *(const uint4*)&mat[(long long)(i0 + row) * npx + 8 * kv]
+                                                : *(const uint4*)&Xb[(long long)(i0 + row) * npy + 8 * kv];
+        if (!(LEFT && IN == 0))
+            *(uint4*)&Bs[row * SLD + 8 * kv] = LEFT ? *(const uint4*)&Xb[(long long)(j0 + row) * npx + 8 * kv]
+                                                    : *(const uint4*)&mat[(long long)(j0 + row) * npy + 8 * kv];
+    }
+    if (LEFT && IN == 0) {                                         // rows j0 + wave + 4q of r, lanes along k
+        const RT* X = rws + so;
+        for (int k = lane; k < K; k += 64) {
+            float v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int j = j0 + wave + 4 * q;
+                v[q] = (k < nx && j < ny) ? (float)X[(long long)j * nx + k] : 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) Bs[(wave + 4 * q) * SLD + k] = (__bf16)v[q];
+        }
+    }
+    __syncthreads();
+    flt4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = flt4{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 32 * wave; ks < K; ks += 128) {                // this wave's k-chunks: wave, wave + 4, ...
+        bf8 a[2], b[2];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            a[f] = *(const bf8*)&As[(f * 16 + lr) * SLD + ks + 8 * lg];
+            b[f] = *(const bf8*)&Bs[(f * 16 + lr) * SLD + ks + 8 * lg];
+        }
+#pragma unroll
+        for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+            for (int fj = 0; fj < 2; ++fj)
+                acc[fi][fj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[fi], b[fj], acc[fi][fj], 0, 0, 0);
+    }
+    __syncthreads();
+    float* part = (float*)raw;                                     // [wave][j][i], stride 33
+#pragma unroll
+    for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+        for (int fj = 0; fj < 2; ++fj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                part[wave * 32 * 33 + (fj * 16 + lr) * 33 + fi * 16 + 4 * lg + r] = acc[fi][fj][r];
+    __syncthreads();
+    const double theta = EPI == 1 ? desc[s].theta_lhs : 0.0;
+    double dot = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int idx = tid + NT * k;
+        const int jl = idx >> 5, il = idx & 31;
+        const int i = i0 + il, j = j0 + jl;
+        const int o32 = jl * 33 + il;
+        float v = ((part[o32] + part[32 * 33 + o32]) + part[2 * 32 * 33 + o32]) + part[3 * 32 * 33 + o32];
+        if (EPI == 0) {
+            ((__bf16*)yout)[sob + (long long)i * npy + j] = (__bf16)v;      // transposed, as in k_fdb_gemm
+        } else if (EPI == 1) {
+            v = (float)((double)v / (1.0 + theta * ((double)lx[i] + (double)ly[j])));
+            ((__bf16*)yout)[sob + (long long)j * npx + i] = (__bf16)v;
+        } else if (i < nx && j < ny) {
+            const long long o = (long long)j * nx + i;
+            ((RT*)yout)[so + o] = (RT)v;
+            if (ycopy) ycopy[so + o] = (RT)v;
+            dot += (double)v * (double)rws[so + o];
+        }
+    }
+    if (EPI == 2) {
+        dot = block_sum(dot, red);
+        const int gx = i0 / 32, gy = j0 / 32;
+        if (tid == 0 && gx < g.tiles_x[1] && gy < g.tiles_y[1]) partial[(long long)s * g.pmax + gx + g.tiles_x[1] * gy] = dot;
+    }
+}
+
 __global__ __launch_bounds__(NT) void k_add_g(Geom g, const PropDesc* __restrict__ desc, int S, double* xbase,
                                               const double* gbase) {
     int s, c;
@@ -1514,6 +1624,23 @@ namespace {
 template <typename RT>
 void fdb_chain(const Geom* g, const FdMatsB* fd, const PropDesc* desc, int S, const RT* rws, RT* zws, RT* zcopy,
                void* t1, void* t2, double* partial_rz, const int* active, hipStream_t st) {
+    const int npx = g->tiles_x[0] * 64, npy = g->tiles_y[0] * 64;
+    if (npx <= 256 && npy <= 256 && S * g->ntiles[0] < 256) {      // batches that leave compute units idle
+        const dim3 grid(grid_blocks((npx / 32) * (npy / 32), S)), blk(NT);
+        const __bf16* VxT = (const __bf16*)fd->VxT;
+        const __bf16* Vx = (const __bf16*)fd->Vx;
+        const __bf16* VyT = (const __bf16*)fd->VyT;
+        const __bf16* Vy = (const __bf16*)fd->Vy;
+        hipLaunchKernelGGL((k_fdb_gemm32<true, 0, 0, RT>), grid, blk, 0, st, *g, S, VxT, (const void*)nullptr, t1,
+                           desc, fd->lx, fd->ly, rws, (RT*)nullptr, (double*)nullptr, active);
+        hipLaunchKernelGGL((k_fdb_gemm32<false, 1, 1, RT>), grid, blk, 0, st, *g, S, VyT, (const void*)t1, t2,
+                           desc, fd->lx, fd->ly, rws, (RT*)nullptr, (double*)nullptr, active);
+        hipLaunchKernelGGL((k_fdb_gemm32<true, 1, 0, RT>), grid, blk, 0, st, *g, S, Vx, (const void*)t2, t1,
+                           desc, fd->lx, fd->ly, rws, (RT*)nullptr, (double*)nullptr, active);
+        hipLaunchKernelGGL((k_fdb_gemm32<false, 1, 2, RT>), grid, blk, 0, st, *g, S, Vy, (const void*)t1,
+                           (void*)zws, desc, fd->lx, fd->ly, rws, zcopy, partial_rz, active);
+        return;
+    }
     const dim3 grid(grid_blocks(g->ntiles[0], S)), blk(NT);
     const __bf16* VxT = (const __bf16*)fd->VxT;
     const __bf16* Vx = (const __bf16*)fd->Vx;
