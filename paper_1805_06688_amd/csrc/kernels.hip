@@ -348,6 +348,15 @@ __device__ __forceinline__ void chunk_range(const Geom& g, int c, long long& lo,
     if (hi > g.stride) hi = g.stride;
 }
 
+// Elements per thread in a chunk.  The kernels below load all of a thread's
+// elements (indices clamped into the chunk, so every load is in bounds) before
+// they store any result: at small batches a chunk loop that waits for each
+// element's loads in turn is bound by memory latency.  Positions k = 0, 1, ...
+// of a thread are its elements lo + tid + k NT in the order a plain strided
+// loop visits them, so sums over them keep that order.
+constexpr int PT = CH / NT;
+static_assert(CH % NT == 0, "chunk must be a multiple of the workgroup");
+
 // ---- mixed precision: FP32 inner solves of an iterative refinement ----
 // The outer loop keeps b, x and r = b - B x in FP64; each step solves
 // B d = r / ||r|| by PCG in FP32 (operator on the FP32 matrix cores, vectors
@@ -426,8 +435,8 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
 }
 
 // alpha = rho / p.q; d32 += alpha p32, r32 -= alpha q32; partial r32.r32.
-__global__ __launch_bounds__(NT) void k_mx_update(Geom g, int S, float* d32, float* r32, const float* p32,
-                                                  const float* q32, const double* partial_rho, int nrho,
+__global__ __launch_bounds__(NT) void k_mx_update(Geom g, int S, float* __restrict__ d32, float* __restrict__ r32,
+                                                  const float* __restrict__ p32, const float* __restrict__ q32, const double* partial_rho, int nrho,
                                                   const double* partial_pq, int npq, double* partial_rr_new,
                                                   const int* active) {
     int s, c;
@@ -438,12 +447,26 @@ __global__ __launch_bounds__(NT) void k_mx_update(Geom g, int S, float* d32, flo
     const long long so = (long long)s * g.stride;
     long long lo, hi;
     chunk_range(g, c, lo, hi);
+    const long long e0 = so + lo + threadIdx.x, last = so + hi - 1;
+    float dv[PT], rv[PT], pv[PT], qv[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+        const long long e = e0 + (long long)k * NT < last ? e0 + (long long)k * NT : last;
+        dv[k] = d32[e];
+        rv[k] = r32[e];
+        pv[k] = p32[e];
+        qv[k] = q32[e];
+    }
     double acc = 0.0;
-    for (long long e = so + lo + threadIdx.x; e < so + hi; e += NT) {
-        d32[e] += alpha * p32[e];
-        const float rn = r32[e] - alpha * q32[e];
-        r32[e] = rn;
-        acc += (double)rn * (double)rn;
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+        const long long e = e0 + (long long)k * NT;
+        const float rn = rv[k] - alpha * qv[k];
+        if (e <= last) {
+            d32[e] = dv[k] + alpha * pv[k];
+            r32[e] = rn;
+            acc += (double)rn * (double)rn;
+        }
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) partial_rr_new[(long long)s * g.pmax + c] = acc;
@@ -452,7 +475,8 @@ __global__ __launch_bounds__(NT) void k_mx_update(Geom g, int S, float* d32, flo
 // p32 = z32 + (rho_new / rho) p32; the inner solve of slice s stops when
 // ||r32||^2 <= eta2[s] (its right-hand side has unit norm) or at maxit
 // iterations in all (counted over the refinement steps).
-__global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float* z32, float* p32,
+__global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float* __restrict__ z32,
+                                                     float* __restrict__ p32,
                                                      const double* partial_rho, int nrho,
                                                      const double* partial_rho_new, int nrho_new,
                                                      const double* partial_rr_new, const double* eta2, int maxit,
@@ -468,7 +492,17 @@ __global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float*
     const long long so = (long long)s * g.stride;
     long long lo, hi;
     chunk_range(g, c, lo, hi);
-    for (long long e = so + lo + threadIdx.x; e < so + hi; e += NT) p32[e] = z32[e] + beta * p32[e];
+    const long long e0 = so + lo + threadIdx.x, last = so + hi - 1;
+    float zv[PT], pv[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+        const long long e = e0 + (long long)k * NT < last ? e0 + (long long)k * NT : last;
+        zv[k] = z32[e];
+        pv[k] = p32[e];
+    }
+#pragma unroll
+    for (int k = 0; k < PT; ++k)
+        if (e0 + (long long)k * NT <= last) p32[e0 + (long long)k * NT] = zv[k] + beta * pv[k];
     if (c == 0 && threadIdx.x == 0) {
         const double rrn = slice_sum(partial_rr_new, g.pmax, s, g.nchunk);
         const int it = iters[s] + 1;
@@ -488,7 +522,18 @@ __global__ __launch_bounds__(NT) void k_mx_refine(Geom g, const PropDesc* __rest
     const double a = scale[s];
     long long lo, hi;
     chunk_range(g, c, lo, hi);
-    for (long long e = lo + threadIdx.x; e < hi; e += NT) x[e] += a * (double)d[e];
+    const long long e0 = lo + threadIdx.x, last = hi - 1;
+    double xv[PT];
+    float dv[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+        const long long e = e0 + (long long)k * NT < last ? e0 + (long long)k * NT : last;
+        xv[k] = x[e];
+        dv[k] = d[e];
+    }
+#pragma unroll
+    for (int k = 0; k < PT; ++k)
+        if (e0 + (long long)k * NT <= last) x[e0 + (long long)k * NT] = xv[k] + a * (double)dv[k];
 }
 
 __global__ __launch_bounds__(NT) void k_cg_init_x(Geom g, const PropDesc* __restrict__ desc, int S,
@@ -545,19 +590,36 @@ __global__ __launch_bounds__(NT) void k_cg_update(Geom g, const PropDesc* __rest
     const double rho = slice_sum(partial_rho, g.pmax, s, nrho);
     const double pq = slice_sum(partial_pq, g.pmax, s, npq);
     const double alpha = rho / pq;
-    double* x = xbase + desc[s].x * g.stride;
+    double* __restrict__ x = xbase + desc[s].x * g.stride;
     const long long so = (long long)s * g.stride;
-    double* r = rws + so;
-    const double* p = pws + so;
-    const double* q = qws + so;
+    double* __restrict__ r = rws + so;
+    const double* __restrict__ p = pws + so;
+    const double* __restrict__ q = qws + so;
     long long lo, hi;
     chunk_range(g, c, lo, hi);
+    const long long e0 = lo + threadIdx.x, last = hi - 1;
     double acc = 0.0;
-    for (long long e = lo + threadIdx.x; e < hi; e += NT) {
-        x[e] += alpha * p[e];
-        const double rn = r[e] - alpha * q[e];
-        r[e] = rn;
-        acc += rn * rn;
+#pragma unroll
+    for (int k0 = 0; k0 < PT; k0 += PT / 2) {                     // two halves: 64 FP64 values in flight
+        double xv[PT / 2], rv[PT / 2], pv[PT / 2], qv[PT / 2];
+#pragma unroll
+        for (int k = 0; k < PT / 2; ++k) {
+            const long long e1 = e0 + (long long)(k0 + k) * NT, e = e1 < last ? e1 : last;
+            xv[k] = x[e];
+            rv[k] = r[e];
+            pv[k] = p[e];
+            qv[k] = q[e];
+        }
+#pragma unroll
+        for (int k = 0; k < PT / 2; ++k) {
+            const long long e = e0 + (long long)(k0 + k) * NT;
+            const double rn = rv[k] - alpha * qv[k];
+            if (e <= last) {
+                x[e] = xv[k] + alpha * pv[k];
+                r[e] = rn;
+                acc += rn * rn;
+            }
+        }
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) partial_rr_new[(long long)s * g.pmax + c] = acc;
@@ -580,11 +642,21 @@ __global__ __launch_bounds__(NT) void k_cg_direction(Geom g, int S, const double
     const double rhon = slice_sum(partial_rho_new, g.pmax, s, nrho_new);
     const double beta = rhon / rho;
     const long long so = (long long)s * g.stride;
-    const double* z = zws + so;
-    double* p = pws + so;
+    const double* __restrict__ z = zws + so;
+    double* __restrict__ p = pws + so;
     long long lo, hi;
     chunk_range(g, c, lo, hi);
-    for (long long e = lo + threadIdx.x; e < hi; e += NT) p[e] = z[e] + beta * p[e];
+    const long long e0 = lo + threadIdx.x, last = hi - 1;
+    double zv[PT], pv[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+        const long long e = e0 + (long long)k * NT < last ? e0 + (long long)k * NT : last;
+        zv[k] = z[e];
+        pv[k] = p[e];
+    }
+#pragma unroll
+    for (int k = 0; k < PT; ++k)
+        if (e0 + (long long)k * NT <= last) p[e0 + (long long)k * NT] = zv[k] + beta * pv[k];
     if (c == 0 && threadIdx.x == 0) {
         const double rrn = slice_sum(partial_rr_new, g.pmax, s, g.nchunk);
         const int it = iters[s] + 1;
