@@ -1402,11 +1402,20 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
             tw = kst + 3 * L;
         }
     } else {
-        // columns l0 - 1 .. l0 + 14 of every row, staged through LDS (row segments are contiguous)
+        // columns l0 - 1 .. l0 + 14 of every row, staged through LDS (row segments are contiguous);
+        // all of a thread's loads are issued before the first store
         T* stg = (T*)lds;
-        for (int idx = tid; idx < ny * 16; idx += FNT) {
-            const int pos = idx >> 4, c = idx & 15, col = l0 - 1 + c;
-            stg[pos * 17 + c] = (col >= 0 && col < nx) ? v[(long long)pos * nx + col] : T(0);
+        constexpr int SG = L / 2 * 16 / FNT;                    // staged values per thread (ny <= L / 2)
+        T sv[SG];
+#pragma unroll
+        for (int q = 0; q < SG; ++q) {
+            const int idx = tid + FNT * q, pos = idx >> 4, col = l0 - 1 + (idx & 15);
+            sv[q] = (pos < ny && col >= 0 && col < nx) ? v[(long long)pos * nx + col] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < SG; ++q) {
+            const int idx = tid + FNT * q, pos = idx >> 4;
+            if (pos < ny) stg[pos * 17 + (idx & 15)] = sv[q];
         }
         if constexpr (KST) {
 #pragma unroll
@@ -1496,7 +1505,7 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
     }
     __syncthreads();
     // epilogue in groups of FG elements per thread: the loads of a group are issued before its stores
-    constexpr int FG = 4;
+    constexpr int FG = FE <= 8 ? FE : 8;
     double dot = 0.0;
 #pragma unroll 1
     for (int e0 = 0; e0 < FE; e0 += FG) {
