@@ -804,8 +804,10 @@ union Pack8 {
 // The BF16 intermediates between the products are stored transposed ([i][j],
 // y fastest) after a product over x, so that the next product, over y, reads
 // its operand rows directly instead of transposing them through LDS.
+// The last product gets a register budget of 8 workgroups per compute unit (64 registers), so that
+// 128 slices of 16 tiles are resident at once (the others would spill at that budget).
 template <bool LEFT, int IN, int EPI, typename RT>
-__global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __restrict__ mat,
+__global__ __launch_bounds__(NT, EPI == 2 ? 8 : 1) void k_fdb_gemm(Geom g, int S, const __bf16* __restrict__ mat,
                                                  const void* __restrict__ xin, void* __restrict__ yout,
                                                  const PropDesc* __restrict__ desc, const float* __restrict__ lx,
                                                  const float* __restrict__ ly, const RT* __restrict__ rws,
@@ -918,7 +920,9 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __
         }
         return;
     }
-    const double theta = EPI == 1 ? desc[s].theta_lhs : 0.0;
+    // the scale 1 / (1 + theta (lx + ly)) (lx, ly >= 0) in FP32 by the hardware reciprocal: its error
+    // is far below the BF16 rounding of the product it scales
+    const float theta = EPI == 1 ? (float)desc[s].theta_lhs : 0.0f;
     double dot[4] = {0.0, 0.0, 0.0, 0.0};                     // per 32 x 32 quadrant, as in apply_tile
 #pragma unroll
     for (int qd = 0; qd < 4; ++qd) {
@@ -929,7 +933,7 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm(Geom g, int S, const __bf16* __
             const int jl = qy * 32 + idx / 32, il = qx * 32 + (idx & 31);
             const int i = i0 + il, j = j0 + jl;
             float v = epi[jl * 65 + il];
-            if (EPI == 1) v = (float)((double)v / (1.0 + theta * ((double)lx[i] + (double)ly[j])));
+            if (EPI == 1) v *= __builtin_amdgcn_rcpf(1.0f + theta * (lx[i] + ly[j]));
             if (EPI == 2) {
                 if (i < nx && j < ny) {
                     const long long o = (long long)j * nx + i;
@@ -1043,7 +1047,9 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm32(Geom g, int S, const __bf16* 
             for (int r = 0; r < 4; ++r)
                 part[wave * 32 * 33 + (fj * 16 + lr) * 33 + fi * 16 + 4 * lg + r] = acc[fi][fj][r];
     __syncthreads();
-    const double theta = EPI == 1 ? desc[s].theta_lhs : 0.0;
+    // the scale 1 / (1 + theta (lx + ly)) (lx, ly >= 0) in FP32 by the hardware reciprocal: its error
+    // is far below the BF16 rounding of the product it scales
+    const float theta = EPI == 1 ? (float)desc[s].theta_lhs : 0.0f;
     double dot = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -1055,7 +1061,7 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm32(Geom g, int S, const __bf16* 
         if (EPI == 0) {
             ((__bf16*)yout)[sob + (long long)i * npy + j] = (__bf16)v;      // transposed, as in k_fdb_gemm
         } else if (EPI == 1) {
-            v = (float)((double)v / (1.0 + theta * ((double)lx[i] + (double)ly[j])));
+            v *= __builtin_amdgcn_rcpf(1.0f + theta * (lx[i] + ly[j]));
             ((__bf16*)yout)[sob + (long long)j * npx + i] = (__bf16)v;
         } else if (i < nx && j < ny) {
             const long long o = (long long)j * nx + i;
