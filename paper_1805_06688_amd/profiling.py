@@ -8,7 +8,11 @@
         mean value per dispatch of every counter for kernels matching REGEX
     python -m paper_1805_06688_amd.profiling source-hash
         hash of the HIP kernel sources (counters are tied to one version)
+    python -m paper_1805_06688_amd.profiling traffic FETCH_CSV WRITE_CSV REGEX_X REGEX_Y VARIANT [FF WF]
+        HBM bytes per operator application (one x-pass and one y-pass dispatch) from a FETCH_SIZE
+        and a WRITE_SIZE run, each counter scaled by its copy-kernel factor (FF, WF; default 2, 1)
 """
+import json
 import csv
 import hashlib
 import os
@@ -98,6 +102,30 @@ def counters(path, regex):
         print(f"{k} grid={g} {c}: dispatches={n} mean={tot / n:.1f}")
 
 
+def _kib(path, regex, counter):
+    pat = re.compile(regex)
+    tot, n = 0.0, 0
+    for r in csv.DictReader(open(path)):
+        if pat.search(r.get("Kernel_Name", "")) and r["Counter_Name"] == counter:
+            tot += float(r["Counter_Value"])
+            n += 1
+    return tot, n
+
+
+def traffic(fetch_csv, write_csv, regex_x, regex_y, variant, ff=2.0, wf=1.0):
+    fx, nx = _kib(fetch_csv, regex_x, "FETCH_SIZE")
+    fy, ny = _kib(fetch_csv, regex_y, "FETCH_SIZE")
+    wx, mx = _kib(write_csv, regex_x, "WRITE_SIZE")
+    wy, my = _kib(write_csv, regex_y, "WRITE_SIZE")
+    if not (nx and nx == ny and mx == nx and my == nx):
+        raise SystemExit(f"dispatch counts differ: {nx} {ny} {mx} {my}")
+    per = (ff * (fx + fy) + wf * (wx + wy)) * 1024.0 / nx
+    out = {"variant": int(variant), "source_hash": source_hash(), "counter_factors": {"FETCH_SIZE": ff, "WRITE_SIZE": wf},
+           "applications": nx, "fetch_kib_per_application": {"x": fx / nx, "y": fy / nx},
+           "write_kib_per_application": {"x": wx / nx, "y": wy / nx}, "bytes_per_launch": per}
+    print(json.dumps(out, indent=1))
+
+
 if __name__ == "__main__":
     cmd = sys.argv[1] if len(sys.argv) > 1 else ""
     if cmd == "copy":
@@ -108,6 +136,8 @@ if __name__ == "__main__":
         counters(sys.argv[2], sys.argv[3])
     elif cmd == "source-hash":
         print(source_hash())
+    elif cmd == "traffic":
+        traffic(*sys.argv[2:6], int(sys.argv[6]), *[float(x) for x in sys.argv[7:9]])
     else:
         print(__doc__)
         sys.exit(2)
