@@ -55,8 +55,8 @@ def cpu_baseline(W, t, F, psi0, steps, cg_rtol):
                       f"{len(t) - 1} steps, CG rtol {cg_rtol:g}, numpy FP64 on the host; {dt:.1f} s"}
 
 
-SOLVE_OPTS = dict(coarse="opt", precond="fd-bf16", cg_rtol=3e-10, cg_rtol_coarse=1e-3, precision="mixed",
-                  cg_maxit=100000, tol_abs=0.0, tol_rel=1e-9, max_iter=40, max_levels=3)
+SOLVE_OPTS = dict(coarse="opt", precond="fd-bf16", cg_rtol=1e-9, cg_rtol_coarse=1e-3, precision="mixed",
+                  cg_maxit=100000, tol_abs=0.0, tol_rel=1e-8, max_iter=40, max_levels=3)
 
 
 def serving(mgrit, wl, torch, n_requests, rate, max_concurrent, budget_gb):
@@ -83,8 +83,8 @@ def serving(mgrit, wl, torch, n_requests, rate, max_concurrent, budget_gb):
             "mean_queue_s": float(np.mean([i.start_s - i.submit_s for i, _ in done])),
             "throughput_dof_per_s": dof / span, "all_converged": ok,
             "trace": "seed 5: Poisson arrivals; n_x, n_y ~ U{63..255}, N_t ~ U{64..512} (multiple of 8), "
-                     "beta, gamma ~ U(0.55, 0.95), K = 1, m = 8; mixed precision with FP64 stop tests (CG 3e-10, "
-                     "coarse levels 1e-3, MGRIT stop 1e-9 rel.)"}
+                     "beta, gamma ~ U(0.55, 0.95), K = 1, m = 8; mixed precision with FP64 stop tests (CG 1e-9, "
+                     "coarse levels 1e-3, MGRIT stop 1e-8 rel.)"}
 
 
 def many_instance(mgrit, wl, torch, n_problems, max_concurrent):
@@ -111,8 +111,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--coarse", default="opt")
-    ap.add_argument("--cg-rtol", type=float, default=3e-10)
-    ap.add_argument("--tol-rel", type=float, default=1e-9)
+    # CG tolerance of the paper's spatial solves (1e-9 relative); MGRIT stops once the C-point residual
+    # norm has dropped by 1e-8, which leaves the error against FP64 sequential stepping at about 4e-9
+    ap.add_argument("--cg-rtol", type=float, default=1e-9)
+    ap.add_argument("--tol-rel", type=float, default=1e-8)
     ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--precond", default="fd-bf16")
     ap.add_argument("--max-levels", type=int, default=3)
