@@ -556,11 +556,11 @@ def test_mixed_511_full_size_sampled(opk):
         assert rel(p32[i], p64[i]) <= 1e-10, (k, rel(p32[i], p64[i]))
 
 
-@pytest.mark.parametrize("cg_rtol,tol_rel", [(3e-10, 1e-9), (1e-9, 1e-8)])
-def test_mixed_511_mgrit_reaches_fp64_sequential(cg_rtol, tol_rel):
+@pytest.mark.parametrize("cg_rtol,cg_coarse,tol_rel", [(3e-10, 1e-3, 1e-9), (1e-9, 5e-3, 1e-8)])
+def test_mixed_511_mgrit_reaches_fp64_sequential(cg_rtol, cg_coarse, tol_rel):
     """511 x 511, graded grid (128 steps here), mixed-precision MGRIT against FP64 sequential stepping:
     relative l2 <= 1e-8 (the bar of the mixed form), also at the benchmark's tolerances (CG 1e-9, MGRIT
-    stop 1e-8)."""
+    stop 1e-8, coarse-level CG 5e-3)."""
     mg = _mg()
     W = wl.mixed_511()
     Nt = 128
@@ -571,11 +571,12 @@ def test_mixed_511_mgrit_reaches_fp64_sequential(cg_rtol, tol_rel):
     with mg.Solver(*common, m=W["m"], precond="fd-bf16", cg_rtol=1e-13) as s:
         ref, _, _ = s.sequential(dev(F), dev(psi0))
     with mg.Solver(*common, m=W["m"], max_levels=3, coarse="opt", precond="fd-bf16", precision="mixed",
-                   cg_rtol=cg_rtol, cg_rtol_coarse=1e-3, tol_abs=0.0, tol_rel=tol_rel, max_iter=40) as s:
+                   cg_rtol=cg_rtol, cg_rtol_coarse=cg_coarse, tol_abs=0.0, tol_rel=tol_rel, max_iter=40) as s:
         U, st, rc = s.solve(dev(F), dev(psi0))
     assert rc == 0
     err = float(torch.linalg.norm(U - ref) / torch.linalg.norm(ref))
-    print(f"511 mixed MGRIT cg_rtol={cg_rtol:g} tol_rel={tol_rel:g}: {st.iterations} iterations, error {err:.3e}")
+    print(f"511 mixed MGRIT cg_rtol={cg_rtol:g} coarse {cg_coarse:g} tol_rel={tol_rel:g}: {st.iterations} iterations, "
+          f"error {err:.3e}")
     assert err <= 1e-8, err
 
 
