@@ -435,15 +435,16 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
 }
 
 // alpha = rho / p.q; d32 += alpha p32, r32 -= alpha q32; partial r32.r32.
+// The element loads are issued before the partial sums are reduced, so the two
+// memory round trips overlap (as in k_mx_direction).
 __global__ __launch_bounds__(NT) void k_mx_update(Geom g, int S, float* __restrict__ d32, float* __restrict__ r32,
-                                                  const float* __restrict__ p32, const float* __restrict__ q32, const double* partial_rho, int nrho,
-                                                  const double* partial_pq, int npq, double* partial_rr_new,
-                                                  const int* active) {
+                                                  const float* __restrict__ p32, const float* __restrict__ q32,
+                                                  const double* partial_rho, int nrho, const double* partial_pq,
+                                                  int npq, double* partial_rr_new, const int* active) {
     int s, c;
     decode_block(g.nchunk, S, s, c);
     if (s < 0 || !active[s]) return;
     __shared__ double red[4];
-    const float alpha = (float)(slice_sum(partial_rho, g.pmax, s, nrho) / slice_sum(partial_pq, g.pmax, s, npq));
     const long long so = (long long)s * g.stride;
     long long lo, hi;
     chunk_range(g, c, lo, hi);
@@ -457,6 +458,7 @@ __global__ __launch_bounds__(NT) void k_mx_update(Geom g, int S, float* __restri
         pv[k] = p32[e];
         qv[k] = q32[e];
     }
+    const float alpha = (float)(slice_sum(partial_rho, g.pmax, s, nrho) / slice_sum(partial_pq, g.pmax, s, npq));
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < PT; ++k) {
@@ -488,7 +490,6 @@ __global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float*
         if (c == 0 && threadIdx.x == 0) active_next[s] = 0;
         return;
     }
-    const float beta = (float)(slice_sum(partial_rho_new, g.pmax, s, nrho_new) / slice_sum(partial_rho, g.pmax, s, nrho));
     const long long so = (long long)s * g.stride;
     long long lo, hi;
     chunk_range(g, c, lo, hi);
@@ -500,6 +501,7 @@ __global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float*
         zv[k] = z32[e];
         pv[k] = p32[e];
     }
+    const float beta = (float)(slice_sum(partial_rho_new, g.pmax, s, nrho_new) / slice_sum(partial_rho, g.pmax, s, nrho));
 #pragma unroll
     for (int k = 0; k < PT; ++k)
         if (e0 + (long long)k * NT <= last) p32[e0 + (long long)k * NT] = zv[k] + beta * pv[k];
@@ -1133,11 +1135,11 @@ __global__ __launch_bounds__(NT) void k_zero_slices(Geom g, int S, const int* id
 // complex transform (real and imaginary part), and two output lines are
 // packed the same way for the inverse transform.  Transforms are Stockham
 // FFTs of L = 512 points (three radix-8 passes) or 1024 points (radix 16, 8,
-// 8), one wavefront per transform, L / 64 points per lane.  The slice's theta scales the spectra, and the 7-point mass stencil
-// enters the x pass as three more (3-tap) kernels, so the x pass writes
-// M v + theta X to a workspace and the y pass adds theta Y and applies the
-// rest of the epilogue (sign, added vector, dot-product partial) as the tiled
-// kernels do.
+// 8), one wavefront per transform, L / 64 points per lane.  The slice's theta scales the kernel
+// spectra of the x pass, where the 7-point mass stencil enters as three more (3-tap) kernels, so
+// the x pass writes M v + theta X to a workspace; the y pass adds theta Y (theta applied to its
+// output) and applies the rest of the epilogue (sign, added vector, dot-product partial) as the
+// tiled kernels do.
 constexpr int FJ = 14;               // output lines per workgroup
 constexpr int FNT = 512;             // threads per workgroup: 8 waves, one input pair each
 template <int L>
@@ -1461,10 +1463,10 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
             const cpx<T> vp = {half * (z2.x + z2c.x), half * (z2.y - z2c.y)};
             const cpx<T> vq = {half * (z2.y + z2c.y), half * (z2c.x - z2.x)};
             cpx<T> c1 = K[k], c2 = K[FL + k], c3 = K[2 * FL + k];
-            c1 = {theta * c1.x, theta * c1.y};
-            c2 = {theta * c2.x, theta * c2.y};
-            c3 = {theta * c3.x, theta * c3.y};
-            if (DIR == 0) {
+            if (DIR == 0) {                  // (the y pass applies theta to its output instead)
+                c1 = {theta * c1.x, theta * c1.y};
+                c2 = {theta * c2.x, theta * c2.y};
+                c3 = {theta * c3.x, theta * c3.y};
                 // the mass stencil as three more kernels of the x pass: 6 v + v(i-1) + v(i+1)
                 // on line j, v(i) + v(i+1) on line j+1, v(i) + v(i-1) on line j-1
                 const cpx<T> w = tw[k];
@@ -1496,7 +1498,7 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
         }
         return;
     }
-    // ---- y pass: stage theta Y as [row][column] and apply the epilogue ----
+    // ---- y pass: stage Y as [row][column] and apply the epilogue with theta ----
     __syncthreads();
     T* stg = (T*)lds;
     if (work) {
@@ -1531,7 +1533,7 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
             const int idx = tid + FNT * (e0 + q);
             const int j = idx / FJ, c = idx - j * FJ, i = l0 + c;
             if (e0 + q >= FE || j >= ny || i >= nx) continue;
-            const T val = sign * (pv[q] + stg[j * 15 + c]) + av[q];
+            const T val = sign * (pv[q] + theta * stg[j * 15 + c]) + av[q];
             out[(long long)j * nx + i] = val;
             if (dot_mode == 1) dot += (double)cv[q] * (double)val;
             else if (dot_mode == 2) dot += (double)val * (double)val;
