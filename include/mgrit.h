@@ -76,9 +76,10 @@ extern "C" {
 #define MGRIT_PREC_MIXED_COARSE 2
 
 /* Preconditioner of the spatial CG solves (Section 3.2 uses none).  FD: exact
- * inverse of the tensor-product (bilinear-element) discretisation of the same
- * operator, applied by fast diagonalisation (see mgrit_fd_eigen); it changes
- * the iteration count only, not the solution the solver converges to. */
+ * inverse of a Kronecker-structured approximation of the step matrix (lumped
+ * mass, cross-lumped stiffness), applied by fast diagonalisation (see
+ * mgrit_fd_eigen); it changes the iteration count only, not the solution the
+ * solver converges to. */
 #define MGRIT_PRECOND_NONE    0
 #define MGRIT_PRECOND_FD      1
 /* FD_BF16: the same preconditioner with its four dense products in BF16 on the
@@ -233,16 +234,18 @@ void mgrit_toeplitz_sequences(double rho, int n, double* t, double* u, double* w
 double mgrit_stiffness_scale(double rho, double h_par, double h_perp);
 
 /* Host-only helpers of the preconditioner (no GPU needed).  The spatial solves
- * may be preconditioned by the exact inverse of the tensor-product (bilinear
- * element) discretisation of the same operator,
+ * may be preconditioned by the exact inverse of a Kronecker-structured
+ * approximation of the step matrix,
  *   P = M_y (x) M_x + theta (M_y (x) K_x + K_y (x) M_x),
- * built from 1-D linear-element matrices M = h/6 tridiag(1, 4, 1) and
+ * built from the 1-D lumped mass M = h I and a weighted 1-D fractional stiffness
  * K[i][j] = K_rho h^(1-2rho) / (2 cos(rho pi) Gamma(4-2rho)) g(|i-j|),
- * g(l) = |l-2|^p - 4|l-1|^p + 6|l|^p - 4|l+1|^p + |l+2|^p, p = 3 - 2 rho.
+ * g(l) = |l-2|^p - 4|l-1|^p + 6|l|^p - 4|l+1|^p + |l+2|^p, p = 3 - 2 rho
+ * (h_y K_x is the block stiffness A_x of Section 2 with its coupling across y
+ * lumped onto the diagonal block; the solver passes 0.9 K_rho).
  * mgrit_fd_stiffness_entry returns K[i][i+l] (binary128 evaluation, rounded).
- * mgrit_fd_eigen solves K v = lambda M v for n nodes: V (n x n, row-major,
- * column i = eigenvector i, normalised so that V^T M V = I) and lambda (n).
- * Returns 0, or a negative value when the eigen-iteration fails. */
+ * mgrit_fd_eigen solves K v = lambda M v, M = h I, for n nodes: V (n x n,
+ * row-major, column i = eigenvector i, normalised so that V^T M V = I) and
+ * lambda (n).  Returns 0, or a negative value when the eigen-iteration fails. */
 double mgrit_fd_stiffness_entry(double rho, double h, double K, int l);
 int mgrit_fd_eigen(double rho, int n, double h, double K, double* V, double* lambda);
 

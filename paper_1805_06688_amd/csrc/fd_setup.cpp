@@ -1,13 +1,16 @@
 // Host set-up of the fast-diagonalisation preconditioner of the spatial solves.
 //
-// The step matrix B = M_h + theta A_h of eq. (chp-02-03) is approximated by
-// the tensor-product (bilinear-element) discretisation of the same operator,
+// The step matrix B = M_h + theta A_h of eq. (chp-02-03) is approximated by a
+// sum of Kronecker products that fast diagonalisation inverts,
 //   P = M_y (x) M_x + theta (M_y (x) K_x + K_y (x) M_x),
-// with 1-D linear-element matrices: mass M = h/6 tridiag(1, 4, 1) and the 1-D
-// fractional stiffness K = K_rho h^(1-2rho) / (2 cos(rho pi) Gamma(4-2rho)) g(|i-j|),
+// with 1-D matrices: the lumped mass M = h I (the row sums of M_h are h_x h_y)
+// and the 1-D fractional stiffness K = K_rho h^(1-2rho) / (2 cos(rho pi) Gamma(4-2rho)) g(|i-j|),
 // g(l) = |l-2|^p - 4|l-1|^p + 6|l|^p - 4|l+1|^p + |l+2|^p, p = 3 - 2rho (the
 // fourth difference of |x|^p: the Riemann-Liouville derivatives of the hat
 // functions integrated against each other, as for the entries of Section 2).
+// h_y K_x equals the block stiffness A_x of Section 2 with its coupling across
+// y lumped onto the diagonal block (c_x (A_1 + A_2 + A_2^T)), and likewise for y.
+// The caller weights K (the solver uses 0.9 K_rho; see build_fd).
 // With the generalised eigenvectors K V = M V diag(lambda), V^T M V = I, of each
 // direction, P^{-1} = (V_y (x) V_x) diag(1 / (1 + theta (lambda_x,i + lambda_y,j))) (V_y (x) V_x)^T.
 //
@@ -150,10 +153,11 @@ extern "C" double mgrit_fd_stiffness_entry(double rho, double h, double K, int l
 
 extern "C" int mgrit_fd_eigen(double rho, int n, double h, double K, double* V, double* lambda) {
     if (n < 1) return -1;
-    // 1-D stiffness (dense symmetric Toeplitz) and mass (tridiagonal)
+    // 1-D stiffness (dense symmetric Toeplitz) and lumped mass h I (the Cholesky
+    // factor below is then sqrt(h) I; the general tridiagonal form is kept)
     std::vector<double> col(n);
     for (int l = 0; l < n; ++l) col[l] = mgrit_fd_stiffness_entry(rho, h, K, l);
-    const double m0 = 4.0 * h / 6.0, m1 = h / 6.0;
+    const double m0 = h, m1 = 0.0;
     // Cholesky of the tridiagonal mass: L = bidiag(dl on the diagonal, el below)
     std::vector<double> dl(n), el(n, 0.0);
     dl[0] = std::sqrt(m0);

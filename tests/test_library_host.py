@@ -72,7 +72,7 @@ def test_setup_rejects_invalid_arguments(kw, code):
 @pytest.mark.parametrize("rho,n,h,K", [(0.75, 255, 1 / 256, 2.0), (0.55, 63, 0.1, 1.0), (0.95, 40, 0.025, 7.5),
                                        (0.8, 1, 0.5, 1.0), (0.8, 2, 0.3, 1.0)])
 def test_fd_eigen_matches_scipy(rho, n, h, K):
-    """Preconditioner set-up: generalised eigenpairs of the 1-D (K, M) pair equal scipy's eigh."""
+    """Preconditioner set-up: generalised eigenpairs of the 1-D (K, M) pair, M = h I (lumped), equal scipy's eigh."""
     import math
     import scipy.linalg as sl
     mg = _lib()
@@ -84,7 +84,7 @@ def test_fd_eigen_matches_scipy(rho, n, h, K):
         scale = K * h ** (1 - 2 * rho) / (2 * math.cos(rho * math.pi) * math.gamma(4 - 2 * rho))
         col = [scale * float(g(l - 2) - 4 * g(l - 1) + 6 * g(l) - 4 * g(l + 1) + g(l + 2)) for l in range(n)]
     Kd = np.array([[col[abs(i - j)] for j in range(n)] for i in range(n)])
-    M = h / 6 * (4 * np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1))
+    M = h * np.eye(n)
     ref = sl.eigh(Kd, M, eigvals_only=True)
     assert np.allclose(np.sort(lam), ref, rtol=1e-11, atol=1e-12 * ref.max())
     assert np.abs(V.T @ M @ V - np.eye(n)).max() < 1e-12
