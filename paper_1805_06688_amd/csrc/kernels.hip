@@ -383,9 +383,11 @@ __global__ __launch_bounds__(NT) void k_apply32(Geom g, Seqs32 sq, const PropDes
 // tolerance eta^2 = max(rtol^2 ||b||^2 / ||r||^2, eta_min^2), r32 = r / ||r||,
 // d32 = 0 and, when p32 is given (no preconditioner), p32 = r32 with partial
 // r32.r32.  On the first step x = 0 where b = 0 and the counts restart.  The
-// inner flag is 2 instead of 1 when eta^2 >= 100 eta_min2.
+// inner flag is 2 instead of 1 when eta^2 >= 100 eta_min2.  RT = float: the
+// residual was formed in FP32 in r32 itself (rws == r32), scaled in place.
+template <typename RT>
 __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restrict__ desc, int S, double* xbase,
-                                                 const double* rws, const double* partial_bb,
+                                                 const RT* rws, const double* partial_bb,
                                                  const double* partial_rr, int np, double rtol2, double eta_min2,
                                                  int first, double* bb, double* scale, double* eta2, int* oact,
                                                  int* iact, int* iters, float* r32, float* d32, float* p32,
@@ -407,10 +409,10 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
     }
     if (active) {
         const double inv = 1.0 / sqrt(r2);
-        const double* r = rws + so;
+        const RT* r = rws + so;
         double acc = 0.0;
         for (long long e = lo + threadIdx.x; e < hi; e += NT) {
-            const float rv = (float)(r[e] * inv);
+            const float rv = (float)((double)r[e] * inv);
             r32[so + e] = rv;
             d32[so + e] = 0.0f;
             if (p32) p32[so + e] = rv;
@@ -552,6 +554,7 @@ __global__ __launch_bounds__(NT) void k_cg_init_x(Geom g, const PropDesc* __rest
     chunk_range(g, c, lo, hi);
     for (long long e = lo + threadIdx.x; e < hi; e += NT) x[e] = src[e];
 }
+
 
 __global__ __launch_bounds__(NT) void k_cg_start(Geom g, const PropDesc* __restrict__ desc, int S,
                                                  double* xbase, const double* zws, double* pws,
@@ -1315,11 +1318,13 @@ __device__ __forceinline__ double block_sum8(double v, double* red) {
 }
 
 // Slice operands of one operator use (MODE as in k_prop_apply: 0 right-hand
-// side, 1 initial residual, 2 CG product; 3 the ApplyDesc form of k_apply).
-template <typename T, int MODE>
-__device__ __forceinline__ void fft_operands(const Geom& g, const void* desc, int s, const T* vbase, const T* wsin,
-                                             const T* addbase, T* outbase, const T*& v, const T*& add, T*& out,
-                                             double& theta) {
+// side, 1 initial residual, 2 CG product; 3 the ApplyDesc form of k_apply).  TV and TA
+// are the element types of v and of the added vector (FP64 operands of an FP32 pass
+// are rounded as they are loaded); wsin holds TA elements in mode 1, TV in mode 2.
+template <typename T, typename TV, typename TA, int MODE>
+__device__ __forceinline__ void fft_operands(const Geom& g, const void* desc, int s, const TV* vbase,
+                                             const void* wsin, const TA* addbase, T* outbase, const TV*& v,
+                                             const TA*& add, T*& out, double& theta) {
     const long long so = (long long)s * g.stride;
     if (MODE == 3) {
         const ApplyDesc d = ((const ApplyDesc*)desc)[s];
@@ -1336,10 +1341,10 @@ __device__ __forceinline__ void fft_operands(const Geom& g, const void* desc, in
         theta = d.theta_rhs;
     } else if (MODE == 1) {
         v = vbase + d.x * g.stride;
-        add = wsin + so;
+        add = (const TA*)wsin + so;
         theta = d.theta_lhs;
     } else {
-        v = wsin + so;
+        v = (const TV*)wsin + so;
         add = nullptr;
         theta = d.theta_lhs;
     }
@@ -1349,9 +1354,9 @@ __device__ __forceinline__ void fft_operands(const Geom& g, const void* desc, in
 // One line pass of the FFT operator.  DIR 0: lines along x, writes
 // pbuf = M v + theta X.  DIR 1: lines along y; out = add + sign (pbuf + theta Y)
 // and, with dot_mode, the block's partial of v.out (1) or out.out (2).
-template <typename T, int DIR, int MODE, int L>
+template <typename T, typename TV, typename TA, int DIR, int MODE, int L>
 __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const void* __restrict__ desc, int S,
-                                         const T* vbase, const T* wsin, const T* addbase, T* outbase, T* pbuf,
+                                         const TV* vbase, const void* wsin, const TA* addbase, T* outbase, T* pbuf,
                                          double sign_d, int dot_mode, double* partial, const int* active) {
     const int nb = DIR == 0 ? pl.nbx : pl.nby;
     int s, blk;
@@ -1361,11 +1366,11 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
     constexpr int NP = FftLen<L>::NP, FPAD = FftLen<L>::PAD, FL = L;
     __shared__ __attribute__((aligned(16))) cpx<T> lds[8 * FPAD];
     __shared__ double red[8];
-    const T* v;
-    const T* add;
+    const TV* v;
+    const TA* add;
     T* out;
     double theta_d;
-    fft_operands<T, MODE>(g, desc, s, vbase, wsin, addbase, outbase, v, add, out, theta_d);
+    fft_operands<T, TV, TA, MODE>(g, desc, s, vbase, wsin, addbase, outbase, v, add, out, theta_d);
     const T theta = (T)theta_d;
     const T sign = (T)sign_d;
     constexpr int FE = FftLen<L>::FE;
@@ -1399,8 +1404,8 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
 #pragma unroll
         for (int r = 0; r < NP; ++r) {
             const int pos = lane + 64 * r;
-            a[r].x = (la >= 0 && la < nl && pos < n) ? v[(long long)la * nx + pos] : T(0);
-            a[r].y = (lb >= 0 && lb < nl && pos < n) ? v[(long long)lb * nx + pos] : T(0);
+            a[r].x = (la >= 0 && la < nl && pos < n) ? (T)v[(long long)la * nx + pos] : T(0);
+            a[r].y = (lb >= 0 && lb < nl && pos < n) ? (T)v[(long long)lb * nx + pos] : T(0);
         }
         if constexpr (KST) {
 #pragma unroll
@@ -1418,7 +1423,7 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
 #pragma unroll
         for (int q = 0; q < SG; ++q) {
             const int idx = tid + FNT * q, pos = idx >> 4, col = l0 - 1 + (idx & 15);
-            sv[q] = (pos < ny && col >= 0 && col < nx) ? v[(long long)pos * nx + col] : T(0);
+            sv[q] = (pos < ny && col >= 0 && col < nx) ? (T)v[(long long)pos * nx + col] : T(0);
         }
 #pragma unroll
         for (int q = 0; q < SG; ++q) {
@@ -1525,8 +1530,8 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
             const bool in = e0 + q < FE && j < ny && i < nx;
             const long long o = (long long)j * nx + i;
             pv[q] = in ? P[o] : T(0);
-            av[q] = (in && add) ? add[o] : T(0);
-            cv[q] = (in && dot_mode == 1) ? v[o] : T(0);
+            av[q] = (in && add) ? (T)add[o] : T(0);
+            cv[q] = (in && dot_mode == 1) ? (T)v[o] : T(0);
         }
 #pragma unroll
         for (int q = 0; q < FG; ++q) {
@@ -1550,48 +1555,51 @@ __global__ __launch_bounds__(FNT) void k_fft_line(Geom g, FftPlan pl, const void
                                                   const T* vbase, const T* wsin, const T* addbase, T* outbase,
                                                   T* pbuf, double sign_d, int dot_mode, double* partial,
                                                   const int* active) {
-    fft_line<T, DIR, MODE, L>(g, pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign_d, dot_mode, partial,
-                              active);
+    fft_line<T, T, T, DIR, MODE, L>(g, pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign_d, dot_mode, partial,
+                                    active);
 }
 
 // the FP32 instance with a register budget of three (L = 512) or two workgroups per compute unit
-template <int DIR, int MODE, int L>
+template <int DIR, int MODE, int L, typename TV, typename TA>
 __global__ __launch_bounds__(FNT, L == 512 ? 6 : 4) void k_fft_line32(Geom g, FftPlan pl, const void* __restrict__ desc,
-                                                                      int S, const float* vbase, const float* wsin,
-                                                                      const float* addbase, float* outbase,
+                                                                      int S, const TV* vbase, const void* wsin,
+                                                                      const TA* addbase, float* outbase,
                                                                       float* pbuf, double sign_d, int dot_mode,
                                                                       double* partial, const int* active) {
-    fft_line<float, DIR, MODE, L>(g, pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign_d, dot_mode, partial,
-                                  active);
+    fft_line<float, TV, TA, DIR, MODE, L>(g, pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign_d, dot_mode,
+                                          partial, active);
 }
 
-template <typename T, int MODE, int L>
-void fft_op_len(const Geom* g, const FftPlan* pl, const void* desc, int S, const T* vbase, const T* wsin,
-                const T* addbase, T* outbase, T* pbuf, double sign, int dot_mode, double* partial,
+template <typename T, int MODE, int L, typename TV, typename TA>
+void fft_op_len(const Geom* g, const FftPlan* pl, const void* desc, int S, const TV* vbase, const void* wsin,
+                const TA* addbase, T* outbase, T* pbuf, double sign, int dot_mode, double* partial,
                 const int* active, hipStream_t st) {
     if constexpr (sizeof(T) == 4) {
-        hipLaunchKernelGGL((k_fft_line32<0, MODE, L>), dim3(grid_blocks(pl->nbx, S)), dim3(FNT), 0, st, *g, *pl,
-                           desc, S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
-        hipLaunchKernelGGL((k_fft_line32<1, MODE, L>), dim3(grid_blocks(pl->nby, S)), dim3(FNT), 0, st, *g, *pl,
-                           desc, S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
+        hipLaunchKernelGGL((k_fft_line32<0, MODE, L, TV, TA>), dim3(grid_blocks(pl->nbx, S)), dim3(FNT), 0, st, *g,
+                           *pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
+        hipLaunchKernelGGL((k_fft_line32<1, MODE, L, TV, TA>), dim3(grid_blocks(pl->nby, S)), dim3(FNT), 0, st, *g,
+                           *pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
     } else {
         hipLaunchKernelGGL((k_fft_line<T, 0, MODE, L>), dim3(grid_blocks(pl->nbx, S)), dim3(FNT), 0, st, *g, *pl,
-                           desc, S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
+                           desc, S, vbase, (const T*)wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
         hipLaunchKernelGGL((k_fft_line<T, 1, MODE, L>), dim3(grid_blocks(pl->nby, S)), dim3(FNT), 0, st, *g, *pl,
-                           desc, S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
+                           desc, S, vbase, (const T*)wsin, addbase, outbase, pbuf, sign, dot_mode, partial, active);
     }
 }
 
-template <typename T, int MODE>
-void fft_op(const Geom* g, const FftPlan* pl, const void* desc, int S, const T* vbase, const T* wsin,
-            const T* addbase, T* outbase, T* pbuf, double sign, int dot_mode, double* partial, const int* active,
+// vbase and addbase hold TV and TA elements (both T unless given).
+template <typename T, int MODE, typename TV = T, typename TA = T>
+void fft_op(const Geom* g, const FftPlan* pl, const void* desc, int S, const void* vbase, const void* wsin,
+            const void* addbase, T* outbase, T* pbuf, double sign, int dot_mode, double* partial, const int* active,
             hipStream_t st) {
+    const TV* v = (const TV*)vbase;
+    const TA* a = (const TA*)addbase;
     if (pl->L == 512)
-        fft_op_len<T, MODE, 512>(g, pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial,
-                                 active, st);
+        fft_op_len<T, MODE, 512, TV, TA>(g, pl, desc, S, v, wsin, a, outbase, pbuf, sign, dot_mode, partial, active,
+                                         st);
     else
-        fft_op_len<T, MODE, 1024>(g, pl, desc, S, vbase, wsin, addbase, outbase, pbuf, sign, dot_mode, partial,
-                                  active, st);
+        fft_op_len<T, MODE, 1024, TV, TA>(g, pl, desc, S, v, wsin, a, outbase, pbuf, sign, dot_mode, partial,
+                                          active, st);
 }
 
 template <int TT>
@@ -1781,9 +1789,15 @@ int launch_mx_begin(const Geom* g, const PropDesc* desc, int S, double* xbase, c
                     int first, double* bb, double* scale, double* eta2, int* oact, int* iact, int* iters, float* r32,
                     float* d32, float* p32, double* partial_rr32, void* stream) {
     if (S <= 0) return 0;
-    hipLaunchKernelGGL(k_mx_begin, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, desc, S,
-                       xbase, rws, partial_bb, partial_rr, np, rtol2, eta_min2, first, bb, scale, eta2, oact, iact,
-                       iters, r32, d32, p32, partial_rr32);
+    const dim3 grid(grid_blocks(g->nchunk, S)), blk(NT);
+    if (rws)
+        hipLaunchKernelGGL(k_mx_begin<double>, grid, blk, 0, (hipStream_t)stream, *g, desc, S, xbase, rws,
+                           partial_bb, partial_rr, np, rtol2, eta_min2, first, bb, scale, eta2, oact, iact, iters, r32,
+                           d32, p32, partial_rr32);
+    else
+        hipLaunchKernelGGL(k_mx_begin<float>, grid, blk, 0, (hipStream_t)stream, *g, desc, S, xbase,
+                           (const float*)r32, partial_bb, partial_rr, np, rtol2, eta_min2, first, bb, scale, eta2,
+                           oact, iact, iters, r32, d32, p32, partial_rr32);
     return (int)hipGetLastError();
 }
 
@@ -1860,6 +1874,22 @@ int launch_fft_cg_apply(const Geom* g, const FftPlan* pl, const PropDesc* desc, 
     if (S <= 0) return 0;
     fft_op<double, 2>(g, pl, desc, S, nullptr, pws, nullptr, qws, pbuf, 1.0, 1, partial_pq, active,
                       (hipStream_t)stream);
+    return (int)hipGetLastError();
+}
+
+int launch_fft_rhs32(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const double* ubase,
+                     const double* fbase, float* b32, double* partial_bb, float* pbuf, void* stream) {
+    if (S <= 0) return 0;
+    fft_op<float, 0, double, double>(g, pl, desc, S, ubase, nullptr, fbase, b32, pbuf, 1.0, 2, partial_bb, nullptr,
+                                     (hipStream_t)stream);
+    return (int)hipGetLastError();
+}
+
+int launch_fft_init_residual32(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const double* xbase,
+                               const float* b32, float* r32, double* partial_rr, float* pbuf, void* stream) {
+    if (S <= 0) return 0;
+    fft_op<float, 1, double, float>(g, pl, desc, S, xbase, b32, nullptr, r32, pbuf, -1.0, 2, partial_rr, nullptr,
+                                    (hipStream_t)stream);
     return (int)hipGetLastError();
 }
 

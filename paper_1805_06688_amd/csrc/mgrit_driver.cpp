@@ -510,6 +510,10 @@ unsigned short to_bf16(double v) {
 // 0.55..0.95 and theta from 5e-4 to 0.25 at 255 x 255).
 constexpr double FD_STIFFNESS_WEIGHT = 0.9;
 
+// Mixed-precision passes whose CG tolerance is at least this run wholly in FP32
+// (right-hand side, initial residual, one refinement step).
+constexpr double COARSE_FP32_RTOL = 1e-4;
+
 int build_fd(mgrit_handle* h) {
     const mgrit_problem& p = h->prob;
     const int nx = p.Mx - 1, ny = p.My - 1;
@@ -932,18 +936,31 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
     const int nop = h->nop, npc = g->ntiles[1], nc = g->nchunk;
     const int maxit = h->opt.cg_maxit;
     int tv = 0, tv32 = -1;
-    CHK(tile_variant(h, nullptr, S, &tv));
-    HIPCHK(op_rhs(h, tv, ps, ubase, fbase));
-    CHK(tile_variant(h, &ps, S, &tv));
-    HIPCHK(launch_cg_init_x(g, ps.d, S, ubase, x0base, (x0base && warm && h->opt.warm_start) ? 1 : 0, xbase, st));
-    HIPCHK(op_resid(h, tv, ps, xbase, h->pout));
+    // Loose passes (coarse levels) form the right-hand side and the initial residual in FP32 as
+    // well: their rounding (~1e-7 of ||b||) is far below the tolerance, and one refinement step,
+    // whose inner target is then the pass tolerance itself, settles the pass.
+    const bool all32 = h->use_fft && rtol >= COARSE_FP32_RTOL;
+    if (all32) {
+        HIPCHK(launch_cg_init_x(g, ps.d, S, ubase, x0base, (x0base && warm && h->opt.warm_start) ? 1 : 0, xbase,
+                                st));
+        HIPCHK(launch_fft_rhs32(g, &h->plan, ps.d, S, ubase, fbase, h->z32, h->pbb, h->pfft32, h->stream));
+        HIPCHK(launch_fft_init_residual32(g, &h->plan, ps.d, S, xbase, h->z32, h->r32, h->pout, h->pfft32,
+                                          h->stream));
+    } else {
+        CHK(tile_variant(h, nullptr, S, &tv));
+        HIPCHK(op_rhs(h, tv, ps, ubase, fbase));
+        CHK(tile_variant(h, &ps, S, &tv));
+        HIPCHK(launch_cg_init_x(g, ps.d, S, ubase, x0base, (x0base && warm && h->opt.warm_start) ? 1 : 0, xbase,
+                                st));
+        HIPCHK(op_resid(h, tv, ps, xbase, h->pout));
+    }
     float* zws = pc ? h->z32 : h->r32;
     double** prho = pc ? h->prz : h->prr;        // rho = r.z (r.r without preconditioner)
     int steps = 0;
     for (int outer = 0; outer < 32; ++outer) {
-        HIPCHK(launch_mx_begin(g, ps.d, S, xbase, h->r, h->pbb, h->pout, nop, rtol2, eta * eta, outer == 0 ? 1 : 0,
-                               h->bb, h->mx_scale, h->mx_eta2, h->mx_oact, h->act[0], h->iters, h->r32, h->d32,
-                               pc ? nullptr : h->p32, h->prr[0], st));
+        HIPCHK(launch_mx_begin(g, ps.d, S, xbase, all32 ? nullptr : h->r, h->pbb, h->pout, nop, rtol2, eta * eta,
+                               outer == 0 ? 1 : 0, h->bb, h->mx_scale, h->mx_eta2, h->mx_oact, h->act[0], h->iters,
+                               h->r32, h->d32, pc ? nullptr : h->p32, h->prr[0], st));
         if (tv32 < 0) CHK(tile_variant(h, &ps, S, &tv32, true));
         if (pc)
             HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, h->p32, h->tb1, h->tb2, h->prz[0],
@@ -983,7 +1000,7 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
         // the FP32 residual it reached agrees with the FP64 one to FP32 rounding (about 1e-6 of the
         // step's starting residual, 1 % of the smallest such target), so the FP64 check is skipped.  Steps
         // that ran to the floor (the first ones at tight tolerances) are always checked in FP64.
-        if (untrusted == 0) break;
+        if (untrusted == 0 || all32) break;
         HIPCHK(op_resid(h, tv, ps, xbase, h->pout));
     }
     HIPCHK(launch_add_g(g, ps.d, S, xbase, gbase, st));

@@ -170,7 +170,8 @@ int launch_fdb_apply32(const Geom* g, const FdMatsB* fd, const PropDesc* desc, i
 // q32 = M p32 + theta_lhs A p32 (FP32 matrix cores) for active slices, partial p.q.
 int launch_apply32(const Geom* g, const Seqs32* sq, int tv, const PropDesc* desc, int S, const float* p32,
                    float* q32, double* partial_pq, const int* active, void* stream);
-// Start of a refinement step from the FP64 residual: flags, scale ||r||, inner tolerance
+// Start of a refinement step from the FP64 residual (or, with rws == NULL, from an FP32
+// residual already in r32, scaled in place): flags, scale ||r||, inner tolerance
 // eta^2 = max(rtol^2 ||b||^2 / ||r||^2, eta_min2), r32 = r / ||r||, d32 = 0, and p32 = r32
 // with partial r32.r32 when p32 != NULL; first: x = 0 where b = 0, counts reset.
 int launch_mx_begin(const Geom* g, const PropDesc* desc, int S, double* xbase, const double* rws,
@@ -202,6 +203,13 @@ int launch_fft_cg_apply(const Geom* g, const FftPlan* pl, const PropDesc* desc, 
                         double* qws, double* partial_pq, const int* active, double* pbuf, void* stream);
 int launch_fft_apply32(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const float* p32, float* q32,
                        double* partial_pq, const int* active, float* pbuf, void* stream);
+// The right-hand side and the initial residual computed in FP32 from the FP64 U, F and X
+// (rounded as they are loaded) into slot s of b32 and r32: b32 = M u + theta_rhs A u + f,
+// partial ||b||^2; r32 = b32 - (M x + theta_lhs A x), partial ||r||^2.
+int launch_fft_rhs32(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const double* ubase,
+                     const double* fbase, float* b32, double* partial_bb, float* pbuf, void* stream);
+int launch_fft_init_residual32(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const double* xbase,
+                               const float* b32, float* r32, double* partial_rr, float* pbuf, void* stream);
 
 // x[s] += G[s] for slices with g >= 0.
 int launch_add_g(const Geom* g, const PropDesc* desc, int S, double* xbase, const double* gbase, void* stream);
