@@ -68,10 +68,13 @@ extern "C" {
  * reductions) to the relative tolerance max(rtol ||b|| / ||r||, inner_rtol).
  * The solution is the FP64 one to the CG tolerance; a refinement step whose
  * inner target was the pass tolerance itself (rtol ||b|| / ||r|| >= 10 x
- * inner_rtol, e.g. the last step, or the only one at loose coarse-level
- * tolerances) is accepted without recomputing the FP64 residual.  MIXED_COARSE: FP64 on
- * level 0 (and in sequential stepping), MIXED on the coarse levels.  Both take
- * precond NONE or FD_BF16. */
+ * inner_rtol, e.g. the last step) is accepted without recomputing the FP64
+ * residual.  Passes whose CG tolerance is 1e-4 or looser (the coarse levels at
+ * the usual cg_rtol_coarse) run wholly in FP32 with the FFT operator: right-hand
+ * side and initial residual from the FP64 data rounded on load, one refinement
+ * step (FP32 rounding, ~1e-7 of ||b||, is far below such a tolerance).
+ * MIXED_COARSE: FP64 on level 0 (and in sequential stepping), MIXED on the
+ * coarse levels.  Both take precond NONE or FD_BF16. */
 #define MGRIT_PREC_MIXED        1
 #define MGRIT_PREC_MIXED_COARSE 2
 
