@@ -93,6 +93,32 @@ def test_fd_eigen_matches_scipy(rho, n, h, K):
         assert mg.fd_stiffness_entry(rho, h, K, l) == pytest.approx(Kd[0, l], rel=1e-12)
 
 
+@pytest.mark.parametrize("beta,gamma,Kx,Ky,n", [(0.75, 0.85, 2.0, 1.0, 31), (0.55, 0.95, 1.0, 3.0, 31),
+                                                 (0.9, 0.6, 1.0, 1.0, 24)])
+def test_fd_preconditioner_spectrum(beta, gamma, Kx, Ky, n):
+    """The solver's preconditioner P (lumped 1-D mass, 1-D stiffness weighted 0.9, from mgrit_fd_eigen)
+    against the step matrix B = M_h + theta A_h assembled by the oracle: where the stiffness dominates
+    (theta >= 0.03 here) the spectrum of P^-1 B lies in [0.75, 1.2] (condition number <= 1.45; the
+    bilinear-element pair gives about 3 on the same problems); with theta = 0 it is the ratio of M_h to
+    the lumped mass, within (1/4, 1]."""
+    from oracle import fem
+    mg = _lib()
+    prob = fem.Problem(beta, gamma, Kx, Ky, n + 1, n + 1)
+    op = fem.Operator(prob)
+    M, A = op.assembled_M(), op.assembled_A()
+    Vx, lx = mg.fd_eigen(beta, n, prob.hx, 0.9 * Kx)
+    Vy, ly = mg.fd_eigen(gamma, n, prob.hy, 0.9 * Ky)
+    W = np.kron(Vy, Vx)                                   # x fastest: slice index j n_x + i
+    for theta in (0.0, 0.03, 1.0):
+        D = 1.0 + theta * (ly[:, None] + lx[None, :]).ravel()
+        lam = np.linalg.eigvals((W / D) @ W.T @ (M + theta * A)).real
+        if theta == 0.0:
+            assert 0.24 < lam.min() and lam.max() <= 1.0 + 1e-12, (lam.min(), lam.max())
+        else:
+            assert 0.75 <= lam.min() and lam.max() <= 1.2 and lam.max() / lam.min() <= 1.45, (theta, lam.min(),
+                                                                                             lam.max())
+
+
 def test_footprint_grows_with_the_problem():
     mg = _lib()
     t1 = np.linspace(0, 1, 65)
