@@ -136,6 +136,7 @@ struct mgrit_handle {
     int* h_act = nullptr;                    // pinned, two buffers of Smax flags
     hipEvent_t flag_ev[2] = {};
     int* h_iters = nullptr;                  // pinned
+    int* h_iters_step = nullptr;             // pinned, 4 x Smax: iteration counts after each refinement step
     double* h_norm = nullptr;                // pinned
     long long phi_count = 0, cg_count = 0;
     std::vector<void*> allocations;
@@ -635,6 +636,7 @@ int alloc_workspace(mgrit_handle* h, int S) {
     HIPCHK(hipHostMalloc((void**)&h->h_act, 2 * S * sizeof(int), hipHostMallocDefault));
     for (hipEvent_t& e : h->flag_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPCHK(hipHostMalloc((void**)&h->h_iters, S * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&h->h_iters_step, 4 * (size_t)S * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&h->h_norm, S * nt * sizeof(double), hipHostMallocDefault));
     return 0;
 }
@@ -884,7 +886,7 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     const int maxit = h->opt.cg_maxit;
     // The first chunk covers what this pass needed last time, later chunks are
     // short, so few launches find every slice converged.
-    const int first = ps.last_iters > 0 ? std::max(1, ps.last_iters - 1) : (pc ? 8 : 16);
+    const int first = ps.last_iters > 0 ? ps.last_iters : (pc ? 8 : 16);
     auto iter = [&](int c0, int nr) -> int {
         const int nxt = c0 ^ 1;
         if (h->prof_on) CHK(prof_record(h, tv));
@@ -956,7 +958,7 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
     }
     float* zws = pc ? h->z32 : h->r32;
     double** prho = pc ? h->prz : h->prr;        // rho = r.z (r.r without preconditioner)
-    int steps = 0;
+    int steps = 0, nrec = 0;
     for (int outer = 0; outer < 32; ++outer) {
         HIPCHK(launch_mx_begin(g, ps.d, S, xbase, all32 ? nullptr : h->r, h->pbb, h->pout, nop, rtol2, eta * eta,
                                outer == 0 ? 1 : 0, h->bb, h->mx_scale, h->mx_eta2, h->mx_oact, h->act[0], h->iters,
@@ -986,14 +988,20 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
             return launch_iterations(h, {ps.d, nullptr, S, tv32, nrho, nrho_next, maxit, 0, 1, 0.0}, n, cur, nrho,
                                      iter);
         };
-        // the flags at the start are the outer ones: none active ends the refinement
+        // the flags at the start are the outer ones: none active ends the refinement.  The first
+        // chunk is what the slowest slice of this step needed last time (then one iteration at a
+        // time, one queued ahead of each flag check).
         const int li = ps.last_inner[std::min(outer, 3)];
-        const int first = li > 0 ? std::max(1, li - 1) : 6;
+        const int first = li > 0 ? li : 6;
         int untrusted = 0;
         CHK(run_checked(h, S, first, maxit, outer > 0, cur, it, &nact, chunk, &untrusted));
         if (nact == 0) break;
         steps += nact;
-        ps.last_inner[std::min(outer, 3)] = it;
+        if (outer < 4) {                     // counts after this step, read once the pass has ended
+            HIPCHK(hipMemcpyAsync(h->h_iters_step + (size_t)outer * h->Smax, h->iters, S * sizeof(int),
+                                  hipMemcpyDeviceToHost, h->stream));
+            nrec = outer + 1;
+        }
         HIPCHK(launch_mx_refine(g, ps.d, S, xbase, h->d32, h->mx_scale, h->mx_oact, st));
         // When every inner solve of this step had the pass tolerance itself as its target and that
         // target is at least 10 x the FP32 floor (inner flag 2), its own test settles the slice:
@@ -1009,6 +1017,13 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
     if (h->prof_on) CHK(prof_drain(h));
     long long its = 0;
     for (int s = 0; s < S; ++s) its += h->h_iters[s];
+    for (int k = 0; k < nrec; ++k) {         // iterations the slowest slice needed in step k
+        const int* c = h->h_iters_step + (size_t)k * h->Smax;
+        const int* p = k > 0 ? c - h->Smax : nullptr;
+        int most = 0;
+        for (int s = 0; s < S; ++s) most = std::max(most, c[s] - (p ? p[s] : 0));
+        ps.last_inner[k] = most;
+    }
     h->cg_count += its;
     h->refine_count += steps;
     if (h->prof_on && tv32 >= 0) h->prof_slices[2 + tv32] += its;
@@ -1330,6 +1345,7 @@ void mgrit_destroy(mgrit_handle* h) {
     for (hipEvent_t e : h->flag_ev)
         if (e) (void)hipEventDestroy(e);
     if (h->h_iters) (void)hipHostFree(h->h_iters);
+    if (h->h_iters_step) (void)hipHostFree(h->h_iters_step);
     if (h->h_norm) (void)hipHostFree(h->h_norm);
     delete h;
 }
