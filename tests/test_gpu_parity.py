@@ -382,6 +382,29 @@ def test_mixed_precision_propagate_matches_oracle(level, coarse, pc):
         assert rel(out[i], ref) <= 1e-10, (i, rel(out[i], ref))
 
 
+@pytest.mark.parametrize("pc", ["fd-bf16", "none"])
+def test_loose_mixed_pass_meets_its_tolerance(pc):
+    """A mixed-precision pass at a CG tolerance of 1e-4 or looser forms its right-hand side and initial
+    residual in FP32 (from the FP64 data) and settles in one refinement step; its result still meets the
+    stop criterion ||b - B x|| <= rtol ||b||, b = C u + F, evaluated in FP64 by the oracle."""
+    mg = _mg()
+    beta, gamma, Kx, Ky, Mx, My = 0.65, 0.9, 1.5, 1.0, 80, 70
+    prob = fem.Problem(beta, gamma, Kx, Ky, Mx, My)
+    op = fem.Operator(prob)
+    t = wl.random_grid(17, 9)
+    steps = [1, 4, 8]
+    u = wl.random_slices(61, 3, prob.nx, prob.ny)
+    f = wl.random_slices(62, 3, prob.nx, prob.ny)
+    rtol = 2e-3
+    with mg.Solver(beta, gamma, Kx, Ky, Mx, My, t, m=4, cg_rtol=rtol, precond=pc, precision="mixed") as s:
+        out = host(s.propagate(0, steps, dev(u), dev(f)))
+    for i, k in enumerate(steps):
+        tau = t[k] - t[k - 1]
+        b = op.apply_C(u[i], tau) + f[i]
+        r = b - op.apply_B(out[i], tau)
+        assert np.linalg.norm(r) <= 1.01 * rtol * np.linalg.norm(b), (i, np.linalg.norm(r) / np.linalg.norm(b))
+
+
 @pytest.mark.parametrize("precision", ["mixed", "mixed-coarse"])
 def test_mixed_precision_solve_reaches_sequential(precision):
     mg = _mg()
