@@ -484,12 +484,16 @@ __global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float*
                                                      const double* partial_rho, int nrho,
                                                      const double* partial_rho_new, int nrho_new,
                                                      const double* partial_rr_new, const double* eta2, int maxit,
-                                                     const int* active, int* active_next, int* iters) {
+                                                     const int* active, int* active_next, int* iters,
+                                                     int* host_next) {
     int s, c;
     decode_block(g.nchunk, S, s, c);
     if (s < 0) return;
     if (!active[s]) {
-        if (c == 0 && threadIdx.x == 0) active_next[s] = 0;
+        if (c == 0 && threadIdx.x == 0) {
+            active_next[s] = 0;
+            if (host_next) host_next[s] = 0;
+        }
         return;
     }
     const long long so = (long long)s * g.stride;
@@ -511,7 +515,9 @@ __global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float*
         const double rrn = slice_sum(partial_rr_new, g.pmax, s, g.nchunk);
         const int it = iters[s] + 1;
         iters[s] = it;
-        active_next[s] = (rrn > eta2[s] && it < maxit) ? 1 : 0;
+        const int flag = (rrn > eta2[s] && it < maxit) ? 1 : 0;
+        active_next[s] = flag;
+        if (host_next) host_next[s] = flag;
     }
 }
 
@@ -635,12 +641,16 @@ __global__ __launch_bounds__(NT) void k_cg_direction(Geom g, int S, const double
                                                      const double* partial_rho, int nrho,
                                                      const double* partial_rho_new, int nrho_new,
                                                      const double* partial_rr_new, const double* bb, double rtol2,
-                                                     int maxit, const int* active, int* active_next, int* iters) {
+                                                     int maxit, const int* active, int* active_next, int* iters,
+                                                     int* host_next) {
     int s, c;
     decode_block(g.nchunk, S, s, c);
     if (s < 0) return;
     if (!active[s]) {
-        if (c == 0 && threadIdx.x == 0) active_next[s] = 0;
+        if (c == 0 && threadIdx.x == 0) {
+            active_next[s] = 0;
+            if (host_next) host_next[s] = 0;
+        }
         return;
     }
     const double rho = slice_sum(partial_rho, g.pmax, s, nrho);
@@ -666,7 +676,9 @@ __global__ __launch_bounds__(NT) void k_cg_direction(Geom g, int S, const double
         const double rrn = slice_sum(partial_rr_new, g.pmax, s, g.nchunk);
         const int it = iters[s] + 1;
         iters[s] = it;
-        active_next[s] = (rrn > rtol2 * bb[s] && it < maxit) ? 1 : 0;
+        const int flag = (rrn > rtol2 * bb[s] && it < maxit) ? 1 : 0;
+        active_next[s] = flag;
+        if (host_next) host_next[s] = flag;
     }
 }
 
@@ -1696,11 +1708,12 @@ int launch_cg_update(const Geom* g, const PropDesc* desc, int S, double* xbase, 
 
 int launch_cg_direction(const Geom* g, int S, const double* zws, double* pws, const double* partial_rho, int nrho,
                         const double* partial_rho_new, int nrho_new, const double* partial_rr_new, const double* bb,
-                        double rtol2, int maxit, const int* active, int* active_next, int* iters, void* stream) {
+                        double rtol2, int maxit, const int* active, int* active_next, int* iters, int* host_next,
+                        void* stream) {
     if (S <= 0) return 0;
     hipLaunchKernelGGL(k_cg_direction, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, S, zws,
                        pws, partial_rho, nrho, partial_rho_new, nrho_new, partial_rr_new, bb, rtol2, maxit, active,
-                       active_next, iters);
+                       active_next, iters, host_next);
     return (int)hipGetLastError();
 }
 
@@ -1812,11 +1825,11 @@ int launch_mx_update(const Geom* g, int S, float* d32, float* r32, const float* 
 
 int launch_mx_direction(const Geom* g, int S, const float* z32, float* p32, const double* partial_rho, int nrho,
                         const double* partial_rho_new, int nrho_new, const double* partial_rr_new, const double* eta2,
-                        int maxit, const int* active, int* active_next, int* iters, void* stream) {
+                        int maxit, const int* active, int* active_next, int* iters, int* host_next, void* stream) {
     if (S <= 0) return 0;
     hipLaunchKernelGGL(k_mx_direction, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, S,
                        z32, p32, partial_rho, nrho, partial_rho_new, nrho_new, partial_rr_new, eta2, maxit, active,
-                       active_next, iters);
+                       active_next, iters, host_next);
     return (int)hipGetLastError();
 }
 

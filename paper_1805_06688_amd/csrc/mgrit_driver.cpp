@@ -133,7 +133,9 @@ struct mgrit_handle {
     long long refine_count = 0;             // refinement steps summed over slices
     int* act[2] = {nullptr, nullptr};
     int* iters = nullptr;
-    int* h_act = nullptr;                    // pinned, two buffers of Smax flags
+    int* h_act = nullptr;                    // pinned, two buffers of Smax flags (copies of act at a check)
+    int* h_flags = nullptr;                  // pinned, 2 x Smax: act[0], act[1] as the direction kernels set them
+    int* d_flags = nullptr;                  // the device address of h_flags
     hipEvent_t flag_ev[2] = {};
     int* h_iters = nullptr;                  // pinned
     int* h_iters_step = nullptr;             // pinned, 4 x Smax: iteration counts after each refinement step
@@ -634,6 +636,9 @@ int alloc_workspace(mgrit_handle* h, int S) {
         }
     }
     HIPCHK(hipHostMalloc((void**)&h->h_act, 2 * S * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&h->h_flags, 2 * S * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void**)&h->d_flags, h->h_flags, 0));
+    for (int i = 0; i < 2 * S; ++i) h->h_flags[i] = 0;
     for (hipEvent_t& e : h->flag_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPCHK(hipHostMalloc((void**)&h->h_iters, S * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&h->h_iters_step, 4 * (size_t)S * sizeof(int), hipHostMallocDefault));
@@ -793,17 +798,27 @@ int launch_iterations(mgrit_handle* h, mgrit_handle::GraphKey key, int n, int& c
 // the check; the one iteration queued after the last slice converged finds
 // every slice inactive and does nothing.  sync_first: wait for the flags at
 // the start before queueing anything (when all slices are likely converged).
-// *n_active0: active slices at the start.
+// *n_active0: active slices at the start.  The flags at the start are copied
+// (a snapshot: the first chunk may set the same parity again while the host
+// reads); later checks read the pinned mirror the direction kernels write,
+// h_flags[parity], which the single queued iteration does not touch (it
+// writes the other parity).
 int run_checked(mgrit_handle* h, int S, int n_first, int maxit, bool sync_first, int& cur, int& it,
                 int* n_active0, const std::function<int(int)>& launch_chunk, int* n_ones0 = nullptr) {
-    auto queue_flags = [&](int k) -> int {
-        HIPCHK(hipMemcpyAsync(h->h_act + (size_t)k * h->Smax, h->act[cur], S * sizeof(int), hipMemcpyDeviceToHost,
-                              h->stream));
+    const int* src[2] = {nullptr, nullptr};
+    auto queue_flags = [&](int k, bool snapshot) -> int {
+        if (snapshot) {
+            HIPCHK(hipMemcpyAsync(h->h_act + (size_t)k * h->Smax, h->act[cur], S * sizeof(int),
+                                  hipMemcpyDeviceToHost, h->stream));
+            src[k] = h->h_act + (size_t)k * h->Smax;
+        } else {
+            src[k] = h->h_flags + (size_t)cur * h->Smax;
+        }
         HIPCHK(hipEventRecord(h->flag_ev[k], h->stream));
         return 0;
     };
     auto count = [&](int k) -> int {
-        const int* f = h->h_act + (size_t)k * h->Smax;
+        const int* f = src[k];
         int nact = 0, ones = 0;
         for (int s = 0; s < S; ++s) {
             nact += f[s] != 0;
@@ -815,7 +830,7 @@ int run_checked(mgrit_handle* h, int S, int n_first, int maxit, bool sync_first,
         }
         return nact;
     };
-    CHK(queue_flags(0));
+    CHK(queue_flags(0, true));
     if (sync_first) {
         HIPCHK(hipEventSynchronize(h->flag_ev[0]));
         const int nact = count(0);
@@ -829,7 +844,7 @@ int run_checked(mgrit_handle* h, int S, int n_first, int maxit, bool sync_first,
         if (launched) {
             CHK(launch_chunk(n));
             it += n;
-            CHK(queue_flags(k ^ 1));
+            CHK(queue_flags(k ^ 1, false));
         }
         HIPCHK(hipEventSynchronize(h->flag_ev[k]));
         const int nact = count(k);
@@ -896,7 +911,8 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
                                 h->act[c0], st));
         if (pc) HIPCHK(precondition(h->prz[nxt], h->act[c0]));
         HIPCHK(launch_cg_direction(g, S, zws, h->p, prho[c0], nr, prho[nxt], nrho_next, h->prr[nxt], h->bb, rtol2,
-                                   maxit, h->act[c0], h->act[nxt], h->iters, st));
+                                   maxit, h->act[c0], h->act[nxt], h->iters, h->d_flags + (size_t)nxt * h->Smax,
+                                   st));
         return 0;
     };
     auto chunk = [&](int n) -> int {
@@ -981,7 +997,8 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
                 HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, nullptr, h->tb1, h->tb2, h->prz[nxt],
                                           h->act[c0], st));
             HIPCHK(launch_mx_direction(g, S, zws, h->p32, prho[c0], nr, prho[nxt], nrho_next, h->prr[nxt],
-                                       h->mx_eta2, maxit, h->act[c0], h->act[nxt], h->iters, st));
+                                       h->mx_eta2, maxit, h->act[c0], h->act[nxt], h->iters,
+                                       h->d_flags + (size_t)nxt * h->Smax, st));
             return 0;
         };
         auto chunk = [&](int n) -> int {
@@ -1342,6 +1359,7 @@ void mgrit_destroy(mgrit_handle* h) {
         if (e) (void)hipEventDestroy(e);
     for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     if (h->h_act) (void)hipHostFree(h->h_act);
+    if (h->h_flags) (void)hipHostFree(h->h_flags);
     for (hipEvent_t e : h->flag_ev)
         if (e) (void)hipEventDestroy(e);
     if (h->h_iters) (void)hipHostFree(h->h_iters);

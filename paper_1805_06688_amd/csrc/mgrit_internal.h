@@ -152,10 +152,13 @@ int launch_cg_start(const Geom* g, const PropDesc* desc, int S, const double* ub
 int launch_cg_update(const Geom* g, const PropDesc* desc, int S, double* xbase, double* rws, const double* pws,
                      const double* qws, const double* partial_rho, int nrho, const double* partial_pq, int npq,
                      double* partial_rr_new, const int* active, void* stream);
-// p = z + (rho_new / rho) p; next active flags (from ||r||^2) and iteration counts.
+// p = z + (rho_new / rho) p; next active flags (from ||r||^2) and iteration counts.  The
+// direction kernels also store the next flags into host_next (pinned host memory, may be
+// NULL), which the host reads without a copy once the iteration is complete.
 int launch_cg_direction(const Geom* g, int S, const double* zws, double* pws, const double* partial_rho, int nrho,
                         const double* partial_rho_new, int nrho_new, const double* partial_rr_new, const double* bb,
-                        double rtol2, int maxit, const int* active, int* active_next, int* iters, void* stream);
+                        double rtol2, int maxit, const int* active, int* active_next, int* iters, int* host_next,
+                        void* stream);
 // z = P^{-1} r (four batched dense products), partial r.z; active may be NULL.
 int launch_fd_apply(const Geom* g, const FdMats* fd, int tv, const PropDesc* desc, int S, const double* rws,
                     double* zws, double* t1, double* t2, double* partial_rz, const int* active, void* stream);
@@ -185,7 +188,7 @@ int launch_mx_update(const Geom* g, int S, float* d32, float* r32, const float* 
 // p32 = z32 + (rho_new / rho) p32; next flags from ||r32||^2 <= eta2[s] and the total count.
 int launch_mx_direction(const Geom* g, int S, const float* z32, float* p32, const double* partial_rho, int nrho,
                         const double* partial_rho_new, int nrho_new, const double* partial_rr_new, const double* eta2,
-                        int maxit, const int* active, int* active_next, int* iters, void* stream);
+                        int maxit, const int* active, int* active_next, int* iters, int* host_next, void* stream);
 // x += scale[s] d32 where oact[s].
 int launch_mx_refine(const Geom* g, const PropDesc* desc, int S, double* xbase, const float* d32,
                      const double* scale, const int* oact, void* stream);
