@@ -391,7 +391,7 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
                                                  const double* partial_rr, int np, double rtol2, double eta_min2,
                                                  int first, double* bb, double* scale, double* eta2, int* oact,
                                                  int* iact, int* iters, float* r32, float* d32, float* p32,
-                                                 double* partial_rr32) {
+                                                 double* partial_rr32, int* host_act) {
     int s, c;
     decode_block(g.nchunk, S, s, c);
     if (s < 0) return;
@@ -429,7 +429,9 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
         const double e2 = active ? fmax(rtol2 * b2 / r2, eta_min2) : 0.0;
         // 2: the inner target is the pass tolerance itself and at least 10 x the FP32 floor, so the
         // inner solve's own test settles the slice (see the refinement loop)
-        iact[s] = active ? (e2 >= 1e2 * eta_min2 ? 2 : 1) : 0;
+        const int flag = active ? (e2 >= 1e2 * eta_min2 ? 2 : 1) : 0;
+        iact[s] = flag;
+        if (host_act) host_act[s] = flag;
         scale[s] = active ? sqrt(r2) : 0.0;
         eta2[s] = e2;
         if (first) iters[s] = 0;
@@ -565,7 +567,8 @@ __global__ __launch_bounds__(NT) void k_cg_init_x(Geom g, const PropDesc* __rest
 __global__ __launch_bounds__(NT) void k_cg_start(Geom g, const PropDesc* __restrict__ desc, int S,
                                                  double* xbase, const double* zws, double* pws,
                                                  const double* partial_bb, int nbb, const double* partial_rr, int nrr,
-                                                 double rtol2, double* bb, int* active, int* iters) {
+                                                 double rtol2, double* bb, int* active, int* iters,
+                                                 int* host_act) {
     int s, c;
     decode_block(g.nchunk, S, s, c);
     if (s < 0) return;
@@ -584,7 +587,9 @@ __global__ __launch_bounds__(NT) void k_cg_start(Geom g, const PropDesc* __restr
     }
     if (c == 0 && threadIdx.x == 0) {
         bb[s] = b2;
-        active[s] = (!zero && r2 > rtol2 * b2) ? 1 : 0;
+        const int flag = (!zero && r2 > rtol2 * b2) ? 1 : 0;
+        active[s] = flag;
+        if (host_act) host_act[s] = flag;
         iters[s] = 0;
     }
 }
@@ -1689,11 +1694,11 @@ int launch_cg_apply(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc,
 
 int launch_cg_start(const Geom* g, const PropDesc* desc, int S, const double* ubase, double* xbase,
                     const double* zws, double* pws, const double* partial_bb, int nbb, const double* partial_rr,
-                    int nrr, double rtol2, double* bb, int* active, int* iters, void* stream) {
+                    int nrr, double rtol2, double* bb, int* active, int* iters, int* host_act, void* stream) {
     if (S <= 0) return 0;
     (void)ubase;
     hipLaunchKernelGGL(k_cg_start, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, desc, S,
-                       xbase, zws, pws, partial_bb, nbb, partial_rr, nrr, rtol2, bb, active, iters);
+                       xbase, zws, pws, partial_bb, nbb, partial_rr, nrr, rtol2, bb, active, iters, host_act);
     return (int)hipGetLastError();
 }
 
@@ -1800,17 +1805,17 @@ int launch_apply32(const Geom* g, const Seqs32* sq, int tv, const PropDesc* desc
 int launch_mx_begin(const Geom* g, const PropDesc* desc, int S, double* xbase, const double* rws,
                     const double* partial_bb, const double* partial_rr, int np, double rtol2, double eta_min2,
                     int first, double* bb, double* scale, double* eta2, int* oact, int* iact, int* iters, float* r32,
-                    float* d32, float* p32, double* partial_rr32, void* stream) {
+                    float* d32, float* p32, double* partial_rr32, int* host_act, void* stream) {
     if (S <= 0) return 0;
     const dim3 grid(grid_blocks(g->nchunk, S)), blk(NT);
     if (rws)
         hipLaunchKernelGGL(k_mx_begin<double>, grid, blk, 0, (hipStream_t)stream, *g, desc, S, xbase, rws,
                            partial_bb, partial_rr, np, rtol2, eta_min2, first, bb, scale, eta2, oact, iact, iters, r32,
-                           d32, p32, partial_rr32);
+                           d32, p32, partial_rr32, host_act);
     else
         hipLaunchKernelGGL(k_mx_begin<float>, grid, blk, 0, (hipStream_t)stream, *g, desc, S, xbase,
                            (const float*)r32, partial_bb, partial_rr, np, rtol2, eta_min2, first, bb, scale, eta2,
-                           oact, iact, iters, r32, d32, p32, partial_rr32);
+                           oact, iact, iters, r32, d32, p32, partial_rr32, host_act);
     return (int)hipGetLastError();
 }
 

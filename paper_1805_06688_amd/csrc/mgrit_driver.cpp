@@ -133,9 +133,10 @@ struct mgrit_handle {
     long long refine_count = 0;             // refinement steps summed over slices
     int* act[2] = {nullptr, nullptr};
     int* iters = nullptr;
-    int* h_act = nullptr;                    // pinned, two buffers of Smax flags (copies of act at a check)
     int* h_flags = nullptr;                  // pinned, 2 x Smax: act[0], act[1] as the direction kernels set them
     int* d_flags = nullptr;                  // the device address of h_flags
+    int* h_start = nullptr;                  // pinned, Smax: the flags at the start of a solve or step
+    int* d_start = nullptr;                  // the device address of h_start
     hipEvent_t flag_ev[2] = {};
     int* h_iters = nullptr;                  // pinned
     int* h_iters_step = nullptr;             // pinned, 4 x Smax: iteration counts after each refinement step
@@ -635,10 +636,12 @@ int alloc_workspace(mgrit_handle* h, int S) {
             CHK(dalloc(h, &h->prz[1], S * nt));
         }
     }
-    HIPCHK(hipHostMalloc((void**)&h->h_act, 2 * S * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&h->h_flags, 2 * S * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
     HIPCHK(hipHostGetDevicePointer((void**)&h->d_flags, h->h_flags, 0));
     for (int i = 0; i < 2 * S; ++i) h->h_flags[i] = 0;
+    HIPCHK(hipHostMalloc((void**)&h->h_start, S * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void**)&h->d_start, h->h_start, 0));
+    for (int i = 0; i < S; ++i) h->h_start[i] = 0;
     for (hipEvent_t& e : h->flag_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPCHK(hipHostMalloc((void**)&h->h_iters, S * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&h->h_iters_step, 4 * (size_t)S * sizeof(int), hipHostMallocDefault));
@@ -798,22 +801,16 @@ int launch_iterations(mgrit_handle* h, mgrit_handle::GraphKey key, int n, int& c
 // the check; the one iteration queued after the last slice converged finds
 // every slice inactive and does nothing.  sync_first: wait for the flags at
 // the start before queueing anything (when all slices are likely converged).
-// *n_active0: active slices at the start.  The flags at the start are copied
-// (a snapshot: the first chunk may set the same parity again while the host
-// reads); later checks read the pinned mirror the direction kernels write,
-// h_flags[parity], which the single queued iteration does not touch (it
-// writes the other parity).
+// *n_active0: active slices at the start.  The flags at the start are the
+// ones the start kernel (k_cg_start, k_mx_begin) also stored into h_start,
+// which nothing else writes during the solve; later checks read the pinned
+// mirror the direction kernels write, h_flags[parity], which the single
+// queued iteration does not touch (it writes the other parity).
 int run_checked(mgrit_handle* h, int S, int n_first, int maxit, bool sync_first, int& cur, int& it,
                 int* n_active0, const std::function<int(int)>& launch_chunk, int* n_ones0 = nullptr) {
     const int* src[2] = {nullptr, nullptr};
-    auto queue_flags = [&](int k, bool snapshot) -> int {
-        if (snapshot) {
-            HIPCHK(hipMemcpyAsync(h->h_act + (size_t)k * h->Smax, h->act[cur], S * sizeof(int),
-                                  hipMemcpyDeviceToHost, h->stream));
-            src[k] = h->h_act + (size_t)k * h->Smax;
-        } else {
-            src[k] = h->h_flags + (size_t)cur * h->Smax;
-        }
+    auto queue_flags = [&](int k, bool start) -> int {
+        src[k] = start ? h->h_start : h->h_flags + (size_t)cur * h->Smax;
         HIPCHK(hipEventRecord(h->flag_ev[k], h->stream));
         return 0;
     };
@@ -893,7 +890,7 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     double* zws = pc ? h->z : h->r;
     double** prho = pc ? h->prz : h->prr;        // rho = r.z (r.r without preconditioner)
     HIPCHK(launch_cg_start(g, ps.d, S, ubase, xbase, zws, h->p, h->pbb, nop, h->prr[0], nop, rtol2, h->bb, h->act[0],
-                           h->iters, st));
+                           h->iters, h->d_start, st));
     int cur = 0;
     int it = 0;
     int nrho = pc ? npc : nop;                               // entries of the current rho partials
@@ -978,7 +975,7 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
     for (int outer = 0; outer < 32; ++outer) {
         HIPCHK(launch_mx_begin(g, ps.d, S, xbase, all32 ? nullptr : h->r, h->pbb, h->pout, nop, rtol2, eta * eta,
                                outer == 0 ? 1 : 0, h->bb, h->mx_scale, h->mx_eta2, h->mx_oact, h->act[0], h->iters,
-                               h->r32, h->d32, pc ? nullptr : h->p32, h->prr[0], st));
+                               h->r32, h->d32, pc ? nullptr : h->p32, h->prr[0], h->d_start, st));
         if (tv32 < 0) CHK(tile_variant(h, &ps, S, &tv32, true));
         if (pc)
             HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, h->p32, h->tb1, h->tb2, h->prz[0],
@@ -1358,8 +1355,8 @@ void mgrit_destroy(mgrit_handle* h) {
     for (hipEvent_t e : h->tune_ev)
         if (e) (void)hipEventDestroy(e);
     for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
-    if (h->h_act) (void)hipHostFree(h->h_act);
     if (h->h_flags) (void)hipHostFree(h->h_flags);
+    if (h->h_start) (void)hipHostFree(h->h_start);
     for (hipEvent_t e : h->flag_ev)
         if (e) (void)hipEventDestroy(e);
     if (h->h_iters) (void)hipHostFree(h->h_iters);

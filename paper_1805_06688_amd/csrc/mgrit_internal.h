@@ -144,10 +144,11 @@ int launch_init_residual(const Geom* g, const Seqs* sq, int tv, const PropDesc* 
 // q = B p for active slices, partial p.q.
 int launch_cg_apply(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc, int S, const double* pws,
                     double* qws, double* partial_pq, const int* active, void* stream);
-// x = 0 when ||b|| = 0, p = z; active flags from ||r|| vs rtol ||b||.
+// x = 0 when ||b|| = 0, p = z; active flags from ||r|| vs rtol ||b||, also stored into host_act
+// (pinned host memory, may be NULL).
 int launch_cg_start(const Geom* g, const PropDesc* desc, int S, const double* ubase, double* xbase,
                     const double* zws, double* pws, const double* partial_bb, int nbb, const double* partial_rr,
-                    int nrr, double rtol2, double* bb, int* active, int* iters, void* stream);
+                    int nrr, double rtol2, double* bb, int* active, int* iters, int* host_act, void* stream);
 // alpha = rho / p.q; x += alpha p, r -= alpha q; partial r.r (nchunk entries).
 int launch_cg_update(const Geom* g, const PropDesc* desc, int S, double* xbase, double* rws, const double* pws,
                      const double* qws, const double* partial_rho, int nrho, const double* partial_pq, int npq,
@@ -176,11 +177,12 @@ int launch_apply32(const Geom* g, const Seqs32* sq, int tv, const PropDesc* desc
 // Start of a refinement step from the FP64 residual (or, with rws == NULL, from an FP32
 // residual already in r32, scaled in place): flags, scale ||r||, inner tolerance
 // eta^2 = max(rtol^2 ||b||^2 / ||r||^2, eta_min2), r32 = r / ||r||, d32 = 0, and p32 = r32
-// with partial r32.r32 when p32 != NULL; first: x = 0 where b = 0, counts reset.
+// with partial r32.r32 when p32 != NULL; first: x = 0 where b = 0, counts reset.  The flags
+// are also stored into host_act (pinned host memory, may be NULL).
 int launch_mx_begin(const Geom* g, const PropDesc* desc, int S, double* xbase, const double* rws,
                     const double* partial_bb, const double* partial_rr, int np, double rtol2, double eta_min2,
                     int first, double* bb, double* scale, double* eta2, int* oact, int* iact, int* iters, float* r32,
-                    float* d32, float* p32, double* partial_rr32, void* stream);
+                    float* d32, float* p32, double* partial_rr32, int* host_act, void* stream);
 // alpha = rho / p.q; d32 += alpha p32, r32 -= alpha q32; partial r32.r32.
 int launch_mx_update(const Geom* g, int S, float* d32, float* r32, const float* p32, const float* q32,
                      const double* partial_rho, int nrho, const double* partial_pq, int npq, double* partial_rr_new,
