@@ -277,7 +277,7 @@ def main():
                                 "achieved_GBps": byt / (ms0 / n0 * 1e-3) / 1e9, "peak_GBps": HBM_PEAK_GBPS}
     out = {"metric": METRIC, "value": dof / per_step, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": per_step * 1e3, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f64+f32", "data": "synthetic",
+           "vs_baseline": None, "dtype": ("f64" if args.precision == "fp64" else "f64+f32") + ("+bf16" if args.precond == "fd-bf16" else ""), "data": "synthetic",
            "config": {"workload": W["name"], "nx": nx, "ny": ny, "Nt": Nt, "beta": W["beta"], "gamma": W["gamma"],
                       "Kx": W["Kx"], "Ky": W["Ky"], "m": W["m"], "levels": levels, "relax": args.relax,
                       "coarse": args.coarse, "precond": args.precond, "cg_rtol": args.cg_rtol,
