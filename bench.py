@@ -136,7 +136,8 @@ def main():
                     help="time MGRIT only (no sequential reference, no accuracy check): for profiler runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU (the time-sharded form is not implemented); "
+                                   "--gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
