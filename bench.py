@@ -35,6 +35,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_prop_apply64_fp64_vcycle_255_tr
 FFT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fft_line_vcycle_255_traffic.json")
 
 
+def note(msg):
+    """Progress of a long run on stderr (stdout carries only the result line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_baseline(W, t, F, psi0, steps, cg_rtol):
     """The CPU oracle as it stands: sequential stepping over the first `steps` steps."""
     import numpy as np
@@ -115,7 +120,10 @@ def main():
     # norm has dropped by 1e-8, which leaves the error against FP64 sequential stepping at about 4e-9
     ap.add_argument("--cg-rtol", type=float, default=1e-9)
     ap.add_argument("--tol-rel", type=float, default=1e-8)
-    ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="steps of the CPU oracle sample (0: 200 at 255 x 255, 25 at 511 x 511)")
+    ap.add_argument("--workload", default="vcycle-255",
+                    help="vcycle-255 (255 x 255 x 1024 uniform, the benchmark) | mixed-511 (511 x 511 x 4096 graded)")
     ap.add_argument("--precond", default="fd-bf16")
     ap.add_argument("--max-levels", type=int, default=3)
     ap.add_argument("--tile", default="auto", help="operator tile policy: auto | rule | 64 | 32")
@@ -148,20 +156,30 @@ def main():
         return
     from paper_1805_06688_amd import mgrit, workloads as wl
 
-    W = wl.FP64_VCYCLE_255
+    if args.workload == "vcycle-255":
+        W = wl.FP64_VCYCLE_255
+        t = wl.uniform_grid(W["Nt"], W["T"])
+    elif args.workload == "mixed-511":
+        W = wl.mixed_511()
+        t = wl.graded_grid(W["Nt"], W["T"])
+    else:
+        raise SystemExit(f"unknown workload {args.workload}")
     nx, ny, Nt = W["Mx"] - 1, W["My"] - 1, W["Nt"]
-    t = wl.uniform_grid(Nt, W["T"])
+    if args.cpu_steps <= 0:
+        args.cpu_steps = 200 if nx <= 255 else 25
     F, psi0 = wl.random_inputs(W["seed"], Nt, nx, ny)
     torch.cuda.set_device(0)
     Fd = torch.from_numpy(F).cuda()
     pd = torch.from_numpy(psi0).cuda()
     common = (W["beta"], W["gamma"], W["Kx"], W["Ky"], W["Mx"], W["My"], t)
+    note(f"inputs ready: {W['name']}")
 
     Uref, seq_s, seq_err = None, None, None
     if not args.skip_reference:
         # FP64 sequential reference (outside the timed region)
         with mgrit.Solver(*common, m=W["m"], cg_rtol=1e-13, cg_maxit=100000, precond=args.precond) as ref:
             Uref, _, _ = ref.sequential(Fd, pd)
+        note("FP64 sequential reference done")
         torch.cuda.synchronize()
         # sequential stepping at the benchmark CG tolerance, for comparison
         with mgrit.Solver(*common, m=W["m"], cg_rtol=args.cg_rtol, cg_maxit=100000, precond=args.precond) as sq:
@@ -171,6 +189,7 @@ def main():
             torch.cuda.synchronize()
             seq_s = time.perf_counter() - t0
         seq_err = float(torch.linalg.norm(Useq - Uref) / torch.linalg.norm(Uref))
+        note("sequential stepping at the benchmark tolerance done")
         del Useq
 
     stream = None
@@ -189,12 +208,14 @@ def main():
     for _ in range(args.warmup):
         s.solve(Fd, pd, out=U)
     torch.cuda.synchronize()
+    note("warm-up done")
     s.profile(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         _, st, rc = s.solve(Fd, pd, out=U)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    note(f"timed solves done: {elapsed / args.steps * 1e3:.1f} ms each")
     prof = [s.profile_read(v) for v in (0, 1, 2, 3)]
     s.profile(False)
     levels = s.levels()
@@ -216,6 +237,7 @@ def main():
                 _, st64, rc64 = s64.solve(Fd, pd, out=U64)
             torch.cuda.synchronize()
             t64 = (time.perf_counter() - t1) / args.steps
+        note("FP64 form done")
         err64 = float(torch.linalg.norm(U64.view(Nt + 1, ny, nx) - Uref) / torch.linalg.norm(Uref))
         forms = {"fp64": {"dof_per_s": nx * ny * Nt / t64, "ms_per_step": t64 * 1e3, "rel_l2_err": err64,
                           "mgrit_iterations": st64.iterations, "rc": rc64},
@@ -225,12 +247,16 @@ def main():
 
     dof = nx * ny * Nt
     per_step = elapsed / args.steps
-    fft = args.op == "fft" or (args.op == "auto" and 2 * max(nx, ny) - 1 <= 512)
+    fft = args.op == "fft" or (args.op == "auto" and 2 * max(nx, ny) - 1 <= 1024)
     if fft:
         # one operator application by FFT: per direction ceil(n_lines / 2) packed output pairs, each one
-        # forward and one inverse 512-point radix-8 transform (20736 flops as the kernel computes them) and
-        # the spectral combination with the three kernels (76 flops per frequency, 512 frequencies)
-        flops_per_apply = float(((ny + 1) // 2 + (nx + 1) // 2) * (2 * 20736 + 76 * 512))
+        # forward and one inverse transform of L points and the spectral combination with the three
+        # kernels (76 flops per frequency).  Transform flops as the kernel computes them, per lane:
+        # L = 512: a radix-8 DFT (56) and two twiddled ones (78 + 56 each), 64 lanes: 20736;
+        # L = 1024: a radix-16 DFT (192) and two passes of two twiddled radix-8 DFTs (268 each): 46592
+        L = 512 if 2 * max(nx, ny) - 1 <= 512 else 1024
+        tflops = 20736 if L == 512 else 46592
+        flops_per_apply = float(((ny + 1) // 2 + (nx + 1) // 2) * (2 * tflops + 76 * L))
         names = ["k_fft_line<double,0,2> + <double,1,2> (CG operator by FFT, x and y passes, FP64)", "",
                  "k_fft_line32<0,2> + <1,2> (inner CG operator of mixed precision by FFT, FP32)", ""]
         bound = "alu"
@@ -255,7 +281,7 @@ def main():
     # dominant kernel: the operator variant with the most kernel time
     v0 = max(range(4), key=lambda v: prof[v][0])
     traffic = None
-    if os.path.exists(tfile):
+    if os.path.exists(tfile) and args.workload == "vcycle-255":      # the counters were taken on that workload
         with open(tfile) as fh:
             tr = json.load(fh)
         if tr.get("source_hash") == profiling.source_hash() and tr.get("variant") == v0:
