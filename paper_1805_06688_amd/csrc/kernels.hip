@@ -391,7 +391,7 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
                                                  const double* partial_rr, int np, double rtol2, double eta_min2,
                                                  int first, double* bb, double* scale, double* eta2, int* oact,
                                                  int* iact, int* iters, float* r32, float* d32, float* p32,
-                                                 double* partial_rr32, int* host_act) {
+                                                 double* partial_rr32, int* host_act, int* host_iters) {
     int s, c;
     decode_block(g.nchunk, S, s, c);
     if (s < 0) return;
@@ -434,7 +434,10 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
         if (host_act) host_act[s] = flag;
         scale[s] = active ? sqrt(r2) : 0.0;
         eta2[s] = e2;
-        if (first) iters[s] = 0;
+        if (first) {
+            iters[s] = 0;
+            if (host_iters) host_iters[s] = 0;
+        }
     }
 }
 
@@ -487,7 +490,7 @@ __global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float*
                                                      const double* partial_rho_new, int nrho_new,
                                                      const double* partial_rr_new, const double* eta2, int maxit,
                                                      const int* active, int* active_next, int* iters,
-                                                     int* host_next) {
+                                                     int* host_next, int* host_iters) {
     int s, c;
     decode_block(g.nchunk, S, s, c);
     if (s < 0) return;
@@ -517,6 +520,7 @@ __global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float*
         const double rrn = slice_sum(partial_rr_new, g.pmax, s, g.nchunk);
         const int it = iters[s] + 1;
         iters[s] = it;
+        if (host_iters) host_iters[s] = it;
         const int flag = (rrn > eta2[s] && it < maxit) ? 1 : 0;
         active_next[s] = flag;
         if (host_next) host_next[s] = flag;
@@ -568,7 +572,7 @@ __global__ __launch_bounds__(NT) void k_cg_start(Geom g, const PropDesc* __restr
                                                  double* xbase, const double* zws, double* pws,
                                                  const double* partial_bb, int nbb, const double* partial_rr, int nrr,
                                                  double rtol2, double* bb, int* active, int* iters,
-                                                 int* host_act) {
+                                                 int* host_act, int* host_iters) {
     int s, c;
     decode_block(g.nchunk, S, s, c);
     if (s < 0) return;
@@ -591,6 +595,7 @@ __global__ __launch_bounds__(NT) void k_cg_start(Geom g, const PropDesc* __restr
         active[s] = flag;
         if (host_act) host_act[s] = flag;
         iters[s] = 0;
+        if (host_iters) host_iters[s] = 0;
     }
 }
 
@@ -647,7 +652,7 @@ __global__ __launch_bounds__(NT) void k_cg_direction(Geom g, int S, const double
                                                      const double* partial_rho_new, int nrho_new,
                                                      const double* partial_rr_new, const double* bb, double rtol2,
                                                      int maxit, const int* active, int* active_next, int* iters,
-                                                     int* host_next) {
+                                                     int* host_next, int* host_iters) {
     int s, c;
     decode_block(g.nchunk, S, s, c);
     if (s < 0) return;
@@ -681,6 +686,7 @@ __global__ __launch_bounds__(NT) void k_cg_direction(Geom g, int S, const double
         const double rrn = slice_sum(partial_rr_new, g.pmax, s, g.nchunk);
         const int it = iters[s] + 1;
         iters[s] = it;
+        if (host_iters) host_iters[s] = it;
         const int flag = (rrn > rtol2 * bb[s] && it < maxit) ? 1 : 0;
         active_next[s] = flag;
         if (host_next) host_next[s] = flag;
@@ -1694,11 +1700,13 @@ int launch_cg_apply(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc,
 
 int launch_cg_start(const Geom* g, const PropDesc* desc, int S, const double* ubase, double* xbase,
                     const double* zws, double* pws, const double* partial_bb, int nbb, const double* partial_rr,
-                    int nrr, double rtol2, double* bb, int* active, int* iters, int* host_act, void* stream) {
+                    int nrr, double rtol2, double* bb, int* active, int* iters, int* host_act, int* host_iters,
+                    void* stream) {
     if (S <= 0) return 0;
     (void)ubase;
     hipLaunchKernelGGL(k_cg_start, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, desc, S,
-                       xbase, zws, pws, partial_bb, nbb, partial_rr, nrr, rtol2, bb, active, iters, host_act);
+                       xbase, zws, pws, partial_bb, nbb, partial_rr, nrr, rtol2, bb, active, iters, host_act,
+                       host_iters);
     return (int)hipGetLastError();
 }
 
@@ -1714,11 +1722,11 @@ int launch_cg_update(const Geom* g, const PropDesc* desc, int S, double* xbase, 
 int launch_cg_direction(const Geom* g, int S, const double* zws, double* pws, const double* partial_rho, int nrho,
                         const double* partial_rho_new, int nrho_new, const double* partial_rr_new, const double* bb,
                         double rtol2, int maxit, const int* active, int* active_next, int* iters, int* host_next,
-                        void* stream) {
+                        int* host_iters, void* stream) {
     if (S <= 0) return 0;
     hipLaunchKernelGGL(k_cg_direction, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, S, zws,
                        pws, partial_rho, nrho, partial_rho_new, nrho_new, partial_rr_new, bb, rtol2, maxit, active,
-                       active_next, iters, host_next);
+                       active_next, iters, host_next, host_iters);
     return (int)hipGetLastError();
 }
 
@@ -1805,17 +1813,18 @@ int launch_apply32(const Geom* g, const Seqs32* sq, int tv, const PropDesc* desc
 int launch_mx_begin(const Geom* g, const PropDesc* desc, int S, double* xbase, const double* rws,
                     const double* partial_bb, const double* partial_rr, int np, double rtol2, double eta_min2,
                     int first, double* bb, double* scale, double* eta2, int* oact, int* iact, int* iters, float* r32,
-                    float* d32, float* p32, double* partial_rr32, int* host_act, void* stream) {
+                    float* d32, float* p32, double* partial_rr32, int* host_act, int* host_iters,
+                    void* stream) {
     if (S <= 0) return 0;
     const dim3 grid(grid_blocks(g->nchunk, S)), blk(NT);
     if (rws)
         hipLaunchKernelGGL(k_mx_begin<double>, grid, blk, 0, (hipStream_t)stream, *g, desc, S, xbase, rws,
                            partial_bb, partial_rr, np, rtol2, eta_min2, first, bb, scale, eta2, oact, iact, iters, r32,
-                           d32, p32, partial_rr32, host_act);
+                           d32, p32, partial_rr32, host_act, host_iters);
     else
         hipLaunchKernelGGL(k_mx_begin<float>, grid, blk, 0, (hipStream_t)stream, *g, desc, S, xbase,
                            (const float*)r32, partial_bb, partial_rr, np, rtol2, eta_min2, first, bb, scale, eta2,
-                           oact, iact, iters, r32, d32, p32, partial_rr32, host_act);
+                           oact, iact, iters, r32, d32, p32, partial_rr32, host_act, host_iters);
     return (int)hipGetLastError();
 }
 
@@ -1830,11 +1839,12 @@ int launch_mx_update(const Geom* g, int S, float* d32, float* r32, const float* 
 
 int launch_mx_direction(const Geom* g, int S, const float* z32, float* p32, const double* partial_rho, int nrho,
                         const double* partial_rho_new, int nrho_new, const double* partial_rr_new, const double* eta2,
-                        int maxit, const int* active, int* active_next, int* iters, int* host_next, void* stream) {
+                        int maxit, const int* active, int* active_next, int* iters, int* host_next,
+                        int* host_iters, void* stream) {
     if (S <= 0) return 0;
     hipLaunchKernelGGL(k_mx_direction, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, S,
                        z32, p32, partial_rho, nrho, partial_rho_new, nrho_new, partial_rr_new, eta2, maxit, active,
-                       active_next, iters, host_next);
+                       active_next, iters, host_next, host_iters);
     return (int)hipGetLastError();
 }
 

@@ -138,8 +138,9 @@ struct mgrit_handle {
     int* h_start = nullptr;                  // pinned, Smax: the flags at the start of a solve or step
     int* d_start = nullptr;                  // the device address of h_start
     hipEvent_t flag_ev[2] = {};
-    int* h_iters = nullptr;                  // pinned
-    int* h_iters_step = nullptr;             // pinned, 4 x Smax: iteration counts after each refinement step
+    int* h_iters = nullptr;                  // pinned: iteration counts as the start and direction kernels set them
+    int* d_iters = nullptr;                  // the device address of h_iters
+    int* h_iters_step = nullptr;             // 4 x Smax: iteration counts after each refinement step
     double* h_norm = nullptr;                // pinned
     long long phi_count = 0, cg_count = 0;
     std::vector<void*> allocations;
@@ -643,7 +644,9 @@ int alloc_workspace(mgrit_handle* h, int S) {
     HIPCHK(hipHostGetDevicePointer((void**)&h->d_start, h->h_start, 0));
     for (int i = 0; i < S; ++i) h->h_start[i] = 0;
     for (hipEvent_t& e : h->flag_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    HIPCHK(hipHostMalloc((void**)&h->h_iters, S * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&h->h_iters, S * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void**)&h->d_iters, h->h_iters, 0));
+    for (int i = 0; i < S; ++i) h->h_iters[i] = 0;
     HIPCHK(hipHostMalloc((void**)&h->h_iters_step, 4 * (size_t)S * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&h->h_norm, S * nt * sizeof(double), hipHostMallocDefault));
     return 0;
@@ -890,7 +893,7 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     double* zws = pc ? h->z : h->r;
     double** prho = pc ? h->prz : h->prr;        // rho = r.z (r.r without preconditioner)
     HIPCHK(launch_cg_start(g, ps.d, S, ubase, xbase, zws, h->p, h->pbb, nop, h->prr[0], nop, rtol2, h->bb, h->act[0],
-                           h->iters, h->d_start, st));
+                           h->iters, h->d_start, h->d_iters, st));
     int cur = 0;
     int it = 0;
     int nrho = pc ? npc : nop;                               // entries of the current rho partials
@@ -909,17 +912,20 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
         if (pc) HIPCHK(precondition(h->prz[nxt], h->act[c0]));
         HIPCHK(launch_cg_direction(g, S, zws, h->p, prho[c0], nr, prho[nxt], nrho_next, h->prr[nxt], h->bb, rtol2,
                                    maxit, h->act[c0], h->act[nxt], h->iters, h->d_flags + (size_t)nxt * h->Smax,
-                                   st));
+                                   h->d_iters, st));
         return 0;
     };
     auto chunk = [&](int n) -> int {
         return launch_iterations(h, {ps.d, xbase, S, tv, nrho, nrho_next, maxit, 0, 0, rtol2}, n, cur, nrho, iter);
     };
     CHK(run_checked(h, S, first, maxit, false, cur, it, nullptr, chunk));
+    // the counts are final once run_checked has seen every slice inactive (or maxit): the direction
+    // kernels that set them have completed, later (queued) iterations leave inactive slices alone
     HIPCHK(launch_add_g(g, ps.d, S, xbase, gbase, st));
-    HIPCHK(hipMemcpyAsync(h->h_iters, h->iters, S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    if (h->prof_on) CHK(prof_drain(h));
+    if (h->prof_on) {
+        HIPCHK(hipStreamSynchronize(h->stream));
+        CHK(prof_drain(h));
+    }
     long long its = 0;
     int most = 0;
     for (int s = 0; s < S; ++s) {
@@ -975,7 +981,7 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
     for (int outer = 0; outer < 32; ++outer) {
         HIPCHK(launch_mx_begin(g, ps.d, S, xbase, all32 ? nullptr : h->r, h->pbb, h->pout, nop, rtol2, eta * eta,
                                outer == 0 ? 1 : 0, h->bb, h->mx_scale, h->mx_eta2, h->mx_oact, h->act[0], h->iters,
-                               h->r32, h->d32, pc ? nullptr : h->p32, h->prr[0], h->d_start, st));
+                               h->r32, h->d32, pc ? nullptr : h->p32, h->prr[0], h->d_start, h->d_iters, st));
         if (tv32 < 0) CHK(tile_variant(h, &ps, S, &tv32, true));
         if (pc)
             HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, h->p32, h->tb1, h->tb2, h->prz[0],
@@ -995,7 +1001,7 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
                                           h->act[c0], st));
             HIPCHK(launch_mx_direction(g, S, zws, h->p32, prho[c0], nr, prho[nxt], nrho_next, h->prr[nxt],
                                        h->mx_eta2, maxit, h->act[c0], h->act[nxt], h->iters,
-                                       h->d_flags + (size_t)nxt * h->Smax, st));
+                                       h->d_flags + (size_t)nxt * h->Smax, h->d_iters, st));
             return 0;
         };
         auto chunk = [&](int n) -> int {
@@ -1011,9 +1017,8 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
         CHK(run_checked(h, S, first, maxit, outer > 0, cur, it, &nact, chunk, &untrusted));
         if (nact == 0) break;
         steps += nact;
-        if (outer < 4) {                     // counts after this step, read once the pass has ended
-            HIPCHK(hipMemcpyAsync(h->h_iters_step + (size_t)outer * h->Smax, h->iters, S * sizeof(int),
-                                  hipMemcpyDeviceToHost, h->stream));
+        if (outer < 4) {                     // counts after this step (final: see run_pass)
+            std::memcpy(h->h_iters_step + (size_t)outer * h->Smax, h->h_iters, S * sizeof(int));
             nrec = outer + 1;
         }
         HIPCHK(launch_mx_refine(g, ps.d, S, xbase, h->d32, h->mx_scale, h->mx_oact, st));
@@ -1026,9 +1031,10 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
         HIPCHK(op_resid(h, tv, ps, xbase, h->pout));
     }
     HIPCHK(launch_add_g(g, ps.d, S, xbase, gbase, st));
-    HIPCHK(hipMemcpyAsync(h->h_iters, h->iters, S * sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    if (h->prof_on) CHK(prof_drain(h));
+    if (h->prof_on) {
+        HIPCHK(hipStreamSynchronize(h->stream));
+        CHK(prof_drain(h));
+    }
     long long its = 0;
     for (int s = 0; s < S; ++s) its += h->h_iters[s];
     for (int k = 0; k < nrec; ++k) {         // iterations the slowest slice needed in step k

@@ -144,22 +144,24 @@ int launch_init_residual(const Geom* g, const Seqs* sq, int tv, const PropDesc* 
 // q = B p for active slices, partial p.q.
 int launch_cg_apply(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc, int S, const double* pws,
                     double* qws, double* partial_pq, const int* active, void* stream);
-// x = 0 when ||b|| = 0, p = z; active flags from ||r|| vs rtol ||b||, also stored into host_act
-// (pinned host memory, may be NULL).
+// x = 0 when ||b|| = 0, p = z; active flags from ||r|| vs rtol ||b||, also stored into host_act,
+// and the reset iteration counts into host_iters (pinned host memory, either may be NULL).
 int launch_cg_start(const Geom* g, const PropDesc* desc, int S, const double* ubase, double* xbase,
                     const double* zws, double* pws, const double* partial_bb, int nbb, const double* partial_rr,
-                    int nrr, double rtol2, double* bb, int* active, int* iters, int* host_act, void* stream);
+                    int nrr, double rtol2, double* bb, int* active, int* iters, int* host_act, int* host_iters,
+                    void* stream);
 // alpha = rho / p.q; x += alpha p, r -= alpha q; partial r.r (nchunk entries).
 int launch_cg_update(const Geom* g, const PropDesc* desc, int S, double* xbase, double* rws, const double* pws,
                      const double* qws, const double* partial_rho, int nrho, const double* partial_pq, int npq,
                      double* partial_rr_new, const int* active, void* stream);
 // p = z + (rho_new / rho) p; next active flags (from ||r||^2) and iteration counts.  The
 // direction kernels also store the next flags into host_next (pinned host memory, may be
-// NULL), which the host reads without a copy once the iteration is complete.
+// NULL) and the iteration counts into host_iters (may be NULL), which the host reads without a
+// copy once the iteration is complete.
 int launch_cg_direction(const Geom* g, int S, const double* zws, double* pws, const double* partial_rho, int nrho,
                         const double* partial_rho_new, int nrho_new, const double* partial_rr_new, const double* bb,
                         double rtol2, int maxit, const int* active, int* active_next, int* iters, int* host_next,
-                        void* stream);
+                        int* host_iters, void* stream);
 // z = P^{-1} r (four batched dense products), partial r.z; active may be NULL.
 int launch_fd_apply(const Geom* g, const FdMats* fd, int tv, const PropDesc* desc, int S, const double* rws,
                     double* zws, double* t1, double* t2, double* partial_rz, const int* active, void* stream);
@@ -178,11 +180,12 @@ int launch_apply32(const Geom* g, const Seqs32* sq, int tv, const PropDesc* desc
 // residual already in r32, scaled in place): flags, scale ||r||, inner tolerance
 // eta^2 = max(rtol^2 ||b||^2 / ||r||^2, eta_min2), r32 = r / ||r||, d32 = 0, and p32 = r32
 // with partial r32.r32 when p32 != NULL; first: x = 0 where b = 0, counts reset.  The flags
-// are also stored into host_act (pinned host memory, may be NULL).
+// are also stored into host_act and the reset counts into host_iters (pinned host memory, either
+// may be NULL).
 int launch_mx_begin(const Geom* g, const PropDesc* desc, int S, double* xbase, const double* rws,
                     const double* partial_bb, const double* partial_rr, int np, double rtol2, double eta_min2,
                     int first, double* bb, double* scale, double* eta2, int* oact, int* iact, int* iters, float* r32,
-                    float* d32, float* p32, double* partial_rr32, int* host_act, void* stream);
+                    float* d32, float* p32, double* partial_rr32, int* host_act, int* host_iters, void* stream);
 // alpha = rho / p.q; d32 += alpha p32, r32 -= alpha q32; partial r32.r32.
 int launch_mx_update(const Geom* g, int S, float* d32, float* r32, const float* p32, const float* q32,
                      const double* partial_rho, int nrho, const double* partial_pq, int npq, double* partial_rr_new,
@@ -190,7 +193,8 @@ int launch_mx_update(const Geom* g, int S, float* d32, float* r32, const float* 
 // p32 = z32 + (rho_new / rho) p32; next flags from ||r32||^2 <= eta2[s] and the total count.
 int launch_mx_direction(const Geom* g, int S, const float* z32, float* p32, const double* partial_rho, int nrho,
                         const double* partial_rho_new, int nrho_new, const double* partial_rr_new, const double* eta2,
-                        int maxit, const int* active, int* active_next, int* iters, int* host_next, void* stream);
+                        int maxit, const int* active, int* active_next, int* iters, int* host_next, int* host_iters,
+                        void* stream);
 // x += scale[s] d32 where oact[s].
 int launch_mx_refine(const Geom* g, const PropDesc* desc, int S, double* xbase, const float* d32,
                      const double* scale, const int* oact, void* stream);
