@@ -218,6 +218,27 @@ int mgrit_propagate(mgrit_handle* h, int level, const int* step, int nslices,
 int mgrit_apply(mgrit_handle* h, int nslices, const double* theta, double sign,
                 const double* v, const double* add, double* out, int mem);
 
+/* FP32 forms of the same operator, M_h + theta A_h of eq. (chp-02-03), as the
+ * inner solves of mixed precision apply it (handles set up with MGRIT_PREC_MIXED
+ * or MIXED_COARSE only; EINVAL otherwise).  The handle's operator kind and tile
+ * policy choose the kernel: the Toeplitz products on the FP32 matrix cores
+ * (DENSE, 64- or 32-node tiles) or by FP32 FFTs (FFT).  Sequences, spectra and
+ * theta are rounded to FP32; dot products are accumulated in FP64.
+ *   mgrit_apply_f32:    out[s] = M_h v[s] + theta[s] A_h v[s], v and out FP32;
+ *   mgrit_rhs_f32:      b[s] = M_h u[s] + theta[s] A_h u[s] + f[s] (f may be NULL),
+ *                       FP64 u and f rounded to FP32 as they are loaded, b FP32
+ *                       (the right-hand side of a pass at a loose CG tolerance);
+ *   mgrit_residual_f32: r[s] = b[s] - (M_h x[s] + theta[s] A_h x[s]), x FP64
+ *                       rounded on load, b and r FP32 (its initial residual).
+ * The last two exist for the FFT operator only (EINVAL with DENSE).  theta: host
+ * array of nslices values; arrays [nslices][n_y][n_x], all in the memory space
+ * `mem`; outputs may not overlap inputs.  Returns after the stream has finished. */
+int mgrit_apply_f32(mgrit_handle* h, int nslices, const double* theta, const float* v, float* out, int mem);
+int mgrit_rhs_f32(mgrit_handle* h, int nslices, const double* theta, const double* u, const double* f,
+                  float* b, int mem);
+int mgrit_residual_f32(mgrit_handle* h, int nslices, const double* theta, const double* x, const float* b,
+                       float* r, int mem);
+
 /* Copy the FP64 generating sequences the device uses, already multiplied by
  * K c: seq_x = [t_x (n_x) | u_x (n_x) | w_x (n_x)], seq_y likewise with n_y,
  * where t[l] is the distance-l entry of A_1, u[l] the entry (k, k+l) and w[l]

@@ -1546,6 +1546,113 @@ int mgrit_apply(mgrit_handle* h, int nslices, const double* theta, double sign, 
     return MGRIT_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// FP32 operator forms of the inner solves of mixed precision.  kind 0: out32 = M v32 + theta A v32 (the
+// inner CG operator); kind 1: out32 = M u + theta A u + add (FP64 u and add rounded on load: the
+// right-hand side of a loose pass); kind 2: out32 = add32 - (M u + theta A u) (FP64 u, FP32 add: the
+// initial residual of a loose pass).
+int apply_f32(mgrit_handle* h, int kind, int nslices, const double* theta, const void* v, const void* add,
+              float* out, int mem) {
+    if (!h) return fail(MGRIT_EINVAL, "NULL handle");
+    CHK(check_mem(mem));
+    if (h->opt.precision == MGRIT_PREC_FP64)
+        return fail(MGRIT_EINVAL, "the FP32 operator tables exist only in handles set up for mixed precision");
+    if (kind > 0 && !h->use_fft)
+        return fail(MGRIT_EINVAL, "FP32 right-hand sides and residuals are formed by the FFT operator only");
+    if (nslices < 0 || (nslices > 0 && (!theta || !v || !out))) return fail(MGRIT_EINVAL, "bad slices");
+    if (kind == 2 && nslices > 0 && !add) return fail(MGRIT_EINVAL, "the residual needs its right-hand side");
+    if (nslices == 0) return MGRIT_OK;
+    const size_t st = (size_t)h->geom.stride;
+    const size_t wv = kind == 0 ? 4 : 8, wa = kind == 1 ? 8 : 4;
+    std::vector<void*> owned;
+    struct Free {
+        std::vector<void*>& o;
+        ~Free() {
+            for (void* p : o) (void)hipFree(p);
+        }
+    } fr{owned};
+    auto stage = [&](const void* src, size_t bytes, bool copy, void** dst) -> int {
+        if (mem == MGRIT_MEM_DEVICE || !src) {
+            *dst = (void*)src;
+            return 0;
+        }
+        hipError_t e = hipMalloc(dst, bytes);
+        if (e != hipSuccess) return fail(MGRIT_ENOMEM, "staging hipMalloc failed: %s", hipGetErrorString(e));
+        owned.push_back(*dst);
+        if (copy) HIPCHK(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, h->stream));
+        return 0;
+    };
+    void *dv = nullptr, *da = nullptr, *dout = nullptr;
+    CHK(stage(v, nslices * st * wv, true, &dv));
+    CHK(stage(add, nslices * st * wa, true, &da));
+    CHK(stage(out, nslices * st * 4, false, &dout));
+    const int chunk = h->Smax;              // the operator workspaces and partials hold Smax slices
+    void* ddesc = nullptr;
+    hipError_t e = hipMalloc(&ddesc, std::min(chunk, nslices) * sizeof(PropDesc));
+    if (e != hipSuccess) return fail(MGRIT_ENOMEM, "descriptor allocation failed");
+    owned.push_back(ddesc);
+    std::vector<PropDesc> hd;
+    const Geom* g = &h->geom;
+    for (int s0 = 0; s0 < nslices; s0 += chunk) {
+        const int S = std::min(chunk, nslices - s0);
+        hd.assign(S, PropDesc());
+        for (int s = 0; s < S; ++s) {
+            hd[s].u = s;
+            hd[s].x = s;
+            hd[s].f = (kind == 1 && da) ? s : -1;
+            hd[s].g = -1;
+            hd[s].x0 = -1;
+            hd[s].theta_rhs = theta[s0 + s];
+            hd[s].theta_lhs = theta[s0 + s];
+        }
+        HIPCHK(hipMemcpyAsync(ddesc, hd.data(), S * sizeof(PropDesc), hipMemcpyHostToDevice, h->stream));
+        const PropDesc* d = (const PropDesc*)ddesc;
+        const char* vb = (const char*)dv + s0 * st * wv;
+        const char* ab = da ? (const char*)da + s0 * st * wa : nullptr;
+        float* ob = (float*)dout + s0 * st;
+        if (kind == 0) {
+            int tv = 0;
+            CHK(tile_variant(h, nullptr, S, &tv));
+            if (h->use_fft)
+                HIPCHK(launch_fft_apply32(g, &h->plan, d, S, (const float*)vb, ob, h->ppq, nullptr, h->pfft32,
+                                          h->stream));
+            else
+                HIPCHK(launch_apply32(g, &h->seqs32, tv, d, S, (const float*)vb, ob, h->ppq, nullptr, h->stream));
+        } else if (kind == 1) {
+            HIPCHK(launch_fft_rhs32(g, &h->plan, d, S, (const double*)vb, (const double*)ab, ob, h->pbb, h->pfft32,
+                                    h->stream));
+        } else {
+            HIPCHK(launch_fft_init_residual32(g, &h->plan, d, S, (const double*)vb, (const float*)ab, ob, h->pout,
+                                              h->pfft32, h->stream));
+        }
+    }
+    if (mem == MGRIT_MEM_HOST)
+        HIPCHK(hipMemcpyAsync(out, dout, nslices * st * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return MGRIT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mgrit_apply_f32(mgrit_handle* h, int nslices, const double* theta, const float* v, float* out, int mem) {
+    return apply_f32(h, 0, nslices, theta, v, nullptr, out, mem);
+}
+
+int mgrit_rhs_f32(mgrit_handle* h, int nslices, const double* theta, const double* u, const double* f, float* b,
+                  int mem) {
+    return apply_f32(h, 1, nslices, theta, u, f, b, mem);
+}
+
+int mgrit_residual_f32(mgrit_handle* h, int nslices, const double* theta, const double* x, const float* b, float* r,
+                       int mem) {
+    return apply_f32(h, 2, nslices, theta, x, b, r, mem);
+}
+
 int mgrit_sequences(const mgrit_handle* h, double* seq_x, double* seq_y, double* cx, double* cy) {
     if (!h) return fail(MGRIT_EINVAL, "NULL handle");
     if (seq_x) std::memcpy(seq_x, h->host_seq_x.data(), h->host_seq_x.size() * sizeof(double));

@@ -57,7 +57,8 @@ class RequestInfo(ctypes.Structure):
 
 
 SYMBOLS = ("mgrit_default_options", "mgrit_setup", "mgrit_solve", "mgrit_iterate", "mgrit_sequential",
-           "mgrit_propagate", "mgrit_apply", "mgrit_sequences", "mgrit_levels", "mgrit_destroy",
+           "mgrit_propagate", "mgrit_apply", "mgrit_apply_f32", "mgrit_rhs_f32", "mgrit_residual_f32",
+           "mgrit_sequences", "mgrit_levels", "mgrit_destroy",
            "mgrit_last_error", "mgrit_toeplitz_sequences", "mgrit_stiffness_scale", "mgrit_profile_enable",
            "mgrit_profile_read", "mgrit_fd_stiffness_entry", "mgrit_fd_eigen", "mgrit_footprint",
            "mgrit_device_bytes", "mgrit_server_create", "mgrit_server_submit", "mgrit_server_wait",
@@ -83,6 +84,12 @@ def load_library(path=_LIB_PATH):
     lib.mgrit_propagate.restype = c_int
     lib.mgrit_apply.argtypes = [P, c_int, ctypes.POINTER(c_dbl), c_dbl, P, P, P, c_int]
     lib.mgrit_apply.restype = c_int
+    lib.mgrit_apply_f32.argtypes = [P, c_int, ctypes.POINTER(c_dbl), P, P, c_int]
+    lib.mgrit_apply_f32.restype = c_int
+    lib.mgrit_rhs_f32.argtypes = [P, c_int, ctypes.POINTER(c_dbl), P, P, P, c_int]
+    lib.mgrit_rhs_f32.restype = c_int
+    lib.mgrit_residual_f32.argtypes = [P, c_int, ctypes.POINTER(c_dbl), P, P, P, c_int]
+    lib.mgrit_residual_f32.restype = c_int
     lib.mgrit_sequences.argtypes = [P, ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl),
                                     ctypes.POINTER(c_dbl)]
     lib.mgrit_sequences.restype = c_int
@@ -144,23 +151,23 @@ def _is_torch(x):
     return type(x).__module__.startswith("torch")
 
 
-def _ptr(x, mem, count):
-    """Raw pointer of an FP64 array with at least `count` elements in the expected memory space."""
+def _ptr(x, mem, count, fp32=False):
+    """Raw pointer of an FP64 (FP32) array with at least `count` elements in the expected memory space."""
     if x is None:
         return None
     if _is_torch(x):
         import torch
         if mem != MEM_DEVICE or not x.is_cuda:
             raise ValueError("mixing host and device arrays in one call")
-        if x.dtype != torch.float64 or not x.is_contiguous():
-            raise ValueError("device arrays must be contiguous float64 tensors")
+        if x.dtype != (torch.float32 if fp32 else torch.float64) or not x.is_contiguous():
+            raise ValueError(f"device arrays must be contiguous {'float32' if fp32 else 'float64'} tensors")
         if x.numel() < count:
             raise ValueError(f"array has {x.numel()} elements, {count} needed")
         return ctypes.c_void_p(x.data_ptr())
     if mem != MEM_HOST:
         raise ValueError("mixing host and device arrays in one call")
-    if x.dtype != np.float64 or not x.flags["C_CONTIGUOUS"]:
-        raise ValueError("host arrays must be C-contiguous float64")
+    if x.dtype != (np.float32 if fp32 else np.float64) or not x.flags["C_CONTIGUOUS"]:
+        raise ValueError(f"host arrays must be C-contiguous {'float32' if fp32 else 'float64'}")
     if x.size < count:
         raise ValueError(f"array has {x.size} elements, {count} needed")
     return ctypes.c_void_p(x.ctypes.data)
@@ -336,6 +343,42 @@ class Solver:
         U = self._out(v, S * n, out)
         _check(_lib.mgrit_apply(self._h, S, theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(sign),
                                 _ptr(v, mem, S * n), _ptr(add, mem, S * n), _ptr(U, mem, S * n), mem))
+        return self._shape(U, S)
+
+    def _out32(self, like, count, out):
+        if out is not None:
+            return out
+        if _is_torch(like):
+            import torch
+            return torch.empty(count, dtype=torch.float32, device=like.device)
+        return np.empty(count, dtype=np.float32)
+
+    def apply_f32(self, theta, v, out=None):
+        """FP32 inner operator: out[s] = M v[s] + theta[s] A v[s] with FP32 v and out (mixed-precision handles)."""
+        theta = np.ascontiguousarray(np.atleast_1d(np.asarray(theta, dtype=np.float64)))
+        S, mem, n = len(theta), _mem_of(v), self.slice_size
+        U = self._out32(v, S * n, out)
+        _check(_lib.mgrit_apply_f32(self._h, S, theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    _ptr(v, mem, S * n, True), _ptr(U, mem, S * n, True), mem))
+        return self._shape(U, S)
+
+    def rhs_f32(self, theta, u, f=None, out=None):
+        """FP32 right-hand side b[s] = M u[s] + theta[s] A u[s] + f[s] from FP64 u, f (FFT operator)."""
+        theta = np.ascontiguousarray(np.atleast_1d(np.asarray(theta, dtype=np.float64)))
+        S, mem, n = len(theta), _mem_of(u), self.slice_size
+        U = self._out32(u, S * n, out)
+        _check(_lib.mgrit_rhs_f32(self._h, S, theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  _ptr(u, mem, S * n), _ptr(f, mem, S * n), _ptr(U, mem, S * n, True), mem))
+        return self._shape(U, S)
+
+    def residual_f32(self, theta, x, b, out=None):
+        """FP32 residual r[s] = b[s] - (M x[s] + theta[s] A x[s]) from FP64 x and FP32 b (FFT operator)."""
+        theta = np.ascontiguousarray(np.atleast_1d(np.asarray(theta, dtype=np.float64)))
+        S, mem, n = len(theta), _mem_of(x), self.slice_size
+        U = self._out32(x, S * n, out)
+        _check(_lib.mgrit_residual_f32(self._h, S, theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       _ptr(x, mem, S * n), _ptr(b, mem, S * n, True), _ptr(U, mem, S * n, True),
+                                       mem))
         return self._shape(U, S)
 
     def sequences(self):

@@ -19,7 +19,7 @@ def _lib():
 def test_library_exports_every_declared_symbol():
     mg = _lib()
     text = open(HEADER).read()
-    declared = set(re.findall(r"\b(mgrit_[a-z_]+)\s*\(", text))
+    declared = set(re.findall(r"\b(mgrit_[a-z0-9_]+)\s*\(", text))
     out = subprocess.run(["nm", "-D", "--defined-only", mg._LIB_PATH], capture_output=True, text=True,
                          check=True).stdout
     exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
