@@ -218,6 +218,24 @@ int mgrit_propagate(mgrit_handle* h, int level, const int* step, int nslices,
 int mgrit_apply(mgrit_handle* h, int nslices, const double* theta, double sign,
                 const double* v, const double* add, double* out, int mem);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operator application as mgrit_apply, with the same kernels and the same
+ * results, that allocates nothing.  Its slice descriptors and the x-pass
+ * workspace of the FFT operator live in a fixed per-GPU scratch array of
+ * MGRIT_NOALLOC_SCRATCH_BYTES, held until the process ends; a call that
+ * would need more (24 bytes per slice, rounded up to 256, plus 8 n_x n_y
+ * bytes per slice with the FFT operator: 32 slices of 511 x 511, 128 of
+ * 255 x 255) returns EINVAL before any work.  theta, v, add (may be NULL) and
+ * out are DEVICE pointers (theta: nslices doubles); the work is enqueued on
+ * the handle's stream and the call returns without waiting for it.  All calls
+ * on one GPU share its scratch array: calls whose work overlaps on one GPU
+ * (other streams, other threads, other handles) race and must be ordered by
+ * the caller. */
+#define MGRIT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int mgrit_apply_noalloc(mgrit_handle* h, int nslices, const double* theta, double sign,
+                        const double* v, const double* add, double* out);
+
 /* FP32 forms of the same operator, M_h + theta A_h of eq. (chp-02-03), as the
  * inner solves of mixed precision apply it (handles set up with MGRIT_PREC_MIXED
  * or MIXED_COARSE only; EINVAL otherwise).  The handle's operator kind and tile

@@ -1105,6 +1105,19 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm32(Geom g, int S, const __bf16* 
     }
 }
 
+__global__ __launch_bounds__(NT) void k_fill_apply_desc(int S, const double* __restrict__ theta, int has_add,
+                                                      ApplyDesc* __restrict__ desc) {
+    const int s = blockIdx.x * NT + threadIdx.x;
+    if (s >= S) return;
+    ApplyDesc d;
+    d.v = s;
+    d.out = s;
+    d.add = has_add ? s : -1;
+    d.pad_ = 0;
+    d.theta = theta[s];
+    desc[s] = d;
+}
+
 __global__ __launch_bounds__(NT) void k_add_g(Geom g, const PropDesc* __restrict__ desc, int S, double* xbase,
                                               const double* gbase) {
     int s, c;
@@ -1853,6 +1866,13 @@ int launch_mx_refine(const Geom* g, const PropDesc* desc, int S, double* xbase, 
     if (S <= 0) return 0;
     hipLaunchKernelGGL(k_mx_refine, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, desc, S,
                        xbase, d32, scale, oact);
+    return (int)hipGetLastError();
+}
+
+int launch_fill_apply_desc(int S, const double* theta, int has_add, ApplyDesc* desc, void* stream) {
+    if (S <= 0) return 0;
+    hipLaunchKernelGGL(k_fill_apply_desc, dim3((S + NT - 1) / NT), dim3(NT), 0, (hipStream_t)stream, S, theta,
+                       has_add, desc);
     return (int)hipGetLastError();
 }
 

@@ -26,12 +26,20 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
 
 #include "../../include/mgrit.h"
 #include "mgrit_internal.h"
+
+// Scratch memory of mgrit_apply_noalloc (callers that cannot allocate device memory): the slice
+// descriptors and the x-pass workspace of the FFT operator live in this fixed array instead of memory
+// the call would allocate.  Each GPU holds its own copy until the process ends.  In host code the
+// name only stands in for the symbol: its device address is looked up once per device at set-up
+// (scratch_address) and only that address is ever passed to a kernel.
+static __device__ __align__(256) unsigned char scratch[MGRIT_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -101,6 +109,8 @@ struct mgrit_handle {
     mgrit_options opt;
     std::vector<double> t;
     hipStream_t stream = nullptr;
+    int device = 0;                          // device current at set-up
+    void* scratch = nullptr;                 // device address of that device's scratch array
     Geom geom;
     Seqs seqs;
     double* d_seq = nullptr;                 // T1x | A2x | T1y | A2y
@@ -175,6 +185,25 @@ struct mgrit_handle {
 };
 
 namespace {
+
+// Device address of the scratch array on device `dev` (the current device), looked up once per device.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(MGRIT_EINVAL, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MGRIT_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
 
 int dmalloc(mgrit_handle* h, void** p, size_t bytes) {
     if (bytes == 0) bytes = 8;
@@ -1333,6 +1362,15 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
         delete h;
         return fail(MGRIT_EINVAL, "the FFT operator takes n_x, n_y <= %d", (MGRIT_FFT_LEN + 1) / 2);
     }
+    {   // the device current at set-up, and its scratch array (once per device)
+        const hipError_t e = hipGetDevice(&h->device);
+        int rc0 = e == hipSuccess ? 0 : fail(MGRIT_EHIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+        if (!rc0) rc0 = scratch_address(h->device, &h->scratch);
+        if (rc0) {
+            delete h;
+            return rc0;
+        }
+    }
     h->use_fft = o.op == MGRIT_OP_FFT || (o.op == MGRIT_OP_AUTO && fft_fits);
     if (h->use_fft) g.pmax = std::max(g.pmax, (int)((nx + MGRIT_FFT_LINES - 1) / MGRIT_FFT_LINES));
     h->nop = h->use_fft ? (int)((nx + MGRIT_FFT_LINES - 1) / MGRIT_FFT_LINES) : g.ntiles[1];
@@ -1638,6 +1676,30 @@ int apply_f32(mgrit_handle* h, int kind, int nslices, const double* theta, const
 }  // namespace
 
 extern "C" {
+
+int mgrit_apply_noalloc(mgrit_handle* h, int nslices, const double* theta, double sign, const double* v,
+                        const double* add, double* out) {
+    if (!h) return fail(MGRIT_EINVAL, "NULL handle");
+    if (nslices < 0 || (nslices > 0 && (!theta || !v || !out))) return fail(MGRIT_EINVAL, "bad slices");
+    if (sign != 1.0 && sign != -1.0) return fail(MGRIT_EINVAL, "sign must be +1 or -1");
+    if (nslices == 0) return MGRIT_OK;
+    const size_t desc_bytes = ((size_t)nslices * sizeof(ApplyDesc) + 255) / 256 * 256;
+    const size_t ws_bytes = h->use_fft ? (size_t)nslices * h->geom.stride * sizeof(double) : 0;
+    if (desc_bytes + ws_bytes > (size_t)MGRIT_NOALLOC_SCRATCH_BYTES)
+        return fail(MGRIT_EINVAL, "%d slices need %zu bytes of scratch, more than its %zu bytes", nslices,
+                    desc_bytes + ws_bytes, (size_t)MGRIT_NOALLOC_SCRATCH_BYTES);
+    ApplyDesc* d = (ApplyDesc*)h->scratch;
+    double* pbuf = (double*)((char*)h->scratch + desc_bytes);
+    HIPCHK(launch_fill_apply_desc(nslices, theta, add ? 1 : 0, d, h->stream));
+    if (h->use_fft) {
+        HIPCHK(launch_fft_apply(&h->geom, &h->plan, d, nslices, v, out, add, sign, 0, nullptr, pbuf, h->stream));
+    } else {
+        int tv = 0;
+        CHK(tile_variant(h, nullptr, nslices, &tv));
+        HIPCHK(launch_apply(&h->geom, &h->seqs, tv, d, nslices, v, out, add, sign, 0, nullptr, nullptr, h->stream));
+    }
+    return MGRIT_OK;
+}
 
 int mgrit_apply_f32(mgrit_handle* h, int nslices, const double* theta, const float* v, float* out, int mem) {
     return apply_f32(h, 0, nslices, theta, v, nullptr, out, mem);

@@ -220,6 +220,8 @@ int launch_fft_rhs32(const Geom* g, const FftPlan* pl, const PropDesc* desc, int
 int launch_fft_init_residual32(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const double* xbase,
                                const float* b32, float* r32, double* partial_rr, float* pbuf, void* stream);
 
+// desc[s] = {v = s, out = s, add = has_add ? s : -1, theta = theta[s]} for s < S (theta on the device).
+int launch_fill_apply_desc(int S, const double* theta, int has_add, ApplyDesc* desc, void* stream);
 // x[s] += G[s] for slices with g >= 0.
 int launch_add_g(const Geom* g, const PropDesc* desc, int S, double* xbase, const double* gbase, void* stream);
 // y[yi[s]] += a * x[xi[s]]; when partial != NULL, partial of ||y||^2 after the update (nchunk entries).

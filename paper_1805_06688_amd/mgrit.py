@@ -57,7 +57,7 @@ class RequestInfo(ctypes.Structure):
 
 
 SYMBOLS = ("mgrit_default_options", "mgrit_setup", "mgrit_solve", "mgrit_iterate", "mgrit_sequential",
-           "mgrit_propagate", "mgrit_apply", "mgrit_apply_f32", "mgrit_rhs_f32", "mgrit_residual_f32",
+           "mgrit_propagate", "mgrit_apply", "mgrit_apply_noalloc", "mgrit_apply_f32", "mgrit_rhs_f32", "mgrit_residual_f32",
            "mgrit_sequences", "mgrit_levels", "mgrit_destroy",
            "mgrit_last_error", "mgrit_toeplitz_sequences", "mgrit_stiffness_scale", "mgrit_profile_enable",
            "mgrit_profile_read", "mgrit_fd_stiffness_entry", "mgrit_fd_eigen", "mgrit_footprint",
@@ -84,6 +84,8 @@ def load_library(path=_LIB_PATH):
     lib.mgrit_propagate.restype = c_int
     lib.mgrit_apply.argtypes = [P, c_int, ctypes.POINTER(c_dbl), c_dbl, P, P, P, c_int]
     lib.mgrit_apply.restype = c_int
+    lib.mgrit_apply_noalloc.argtypes = [P, c_int, P, c_dbl, P, P, P]
+    lib.mgrit_apply_noalloc.restype = c_int
     lib.mgrit_apply_f32.argtypes = [P, c_int, ctypes.POINTER(c_dbl), P, P, c_int]
     lib.mgrit_apply_f32.restype = c_int
     lib.mgrit_rhs_f32.argtypes = [P, c_int, ctypes.POINTER(c_dbl), P, P, P, c_int]
@@ -343,6 +345,16 @@ class Solver:
         U = self._out(v, S * n, out)
         _check(_lib.mgrit_apply(self._h, S, theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(sign),
                                 _ptr(v, mem, S * n), _ptr(add, mem, S * n), _ptr(U, mem, S * n), mem))
+        return self._shape(U, S)
+
+    def apply_noalloc(self, theta, v, sign=1.0, add=None, out=None):
+        """mgrit_apply_noalloc: as apply() with device arrays only (theta a float64 CUDA tensor); the work is
+        enqueued on the handle's stream and nothing is allocated by the library."""
+        S, n = theta.numel(), self.slice_size
+        U = self._out(v, S * n, out)
+        _check(_lib.mgrit_apply_noalloc(self._h, S, _ptr(theta, MEM_DEVICE, S), float(sign),
+                                        _ptr(v, MEM_DEVICE, S * n), _ptr(add, MEM_DEVICE, S * n),
+                                        _ptr(U, MEM_DEVICE, S * n)))
         return self._shape(U, S)
 
     def _out32(self, like, count, out):
