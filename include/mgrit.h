@@ -77,6 +77,13 @@ extern "C" {
  * coarse levels.  Both take precond NONE or FD_BF16. */
 #define MGRIT_PREC_MIXED        1
 #define MGRIT_PREC_MIXED_COARSE 2
+/* MIXED_BF16: MIXED with the inner operator's Toeplitz products on the BF16
+ * matrix cores: every FP32 operand is split into two BF16 parts, x = x_hi +
+ * x_lo + O(2^-18 x), and a v is taken as a_hi v_hi + a_hi v_lo + a_lo v_hi with
+ * FP32 accumulation (relative error of each product below 3 x 2^-18, about the
+ * inner tolerance); the mass stencil, the vectors and every FP64 step are those
+ * of MIXED.  The refinement recovers the FP64 solution as in MIXED. */
+#define MGRIT_PREC_MIXED_BF16   3
 
 /* Preconditioner of the spatial CG solves (Section 3.2 uses none).  FD: exact
  * inverse of a Kronecker-structured approximation of the step matrix (lumped
@@ -248,6 +255,7 @@ int mgrit_apply_noalloc(mgrit_handle* h, int nslices, const double* theta, doubl
  *                       (the right-hand side of a pass at a loose CG tolerance);
  *   mgrit_residual_f32: r[s] = b[s] - (M_h x[s] + theta[s] A_h x[s]), x FP64
  *                       rounded on load, b and r FP32 (its initial residual).
+ * With MGRIT_PREC_MIXED_BF16, mgrit_apply_f32 applies the split-BF16 products.
  * The last two exist for the FFT operator only (EINVAL with DENSE).  theta: host
  * array of nslices values; arrays [nslices][n_y][n_x], all in the memory space
  * `mem`; outputs may not overlap inputs.  Returns after the stream has finished. */

@@ -33,6 +33,7 @@ namespace {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 // Matrix-core step of the operator tiles per element type: FP64
 // v_mfma_f64_16x16x4f64, or FP32 v_mfma_f32_16x16x4f32 for the inner solves
@@ -125,6 +126,52 @@ __device__ __forceinline__ double slice_sum(const double* partial, int pmax, int
     double acc = 0.0;
     for (int i = 0; i < count; ++i) acc += p[i];
     return acc;
+}
+
+// Epilogue of an operator tile: epi[jl][il] (ld TT + 1) holds A v on the tile; writes
+// out = add + sign (M v + theta A v) and, with dot_mode, the dot products of its 32 x 32 quadrants to
+// dot_out[32-tile index] (per quadrant with the same thread -> element order for both tile sizes, so the
+// sums do not depend on TT).
+template <int TT, typename T>
+__device__ __forceinline__ void tile_epilogue(const Geom& g, const T* __restrict__ v, T* __restrict__ out,
+                                              const T* __restrict__ add, T theta, T sign, int dot_mode, int i0,
+                                              int j0, const T* epi, double* red, double* dot_out) {
+    const int nx = g.nx, ny = g.ny;
+    const int tid = threadIdx.x;
+    const T mass = (T)g.mass;
+#pragma unroll
+    for (int qd = 0; qd < (TT / 32) * (TT / 32); ++qd) {
+        const int qx = qd % (TT / 32), qy = qd / (TT / 32);
+        double dot = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int idx = tid + NT * k;
+            const int jl = qy * 32 + idx / 32, il = qx * 32 + (idx & 31);
+            const int i = i0 + il, j = j0 + jl;
+            if (i >= nx || j >= ny) continue;
+            const long long o = (long long)j * nx + i;
+            const T c = v[o];
+            const bool hl = i > 0, hr = i + 1 < nx, hd = j > 0, hu = j + 1 < ny;
+            T m7 = T(6) * c;
+            m7 += hl ? v[o - 1] : T(0);
+            m7 += hr ? v[o + 1] : T(0);
+            m7 += hd ? v[o - nx] : T(0);
+            m7 += hu ? v[o + nx] : T(0);
+            m7 += (hr && hu) ? v[o + nx + 1] : T(0);
+            m7 += (hl && hd) ? v[o - nx - 1] : T(0);
+            T val = sign * (mass * m7 + theta * epi[jl * (TT + 1) + il]);
+            if (add) val += add[o];
+            out[o] = val;
+            if (dot_mode == 1) dot += (double)c * (double)val;
+            else if (dot_mode == 2) dot += (double)val * (double)val;
+        }
+        if (dot_mode) {
+            dot = block_sum(dot, red);
+            const int gx = i0 / 32 + qx, gy = j0 / 32 + qy;
+            if (threadIdx.x == 0 && gx < g.tiles_x[1] && gy < g.tiles_y[1])
+                dot_out[gx + g.tiles_x[1] * gy] = dot;
+        }
+    }
 }
 
 // out = add + sign (M v + theta A v) on one TT x TT tile; with dot_mode the
@@ -256,43 +303,7 @@ __device__ void apply_tile(const Geom& g, const typename MF<T>::S& sq, const T* 
                 epi[jl * (TT + 1) + il] = acc[fi][fj][r];
             }
     __syncthreads();
-
-    // Per 32 x 32 quadrant (the partial-sum unit of both tile sizes, with the
-    // same thread -> element order), so the sums do not depend on TT.
-    const T mass = (T)g.mass;
-#pragma unroll
-    for (int qd = 0; qd < (TT / 32) * (TT / 32); ++qd) {
-        const int qx = qd % (TT / 32), qy = qd / (TT / 32);
-        double dot = 0.0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int idx = tid + NT * k;
-            const int jl = qy * 32 + idx / 32, il = qx * 32 + (idx & 31);
-            const int i = i0 + il, j = j0 + jl;
-            if (i >= nx || j >= ny) continue;
-            const long long o = (long long)j * nx + i;
-            const T c = v[o];
-            const bool hl = i > 0, hr = i + 1 < nx, hd = j > 0, hu = j + 1 < ny;
-            T m7 = T(6) * c;
-            m7 += hl ? v[o - 1] : T(0);
-            m7 += hr ? v[o + 1] : T(0);
-            m7 += hd ? v[o - nx] : T(0);
-            m7 += hu ? v[o + nx] : T(0);
-            m7 += (hr && hu) ? v[o + nx + 1] : T(0);
-            m7 += (hl && hd) ? v[o - nx - 1] : T(0);
-            T val = sign * (mass * m7 + theta * epi[jl * (TT + 1) + il]);
-            if (add) val += add[o];
-            out[o] = val;
-            if (dot_mode == 1) dot += (double)c * (double)val;
-            else if (dot_mode == 2) dot += (double)val * (double)val;
-        }
-        if (dot_mode) {
-            dot = block_sum(dot, red);
-            const int gx = i0 / 32 + qx, gy = j0 / 32 + qy;
-            if (threadIdx.x == 0 && gx < g.tiles_x[1] && gy < g.tiles_y[1])
-                dot_out[gx + g.tiles_x[1] * gy] = dot;
-        }
-    }
+    tile_epilogue<TT, T>(g, v, out, add, theta, sign, dot_mode, i0, j0, epi, red, dot_out);
 }
 
 // ---- operator application over slices given by ApplyDesc ----
@@ -376,6 +387,183 @@ __global__ __launch_bounds__(NT) void k_apply32(Geom g, Seqs32 sq, const PropDes
     const long long so = (long long)s * g.stride;
     apply_tile<TT, float>(g, sq, pws + so, qws + so, nullptr, desc[s].theta_lhs, 1.0, 1, tile, lds, red,
                           partial + (long long)s * g.pmax);
+}
+
+// q32 = M p32 + theta_lhs A p32 with the Toeplitz products in BF16 on the matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  Each FP32 operand x is split as
+// x_hi = bf16(x), x_lo = bf16(x - x_hi), so |x - x_hi - x_lo| <= 2^-18 |x|, and every product
+// a v is taken as a_hi v_hi + a_hi v_lo + a_lo v_hi: three BF16 products whose sum misses
+// a v by at most 3 2^-18 |a| |v|.  64 x 64 output tiles as in apply_tile (same wave grid, same
+// epilogue and partial sums); per 32-deep chunk of the contraction the workgroup stages the
+// split strip of p (with its one-line halo) and the three split 64 x 32 Toeplitz tiles of one
+// direction in LDS, rows 16-byte aligned, so every operand of the MFMA is one 16-byte read.
+// MFMA 16x16x32 bf16 lane layout: A[i][k] and B^T[j][k] hold k = 8 (lane/16) + e, e = 0..7, of
+// row i = lane % 16 (resp. column j); accumulator element r of lane l is D[4 (l/16) + r][l % 16].
+namespace obf {
+constexpr int TT = 64;
+constexpr int KCH = 32;                       // contraction chunk: one MFMA depth
+constexpr int LD = KCH + 8;                   // LDS row stride in BF16 elements (80 bytes)
+constexpr int HALO = TT + 2;
+constexpr int WIN = KCH + TT;                 // generating-sequence window per chunk
+constexpr int STRIP = HALO * LD;              // one split part of the strip
+constexpr int TILE = TT * LD;                 // one split part of one Toeplitz tile
+constexpr int BYTES = (2 * STRIP + 6 * TILE) * 2 + 3 * WIN * 4;
+constexpr int EPI_BYTES = TT * (TT + 1) * 4;
+static_assert(EPI_BYTES <= BYTES, "epilogue staging must fit the operand staging");
+}  // namespace obf
+
+__device__ __forceinline__ unsigned int split_pair(float x0, float x1, unsigned int& lo) {
+    const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
+    const __bf16 l0 = (__bf16)(x0 - (float)h0), l1 = (__bf16)(x1 - (float)h1);
+    lo = (unsigned int)__builtin_bit_cast(unsigned short, l0) |
+         ((unsigned int)__builtin_bit_cast(unsigned short, l1) << 16);
+    return (unsigned int)__builtin_bit_cast(unsigned short, h0) |
+           ((unsigned int)__builtin_bit_cast(unsigned short, h1) << 16);
+}
+
+__global__ __launch_bounds__(NT) void k_apply_bf16(Geom g, Seqs32 sq, const PropDesc* __restrict__ desc, int S,
+                                                   const float* pws, float* qws, double* partial,
+                                                   const int* active) {
+    using namespace obf;
+    int s, tile;
+    decode_block(g.ntiles[0], S, s, tile);
+    if (s < 0) return;
+    if (active && !active[s]) return;
+    __shared__ __attribute__((aligned(16))) unsigned char raw[BYTES];
+    __shared__ double red[4];
+    __bf16* Shi = (__bf16*)raw;                      // strip [row][k]
+    __bf16* Slo = Shi + STRIP;
+    __bf16* Thi = Slo + STRIP;                       // three Toeplitz tiles [row][k]
+    __bf16* Tlo = Thi + 3 * TILE;
+    float* w = (float*)(Tlo + 3 * TILE);             // three windows of WIN values
+    const long long so = (long long)s * g.stride;
+    const float* v = pws + so;
+    const int nx = g.nx, ny = g.ny;
+    const int ti = tile % g.tiles_x[0], tj = tile / g.tiles_x[0];
+    const int i0 = ti * TT, j0 = tj * TT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int wi = wave & 1, wj = wave >> 1;
+
+    flt4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = flt4{0.f, 0.f, 0.f, 0.f};
+
+    // Toeplitz tiles of one chunk: T_t[r][kk] = w_t[q(r, kk)], stored as split pairs along kk
+    auto build_tiles = [&](bool xdir) {
+        for (int idx = tid; idx < 3 * TT * (KCH / 2); idx += NT) {
+            const int t = idx / (TT * (KCH / 2));
+            const int rem = idx - t * (TT * (KCH / 2));
+            const int r = rem / (KCH / 2), kk = 2 * (rem - r * (KCH / 2));
+            // x: A[i][k] = w[k - i + TT - 1];  y: B^T[j][k] = w[j - k + KCH - 1]
+            const int q0 = xdir ? kk - r + TT - 1 : r - kk + KCH - 1;
+            const int q1 = xdir ? q0 + 1 : q0 - 1;
+            unsigned int lo;
+            const unsigned int hi = split_pair(w[t * WIN + q0], w[t * WIN + q1], lo);
+            *(unsigned int*)&Thi[t * TILE + r * LD + kk] = hi;
+            *(unsigned int*)&Tlo[t * TILE + r * LD + kk] = lo;
+        }
+    };
+    // one chunk of products: acc += T_t (x: A operand) or strip rows (y: A operand) against the other
+    auto multiply = [&](bool xdir) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            // strip row offset of factor t: x: columns j, j+1, j-1; y: rows i, i+1, i-1
+            const int sh = t == 0 ? 1 : (t == 1 ? 2 : 0);
+            bf8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                const int il = wi * 32 + f * 16 + lr, jl = wj * 32 + f * 16 + lr;
+                if (xdir) {
+                    ah[f] = *(const bf8*)&Thi[t * TILE + il * LD + 8 * lg];
+                    al[f] = *(const bf8*)&Tlo[t * TILE + il * LD + 8 * lg];
+                    bh[f] = *(const bf8*)&Shi[(jl + sh) * LD + 8 * lg];
+                    bl[f] = *(const bf8*)&Slo[(jl + sh) * LD + 8 * lg];
+                } else {
+                    ah[f] = *(const bf8*)&Shi[(il + sh) * LD + 8 * lg];
+                    al[f] = *(const bf8*)&Slo[(il + sh) * LD + 8 * lg];
+                    bh[f] = *(const bf8*)&Thi[t * TILE + jl * LD + 8 * lg];
+                    bl[f] = *(const bf8*)&Tlo[t * TILE + jl * LD + 8 * lg];
+                }
+            }
+#pragma unroll
+            for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+                for (int fj = 0; fj < 2; ++fj) {
+                    acc[fi][fj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[fi], bh[fj], acc[fi][fj], 0, 0, 0);
+                    acc[fi][fj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[fi], bl[fj], acc[fi][fj], 0, 0, 0);
+                    acc[fi][fj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[fi], bh[fj], acc[fi][fj], 0, 0, 0);
+                }
+        }
+    };
+
+    // ---- x-direction: X[i][j] = sum_k A1(k-i) v[j][k] + A2(k-i) v[j+1][k] + A2(i-k) v[j-1][k] ----
+    for (int k0 = 0; k0 < nx; k0 += KCH) {
+        for (int idx = tid; idx < HALO * (KCH / 2); idx += NT) {
+            const int jj = idx / (KCH / 2), kk = 2 * (idx - jj * (KCH / 2));
+            const int k = k0 + kk, j = j0 - 1 + jj;
+            const bool row = j >= 0 && j < ny;
+            const float x0 = (row && k < nx) ? v[(long long)j * nx + k] : 0.f;
+            const float x1 = (row && k + 1 < nx) ? v[(long long)j * nx + k + 1] : 0.f;
+            unsigned int lo;
+            *(unsigned int*)&Shi[jj * LD + kk] = split_pair(x0, x1, lo);
+            *(unsigned int*)&Slo[jj * LD + kk] = lo;
+        }
+        const int dbase = k0 - i0 - (TT - 1);
+        for (int q = tid; q < WIN; q += NT) {
+            const int d = dbase + q;
+            w[q] = sq.T1x[g.seq_off_x + d];
+            w[WIN + q] = sq.A2x[g.seq_off_x + d];
+            w[2 * WIN + q] = sq.A2x[g.seq_off_x - d];
+        }
+        __syncthreads();
+        build_tiles(true);
+        __syncthreads();
+        multiply(true);
+        __syncthreads();
+    }
+
+    // ---- y-direction: Y[i][j] = sum_k v[k][i] A1(j-k) + v[k][i+1] A2(k-j) + v[k][i-1] A2(j-k) ----
+    for (int k0 = 0; k0 < ny; k0 += KCH) {
+        for (int idx = tid; idx < KCH * HALO; idx += NT) {
+            const int kk = idx / HALO, ii = idx - kk * HALO;
+            const int k = k0 + kk, i = i0 - 1 + ii;
+            const float x = (k < ny && i >= 0 && i < nx) ? v[(long long)k * nx + i] : 0.f;
+            const __bf16 hi = (__bf16)x;
+            Shi[ii * LD + kk] = hi;
+            Slo[ii * LD + kk] = (__bf16)(x - (float)hi);
+        }
+        const int ebase = j0 - k0 - (KCH - 1);
+        for (int q = tid; q < WIN; q += NT) {
+            const int e = ebase + q;
+            w[q] = sq.T1y[g.seq_off_y + e];
+            w[WIN + q] = sq.A2y[g.seq_off_y - e];
+            w[2 * WIN + q] = sq.A2y[g.seq_off_y + e];
+        }
+        __syncthreads();
+        build_tiles(false);
+        __syncthreads();
+        multiply(false);
+        __syncthreads();
+    }
+
+    float* epi = (float*)raw;
+#pragma unroll
+    for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+        for (int fj = 0; fj < 2; ++fj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int il = wi * 32 + fi * 16 + 4 * lg + r;
+                const int jl = wj * 32 + fj * 16 + lr;
+                epi[jl * (TT + 1) + il] = acc[fi][fj][r];
+            }
+    __syncthreads();
+    tile_epilogue<TT, float>(g, v, qws + so, (const float*)nullptr, (float)desc[s].theta_lhs, 1.0f, 1, i0, j0, epi,
+                             red, partial + (long long)s * g.pmax);
 }
 
 // Start of a refinement step from the FP64 residual (np partials of ||b||^2
@@ -1820,6 +2008,14 @@ int launch_apply32(const Geom* g, const Seqs32* sq, int tv, const PropDesc* desc
     else
         hipLaunchKernelGGL(k_apply32<32>, dim3(grid_blocks(g->ntiles[1], S)), dim3(NT), 0, st, *g, *sq, desc, S, p32,
                            q32, partial_pq, active);
+    return (int)hipGetLastError();
+}
+
+int launch_apply_bf16(const Geom* g, const Seqs32* sq, const PropDesc* desc, int S, const float* p32, float* q32,
+                      double* partial_pq, const int* active, void* stream) {
+    if (S <= 0) return 0;
+    hipLaunchKernelGGL(k_apply_bf16, dim3(grid_blocks(g->ntiles[0], S)), dim3(NT), 0, (hipStream_t)stream, *g, *sq,
+                       desc, S, p32, q32, partial_pq, active);
     return (int)hipGetLastError();
 }
 

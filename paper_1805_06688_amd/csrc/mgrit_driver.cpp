@@ -726,6 +726,8 @@ int op_cg(mgrit_handle* h, int tv, const Pass& ps, const double* pin, double* qo
 }
 
 int op_cg32(mgrit_handle* h, int tv, const Pass& ps, const float* pin, float* qout, const int* act) {
+    if (h->opt.precision == MGRIT_PREC_MIXED_BF16)
+        return launch_apply_bf16(&h->geom, &h->seqs32, ps.d, ps.S, pin, qout, h->ppq, act, h->stream);
     if (h->use_fft)
         return launch_fft_apply32(&h->geom, &h->plan, ps.d, ps.S, pin, qout, h->ppq, act, h->pfft32, h->stream);
     return launch_apply32(&h->geom, &h->seqs32, tv, ps.d, ps.S, pin, qout, h->ppq, act, h->stream);
@@ -895,7 +897,8 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     const int S = ps.S;
     if (S == 0) return 0;
     if (S > h->Smax) return fail(MGRIT_EINVAL, "batch of %d slices exceeds workspace (%d)", S, h->Smax);
-    if (h->opt.precision == MGRIT_PREC_MIXED || (h->opt.precision == MGRIT_PREC_MIXED_COARSE && h->cur_level > 0))
+    if (h->opt.precision == MGRIT_PREC_MIXED || h->opt.precision == MGRIT_PREC_MIXED_BF16 ||
+        (h->opt.precision == MGRIT_PREC_MIXED_COARSE && h->cur_level > 0))
         return run_pass_mixed(h, ps, ubase, xbase, fbase, gbase, x0base, warm);
     const Geom* g = &h->geom;
     void* st = (void*)h->stream;
@@ -984,6 +987,9 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
     const double eta = h->opt.inner_rtol > 0.0 ? h->opt.inner_rtol : 1e-5;
     const bool pc = h->opt.precond == MGRIT_PRECOND_FD_BF16;
     const int nop = h->nop, npc = g->ntiles[1], nc = g->nchunk;
+    // partials of the inner operator: one per 32 x 32 block from the tiled kernels (dense FP32, split
+    // BF16), one per y-pass workgroup from the FFT passes
+    const int nop32 = (h->use_fft && h->opt.precision != MGRIT_PREC_MIXED_BF16) ? h->nop : g->ntiles[1];
     const int maxit = h->opt.cg_maxit;
     int tv = 0, tv32 = -1;
     // Loose passes (coarse levels) form the right-hand side and the initial residual in FP32 as
@@ -1011,7 +1017,10 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
         HIPCHK(launch_mx_begin(g, ps.d, S, xbase, all32 ? nullptr : h->r, h->pbb, h->pout, nop, rtol2, eta * eta,
                                outer == 0 ? 1 : 0, h->bb, h->mx_scale, h->mx_eta2, h->mx_oact, h->act[0], h->iters,
                                h->r32, h->d32, pc ? nullptr : h->p32, h->prr[0], h->d_start, h->d_iters, st));
-        if (tv32 < 0) CHK(tile_variant(h, &ps, S, &tv32, true));
+        if (tv32 < 0) {
+            if (h->opt.precision == MGRIT_PREC_MIXED_BF16) tv32 = 0;     // one tile size
+            else CHK(tile_variant(h, &ps, S, &tv32, true));
+        }
         if (pc)
             HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, h->p32, h->tb1, h->tb2, h->prz[0],
                                       h->act[0], st));
@@ -1023,7 +1032,7 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
             if (h->prof_on) CHK(prof_record(h, 2 + tv32));
             HIPCHK(op_cg32(h, tv32, ps, h->p32, h->q32, h->act[c0]));
             if (h->prof_on) CHK(prof_record(h, 2 + tv32));
-            HIPCHK(launch_mx_update(g, S, h->d32, h->r32, h->p32, h->q32, prho[c0], nr, h->ppq, nop, h->prr[nxt],
+            HIPCHK(launch_mx_update(g, S, h->d32, h->r32, h->p32, h->q32, prho[c0], nr, h->ppq, nop32, h->prr[nxt],
                                     h->act[c0], st));
             if (pc)
                 HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, nullptr, h->tb1, h->tb2, h->prz[nxt],
@@ -1318,7 +1327,7 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
         return fail(MGRIT_EINVAL, "unknown coarse propagator");
     if (o.coarse == MGRIT_COARSE_OPT && (o.m % 2))
         return fail(MGRIT_EINVAL, "the OPT coarse propagator needs an even coarsening factor");
-    if (o.precision < MGRIT_PREC_FP64 || o.precision > MGRIT_PREC_MIXED_COARSE)
+    if (o.precision < MGRIT_PREC_FP64 || o.precision > MGRIT_PREC_MIXED_BF16)
         return fail(MGRIT_EINVAL, "unknown precision");
     if (o.precision != MGRIT_PREC_FP64 && o.precond == MGRIT_PRECOND_FD)
         return fail(MGRIT_EINVAL, "mixed precision takes precond NONE or FD_BF16");
@@ -1654,7 +1663,9 @@ int apply_f32(mgrit_handle* h, int kind, int nslices, const double* theta, const
         if (kind == 0) {
             int tv = 0;
             CHK(tile_variant(h, nullptr, S, &tv));
-            if (h->use_fft)
+            if (h->opt.precision == MGRIT_PREC_MIXED_BF16)
+                HIPCHK(launch_apply_bf16(g, &h->seqs32, d, S, (const float*)vb, ob, h->ppq, nullptr, h->stream));
+            else if (h->use_fft)
                 HIPCHK(launch_fft_apply32(g, &h->plan, d, S, (const float*)vb, ob, h->ppq, nullptr, h->pfft32,
                                           h->stream));
             else

@@ -176,6 +176,10 @@ int launch_fdb_apply32(const Geom* g, const FdMatsB* fd, const PropDesc* desc, i
 // q32 = M p32 + theta_lhs A p32 (FP32 matrix cores) for active slices, partial p.q.
 int launch_apply32(const Geom* g, const Seqs32* sq, int tv, const PropDesc* desc, int S, const float* p32,
                    float* q32, double* partial_pq, const int* active, void* stream);
+// The same product with the Toeplitz products as split BF16 products on the matrix cores
+// (a v = a_hi v_hi + a_hi v_lo + a_lo v_hi, FP32 accumulation; 64-tiles).
+int launch_apply_bf16(const Geom* g, const Seqs32* sq, const PropDesc* desc, int S, const float* p32, float* q32,
+                      double* partial_pq, const int* active, void* stream);
 // Start of a refinement step from the FP64 residual (or, with rws == NULL, from an FP32
 // residual already in r32, scaled in place): flags, scale ||r||, inner tolerance
 // eta^2 = max(rtol^2 ||b||^2 / ||r||^2, eta_min2), r32 = r / ||r||, d32 = 0, and p32 = r32

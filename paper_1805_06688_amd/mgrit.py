@@ -17,7 +17,7 @@ OK, EINVAL, ENOMEM, EHIP, ENOCONV, EDIVERGED = 0, -1, -2, -3, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 RELAX = {"F": 0, "FCF": 1}
 COARSE = {"cn": 0, "be": 1, "cn2": 2, "opt": 3}
-PRECISION = {"fp64": 0, "mixed": 1, "mixed-coarse": 2}
+PRECISION = {"fp64": 0, "mixed": 1, "mixed-coarse": 2, "mixed-bf16": 3}
 PRECOND = {"none": 0, "fd": 1, "fd-bf16": 2}
 TILE = {"auto": 0, "rule": 1, "64": 2, "32": 3}
 OPERATOR = {"auto": 0, "dense": 1, "fft": 2}
