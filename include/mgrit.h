@@ -299,13 +299,28 @@ double mgrit_stiffness_scale(double rho, double h_par, double h_perp);
 double mgrit_fd_stiffness_entry(double rho, double h, double K, int l);
 int mgrit_fd_eigen(double rho, int n, double h, double K, double* V, double* lambda);
 
-/* Instrumentation.  While enabled, a pair of HIP events on the handle's stream
- * brackets every launch of the CG operator kernel (q = (M_h + theta A_h) p, the
- * dominant kernel); enabling resets the counters.  mgrit_profile_read returns,
- * for the 64-point (variant 0) or 32-point (variant 1) tile version of that
- * kernel, or of its FP32 version in mixed precision (variants 2 and 3), the
- * summed kernel time in ms, the number of launches and the number of slice
- * applications they performed (the sum of CG iterations over slices). */
+/* Instrumentation.  While enabled, HIP events on the handle's stream bracket
+ * every launch of the kernels of a CG iteration, per kernel class below
+ * (enabling resets the counters; each pass ends with a stream synchronisation
+ * to read the events, so instrumented solves run slower than plain ones).
+ * mgrit_profile_read returns, for one class, the summed kernel time in ms, the
+ * number of launches and the number of slice applications they performed (the
+ * sum of CG iterations over slices).  Classes: the operator q = (M_h + theta
+ * A_h) p in FP64 (64- or 32-node tiles; the FFT form counts as T64), in FP32
+ * (likewise), and as split-BF16 products; the preconditioner (its four
+ * products); the CG vector updates x += alpha p, r -= alpha q and the
+ * direction updates p = z + beta p, in FP64 and in the FP32 inner solves. */
+#define MGRIT_PROF_OP64_T64      0
+#define MGRIT_PROF_OP64_T32      1
+#define MGRIT_PROF_OP32_T64      2
+#define MGRIT_PROF_OP32_T32      3
+#define MGRIT_PROF_OP_BF16       4
+#define MGRIT_PROF_PRECOND       5
+#define MGRIT_PROF_UPDATE64      6
+#define MGRIT_PROF_DIRECTION64   7
+#define MGRIT_PROF_UPDATE32      8
+#define MGRIT_PROF_DIRECTION32   9
+#define MGRIT_PROF_CLASSES      10
 int mgrit_profile_enable(mgrit_handle* h, int on);
 int mgrit_profile_read(const mgrit_handle* h, int variant, double* apply_ms, long long* launches,
                        long long* slice_applies);

@@ -177,8 +177,8 @@ struct mgrit_handle {
     std::vector<hipEvent_t> prof_ev;
     std::vector<int> prof_tv;                 // tile variant of each recorded event pair
     size_t prof_used = 0;
-    double prof_ms[4] = {0.0, 0.0, 0.0, 0.0};                 // variants: FP64 64, 32; FP32 64, 32
-    long long prof_launches[4] = {0, 0, 0, 0}, prof_slices[4] = {0, 0, 0, 0};
+    double prof_ms[MGRIT_PROF_CLASSES] = {};                  // per kernel class (MGRIT_PROF_*)
+    long long prof_launches[MGRIT_PROF_CLASSES] = {}, prof_slices[MGRIT_PROF_CLASSES] = {};
     // caller arrays of the current solve (level 0)
     double* U0 = nullptr;
     const double* F0 = nullptr;
@@ -681,25 +681,30 @@ int alloc_workspace(mgrit_handle* h, int S) {
     return 0;
 }
 
-int prof_record(mgrit_handle* h, int tv) {
+// Instrumentation marks: an event recorded on the stream before each instrumented launch, tagged with
+// the launch's kernel class; the time from one mark to the next is that launch's (class -1 closes a
+// sequence of launches without starting a new one).
+int prof_record(mgrit_handle* h, int cls) {
     if (h->prof_used == h->prof_ev.size()) {
         hipEvent_t e;
         HIPCHK(hipEventCreate(&e));
         h->prof_ev.push_back(e);
         h->prof_tv.push_back(0);
     }
-    h->prof_tv[h->prof_used] = tv;
+    h->prof_tv[h->prof_used] = cls;
     HIPCHK(hipEventRecord(h->prof_ev[h->prof_used++], h->stream));
     return 0;
 }
 
-// Accumulate the recorded event pairs (the stream has been synchronised).
+// Accumulate the recorded marks (the stream has been synchronised).
 int prof_drain(mgrit_handle* h) {
-    for (size_t i = 0; i + 1 < h->prof_used; i += 2) {
+    for (size_t i = 0; i + 1 < h->prof_used; ++i) {
+        const int cls = h->prof_tv[i];
+        if (cls < 0) continue;
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, h->prof_ev[i], h->prof_ev[i + 1]));
-        h->prof_ms[h->prof_tv[i]] += ms;
-        h->prof_launches[h->prof_tv[i]] += 1;
+        h->prof_ms[cls] += ms;
+        h->prof_launches[cls] += 1;
     }
     h->prof_used = 0;
     return 0;
@@ -934,17 +939,21 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     // The first chunk covers what this pass needed last time, later chunks are
     // short, so few launches find every slice converged.
     const int first = ps.last_iters > 0 ? ps.last_iters : (pc ? 8 : 16);
+    const bool prof = h->prof_on;
     auto iter = [&](int c0, int nr) -> int {
         const int nxt = c0 ^ 1;
-        if (h->prof_on) CHK(prof_record(h, tv));
+        if (prof) CHK(prof_record(h, tv));
         HIPCHK(op_cg(h, tv, ps, h->p, h->q, h->act[c0]));
-        if (h->prof_on) CHK(prof_record(h, tv));
+        if (prof) CHK(prof_record(h, MGRIT_PROF_UPDATE64));
         HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, prho[c0], nr, h->ppq, nop, h->prr[nxt],
                                 h->act[c0], st));
+        if (prof && pc) CHK(prof_record(h, MGRIT_PROF_PRECOND));
         if (pc) HIPCHK(precondition(h->prz[nxt], h->act[c0]));
+        if (prof) CHK(prof_record(h, MGRIT_PROF_DIRECTION64));
         HIPCHK(launch_cg_direction(g, S, zws, h->p, prho[c0], nr, prho[nxt], nrho_next, h->prr[nxt], h->bb, rtol2,
                                    maxit, h->act[c0], h->act[nxt], h->iters, h->d_flags + (size_t)nxt * h->Smax,
                                    h->d_iters, st));
+        if (prof) CHK(prof_record(h, -1));
         return 0;
     };
     auto chunk = [&](int n) -> int {
@@ -966,7 +975,12 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     }
     ps.last_iters = most;
     h->cg_count += its;
-    if (h->prof_on) h->prof_slices[tv] += its;
+    if (h->prof_on) {
+        h->prof_slices[tv] += its;
+        h->prof_slices[MGRIT_PROF_UPDATE64] += its;
+        h->prof_slices[MGRIT_PROF_DIRECTION64] += its;
+        if (pc) h->prof_slices[MGRIT_PROF_PRECOND] += its;
+    }
     h->phi_count += S;
     return 0;
 }
@@ -991,7 +1005,8 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
     // BF16), one per y-pass workgroup from the FFT passes
     const int nop32 = (h->use_fft && h->opt.precision != MGRIT_PREC_MIXED_BF16) ? h->nop : g->ntiles[1];
     const int maxit = h->opt.cg_maxit;
-    int tv = 0, tv32 = -1;
+    const bool prof = h->prof_on;
+    int tv = 0, tv32 = -1, op32_class = MGRIT_PROF_OP32_T64;
     // Loose passes (coarse levels) form the right-hand side and the initial residual in FP32 as
     // well: their rounding (~1e-7 of ||b||) is far below the tolerance, and one refinement step,
     // whose inner target is then the pass tolerance itself, settles the pass.
@@ -1020,6 +1035,7 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
         if (tv32 < 0) {
             if (h->opt.precision == MGRIT_PREC_MIXED_BF16) tv32 = 0;     // one tile size
             else CHK(tile_variant(h, &ps, S, &tv32, true));
+            op32_class = h->opt.precision == MGRIT_PREC_MIXED_BF16 ? MGRIT_PROF_OP_BF16 : MGRIT_PROF_OP32_T64 + tv32;
         }
         if (pc)
             HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, h->p32, h->tb1, h->tb2, h->prz[0],
@@ -1029,17 +1045,20 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
         const int nrho_next = pc ? npc : nc;
         auto iter = [&](int c0, int nr) -> int {
             const int nxt = c0 ^ 1;
-            if (h->prof_on) CHK(prof_record(h, 2 + tv32));
+            if (prof) CHK(prof_record(h, op32_class));
             HIPCHK(op_cg32(h, tv32, ps, h->p32, h->q32, h->act[c0]));
-            if (h->prof_on) CHK(prof_record(h, 2 + tv32));
+            if (prof) CHK(prof_record(h, MGRIT_PROF_UPDATE32));
             HIPCHK(launch_mx_update(g, S, h->d32, h->r32, h->p32, h->q32, prho[c0], nr, h->ppq, nop32, h->prr[nxt],
                                     h->act[c0], st));
+            if (prof && pc) CHK(prof_record(h, MGRIT_PROF_PRECOND));
             if (pc)
                 HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, nullptr, h->tb1, h->tb2, h->prz[nxt],
                                           h->act[c0], st));
+            if (prof) CHK(prof_record(h, MGRIT_PROF_DIRECTION32));
             HIPCHK(launch_mx_direction(g, S, zws, h->p32, prho[c0], nr, prho[nxt], nrho_next, h->prr[nxt],
                                        h->mx_eta2, maxit, h->act[c0], h->act[nxt], h->iters,
                                        h->d_flags + (size_t)nxt * h->Smax, h->d_iters, st));
+            if (prof) CHK(prof_record(h, -1));
             return 0;
         };
         auto chunk = [&](int n) -> int {
@@ -1084,7 +1103,12 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
     }
     h->cg_count += its;
     h->refine_count += steps;
-    if (h->prof_on && tv32 >= 0) h->prof_slices[2 + tv32] += its;
+    if (h->prof_on && tv32 >= 0) {
+        h->prof_slices[op32_class] += its;
+        h->prof_slices[MGRIT_PROF_UPDATE32] += its;
+        h->prof_slices[MGRIT_PROF_DIRECTION32] += its;
+        if (pc) h->prof_slices[MGRIT_PROF_PRECOND] += its;
+    }
     h->phi_count += S;
     return 0;
 }
@@ -1740,7 +1764,7 @@ int mgrit_profile_enable(mgrit_handle* h, int on) {
     HIPCHK(hipStreamSynchronize(h->stream));
     h->prof_on = on != 0;
     h->prof_used = 0;
-    for (int v = 0; v < 4; ++v) {
+    for (int v = 0; v < MGRIT_PROF_CLASSES; ++v) {
         h->prof_ms[v] = 0.0;
         h->prof_launches[v] = 0;
         h->prof_slices[v] = 0;
@@ -1751,7 +1775,8 @@ int mgrit_profile_enable(mgrit_handle* h, int on) {
 int mgrit_profile_read(const mgrit_handle* h, int variant, double* apply_ms, long long* launches,
                        long long* slice_applies) {
     if (!h) return fail(MGRIT_EINVAL, "NULL handle");
-    if (variant < 0 || variant > 3) return fail(MGRIT_EINVAL, "variant must be 0..3");
+    if (variant < 0 || variant >= MGRIT_PROF_CLASSES)
+        return fail(MGRIT_EINVAL, "kernel class must be 0..%d", MGRIT_PROF_CLASSES - 1);
     if (apply_ms) *apply_ms = h->prof_ms[variant];
     if (launches) *launches = h->prof_launches[variant];
     if (slice_applies) *slice_applies = h->prof_slices[variant];

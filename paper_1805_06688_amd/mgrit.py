@@ -406,7 +406,9 @@ class Solver:
         _check(_lib.mgrit_profile_enable(self._h, 1 if on else 0))
 
     def profile_read(self, variant=0):
-        """(kernel ms, launches, slice applications) of the 64-tile (0) or 32-tile (1) operator kernel."""
+        """(kernel ms, launches, slice applications) of one kernel class of the instrumentation (MGRIT_PROF_*:
+        0/1 FP64 operator 64/32 tiles or FFT, 2/3 FP32 operator, 4 split-BF16 operator, 5 preconditioner,
+        6/7 FP64 CG update/direction, 8/9 FP32 update/direction)."""
         ms, n, sl = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_longlong()
         _check(_lib.mgrit_profile_read(self._h, int(variant), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(sl)))
         return ms.value, n.value, sl.value

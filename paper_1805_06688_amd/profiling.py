@@ -8,9 +8,10 @@
         mean value per dispatch of every counter for kernels matching REGEX
     python -m paper_1805_06688_amd.profiling source-hash
         hash of the HIP kernel sources (counters are tied to one version)
-    python -m paper_1805_06688_amd.profiling traffic FETCH_CSV WRITE_CSV REGEX_X REGEX_Y VARIANT [FF WF]
-        HBM bytes per operator application (one x-pass and one y-pass dispatch) from a FETCH_SIZE
-        and a WRITE_SIZE run, each counter scaled by its copy-kernel factor (FF, WF; default 2, 1)
+    python -m paper_1805_06688_amd.profiling traffic FETCH_CSV WRITE_CSV CLASS REGEX [REGEX2] [--ff FF --wf WF]
+        HBM bytes per launch of one kernel class of the library's instrumentation (a launch of the FFT operator
+        is one dispatch of each of its two passes, REGEX and REGEX2) from a FETCH_SIZE and a WRITE_SIZE run,
+        each counter scaled by its copy-kernel factor (FF, WF; default 2, 1)
 """
 import json
 import csv
@@ -112,17 +113,22 @@ def _kib(path, regex, counter):
     return tot, n
 
 
-def traffic(fetch_csv, write_csv, regex_x, regex_y, variant, ff=2.0, wf=1.0):
-    fx, nx = _kib(fetch_csv, regex_x, "FETCH_SIZE")
-    fy, ny = _kib(fetch_csv, regex_y, "FETCH_SIZE")
-    wx, mx = _kib(write_csv, regex_x, "WRITE_SIZE")
-    wy, my = _kib(write_csv, regex_y, "WRITE_SIZE")
-    if not (nx and nx == ny and mx == nx and my == nx):
-        raise SystemExit(f"dispatch counts differ: {nx} {ny} {mx} {my}")
-    per = (ff * (fx + fy) + wf * (wx + wy)) * 1024.0 / nx
-    out = {"variant": int(variant), "source_hash": source_hash(), "counter_factors": {"FETCH_SIZE": ff, "WRITE_SIZE": wf},
-           "applications": nx, "fetch_kib_per_application": {"x": fx / nx, "y": fy / nx},
-           "write_kib_per_application": {"x": wx / nx, "y": wy / nx}, "bytes_per_launch": per}
+def traffic(fetch_csv, write_csv, cls, regexes, ff=2.0, wf=1.0):
+    fetch, write, counts = [], [], []
+    for rx in regexes:
+        f, n = _kib(fetch_csv, rx, "FETCH_SIZE")
+        w, m = _kib(write_csv, rx, "WRITE_SIZE")
+        fetch.append(f)
+        write.append(w)
+        counts += [n, m]
+    if not counts[0] or len(set(counts)) != 1:
+        raise SystemExit(f"dispatch counts differ or are zero: {counts}")
+    n = counts[0]
+    per = (ff * sum(fetch) + wf * sum(write)) * 1024.0 / n
+    out = {"class": int(cls), "kernels": list(regexes), "source_hash": source_hash(),
+           "counter_factors": {"FETCH_SIZE": ff, "WRITE_SIZE": wf}, "launches": n,
+           "fetch_kib_per_launch": [f / n for f in fetch], "write_kib_per_launch": [w / n for w in write],
+           "bytes_per_launch": per}
     print(json.dumps(out, indent=1))
 
 
@@ -137,7 +143,16 @@ if __name__ == "__main__":
     elif cmd == "source-hash":
         print(source_hash())
     elif cmd == "traffic":
-        traffic(*sys.argv[2:6], int(sys.argv[6]), *[float(x) for x in sys.argv[7:9]])
+        import argparse
+        ap = argparse.ArgumentParser()
+        ap.add_argument("fetch_csv")
+        ap.add_argument("write_csv")
+        ap.add_argument("cls", type=int)
+        ap.add_argument("regex", nargs="+")
+        ap.add_argument("--ff", type=float, default=2.0)
+        ap.add_argument("--wf", type=float, default=1.0)
+        a = ap.parse_args(sys.argv[2:])
+        traffic(a.fetch_csv, a.write_csv, a.cls, a.regex, a.ff, a.wf)
     else:
         print(__doc__)
         sys.exit(2)
