@@ -205,10 +205,17 @@ int scratch_address(int dev, void** out) {
     return 0;
 }
 
+// A failed allocation is ENOMEM; the runtime's last-error state is cleared so that the next kernel launch
+// check does not report it again.
+int alloc_failed(hipError_t e, size_t bytes) {
+    (void)hipGetLastError();
+    return fail(MGRIT_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+}
+
 int dmalloc(mgrit_handle* h, void** p, size_t bytes) {
     if (bytes == 0) bytes = 8;
     hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) return fail(MGRIT_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    if (e != hipSuccess) return alloc_failed(e, bytes);
     h->allocations.push_back(*p);
     h->dev_bytes += bytes;
     return 0;
@@ -1224,7 +1231,7 @@ struct Staging {
         }
         void* d = nullptr;
         hipError_t e = hipMalloc(&d, count * sizeof(double));
-        if (e != hipSuccess) return fail(MGRIT_ENOMEM, "staging hipMalloc failed: %s", hipGetErrorString(e));
+        if (e != hipSuccess) return alloc_failed(e, count * sizeof(double));
         owned.push_back(d);
         HIPCHK(hipMemcpyAsync(d, src, count * sizeof(double), hipMemcpyHostToDevice, h->stream));
         *out = (const double*)d;
@@ -1237,7 +1244,7 @@ struct Staging {
         }
         void* d = nullptr;
         hipError_t e = hipMalloc(&d, count * sizeof(double));
-        if (e != hipSuccess) return fail(MGRIT_ENOMEM, "staging hipMalloc failed: %s", hipGetErrorString(e));
+        if (e != hipSuccess) return alloc_failed(e, count * sizeof(double));
         owned.push_back(d);
         *out = (double*)d;
         return 0;
@@ -1552,7 +1559,7 @@ int mgrit_propagate(mgrit_handle* h, int level, const int* step, int nslices, co
             ps.S = S;
             void* d = nullptr;
             hipError_t e = hipMalloc(&d, S * sizeof(PropDesc));
-            if (e != hipSuccess) return fail(MGRIT_ENOMEM, "descriptor allocation failed");
+            if (e != hipSuccess) return alloc_failed(e, S * sizeof(PropDesc));
             descs.owned.push_back(d);
             ps.d = (PropDesc*)d;
             HIPCHK(hipMemcpyAsync(ps.d, ps.h.data(), S * sizeof(PropDesc), hipMemcpyHostToDevice, h->stream));
@@ -1598,7 +1605,7 @@ int mgrit_apply(mgrit_handle* h, int nslices, const double* theta, double sign, 
     }
     void* dd = nullptr;
     hipError_t e = hipMalloc(&dd, nslices * sizeof(ApplyDesc));
-    if (e != hipSuccess) return fail(MGRIT_ENOMEM, "descriptor allocation failed");
+    if (e != hipSuccess) return alloc_failed(e, nslices * sizeof(ApplyDesc));
     sg.owned.push_back(dd);
     HIPCHK(hipMemcpyAsync(dd, hd.data(), nslices * sizeof(ApplyDesc), hipMemcpyHostToDevice, h->stream));
     int tv = 0;
@@ -1651,7 +1658,7 @@ int apply_f32(mgrit_handle* h, int kind, int nslices, const double* theta, const
             return 0;
         }
         hipError_t e = hipMalloc(dst, bytes);
-        if (e != hipSuccess) return fail(MGRIT_ENOMEM, "staging hipMalloc failed: %s", hipGetErrorString(e));
+        if (e != hipSuccess) return alloc_failed(e, bytes);
         owned.push_back(*dst);
         if (copy) HIPCHK(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, h->stream));
         return 0;
@@ -1663,7 +1670,7 @@ int apply_f32(mgrit_handle* h, int kind, int nslices, const double* theta, const
     const int chunk = h->Smax;              // the operator workspaces and partials hold Smax slices
     void* ddesc = nullptr;
     hipError_t e = hipMalloc(&ddesc, std::min(chunk, nslices) * sizeof(PropDesc));
-    if (e != hipSuccess) return fail(MGRIT_ENOMEM, "descriptor allocation failed");
+    if (e != hipSuccess) return alloc_failed(e, std::min(chunk, nslices) * sizeof(PropDesc));
     owned.push_back(ddesc);
     std::vector<PropDesc> hd;
     const Geom* g = &h->geom;
