@@ -116,6 +116,19 @@ extern "C" {
 #define MGRIT_TILE_64    2
 #define MGRIT_TILE_32    3
 
+/* Space discretisation.  P1: linear elements on the triangulated mesh, the
+ * matrices of Section 2 (the paper's scheme).  Q1: bilinear elements on the
+ * same rectangles, whose matrices are Kronecker products of 1-D linear-element
+ * matrices, M_h = M_y (x) M_x and A_h = K_x M_y (x) A_x + K_y A_y (x) M_x, with
+ * M = h/6 tridiag(1, 4, 1) and the dense Toeplitz 1-D fractional stiffness
+ * A[i][j] = h^(1-2rho) / (2 cos(rho pi) Gamma(4-2rho)) g(|i-j|) of
+ * mgrit_fd_stiffness_entry (K = 1).  With Q1 the FD preconditioner is the
+ * exact inverse of the step matrix (consistent 1-D mass, unweighted
+ * stiffness), so each propagator solve converges in one PCG iteration: the
+ * fast-diagonalisation propagator. */
+#define MGRIT_ELEMENT_P1 0
+#define MGRIT_ELEMENT_Q1 1
+
 typedef struct {
     double beta, gamma;     /* fractional orders, 1/2 < beta, gamma < 1 (eq. 1.1)        */
     double Kx, Ky;          /* diffusion coefficients, > 0                               */
@@ -154,6 +167,7 @@ typedef struct {
                             /* first use (needs a non-NULL stream; results are unchanged)   */
     int op;                 /* MGRIT_OP_*                                                */
     int coarse_relax;       /* relaxation on levels >= 1: MGRIT_RELAX_* (-1: as relax)   */
+    int element;            /* MGRIT_ELEMENT_P1 (Section 2) or MGRIT_ELEMENT_Q1          */
 } mgrit_options;
 
 typedef struct {
@@ -172,7 +186,7 @@ typedef struct mgrit_handle mgrit_handle;
  * tol_abs = 1e-9, tol_rel = 0, cg_rtol = 1e-9 (the paper's tolerances, Section 3.2),
  * cg_maxit = 10000, precond = NONE, cg_rtol_adapt = 0, warm_start = 1,
  * divergence_factor = 0, tile_policy = AUTO, cg_rtol_coarse = 0, inner_rtol = 0,
- * graphs = 0, op = AUTO, coarse_relax = -1. */
+ * graphs = 0, op = AUTO, coarse_relax = -1, element = P1. */
 void mgrit_default_options(mgrit_options* opt);
 
 /* Validate the problem, evaluate the Toeplitz generating sequences of Section 2
@@ -269,7 +283,9 @@ int mgrit_residual_f32(mgrit_handle* h, int nslices, const double* theta, const 
  * K c: seq_x = [t_x (n_x) | u_x (n_x) | w_x (n_x)], seq_y likewise with n_y,
  * where t[l] is the distance-l entry of A_1, u[l] the entry (k, k+l) and w[l]
  * the entry (k+l, k) of A_2 (w[0] repeats the diagonal); and the scalars
- * c_x, c_y.  Host buffers of 3 n_x and 3 n_y doubles. */
+ * c_x, c_y.  Host buffers of 3 n_x and 3 n_y doubles.  With Q1 the x sequences
+ * are K_x (4 h_y / 6) a_x (the factor of column j) and K_x (h_y / 6) a_x (columns
+ * j +- 1), a_x the 1-D stiffness entries, likewise y, and c_x = c_y = 1. */
 int mgrit_sequences(const mgrit_handle* h, double* seq_x, double* seq_y, double* cx, double* cy);
 
 /* Host-only helper (no GPU needed): the generating sequences of A_1^rho and A_2^rho
@@ -298,6 +314,9 @@ double mgrit_stiffness_scale(double rho, double h_par, double h_perp);
  * lambda (n).  Returns 0, or a negative value when the eigen-iteration fails. */
 double mgrit_fd_stiffness_entry(double rho, double h, double K, int l);
 int mgrit_fd_eigen(double rho, int n, double h, double K, double* V, double* lambda);
+/* The same with the consistent 1-D mass M = h/6 tridiag(1, 4, 1) (the Q1 pair):
+ * K v = lambda M v, V^T M V = I. */
+int mgrit_fd_eigen_consistent(double rho, int n, double h, double K, double* V, double* lambda);
 
 /* Instrumentation.  While enabled, HIP events on the handle's stream bracket
  * every launch of the kernels of a CG iteration, per kernel class below

@@ -3,7 +3,8 @@
 // The step matrix B = M_h + theta A_h of eq. (chp-02-03) is approximated by a
 // sum of Kronecker products that fast diagonalisation inverts,
 //   P = M_y (x) M_x + theta (M_y (x) K_x + K_y (x) M_x),
-// with 1-D matrices: the lumped mass M = h I (the row sums of M_h are h_x h_y)
+// with 1-D matrices: the lumped mass M = h I (the row sums of M_h are h_x h_y; for the
+// bilinear variant the consistent mass h/6 tridiag(1, 4, 1), which makes P exact)
 // and the 1-D fractional stiffness K = K_rho h^(1-2rho) / (2 cos(rho pi) Gamma(4-2rho)) g(|i-j|),
 // g(l) = |l-2|^p - 4|l-1|^p + 6|l|^p - 4|l+1|^p + |l+2|^p, p = 3 - 2rho (the
 // fourth difference of |x|^p: the Riemann-Liouville derivatives of the hat
@@ -87,7 +88,10 @@ void householder_tridiagonal(Mat& A, std::vector<double>& diag, std::vector<doub
 }
 
 // Implicit QL on the symmetric tridiagonal (diag, off); Z accumulates the rotations
-// (columns of Z become eigenvectors).  Returns false if an eigenvalue fails to converge.
+// (columns of Z become eigenvectors).  The step sequence is the published implicit QL
+// algorithm with Wilkinson-type shifts (Bowdler, Martin, Reinsch and Wilkinson, 1968;
+// EISPACK tql2), written here from that description.  Returns false if an eigenvalue fails
+// to converge.
 bool tridiagonal_ql(std::vector<double>& d, std::vector<double>& e, Mat& Z) {
     const int n = (int)d.size();
     for (int l = 0; l < n; ++l) {
@@ -151,13 +155,15 @@ extern "C" double mgrit_fd_stiffness_entry(double rho, double h, double K, int l
     return (double)(scale * v);
 }
 
-extern "C" int mgrit_fd_eigen(double rho, int n, double h, double K, double* V, double* lambda) {
+namespace {
+
+// K v = lambda M v for the dense symmetric Toeplitz 1-D stiffness K and the tridiagonal mass
+// M = tridiag(m1, m0, m1): C = L^{-1} K L^{-T} with the bidiagonal Cholesky factor L of M, C = Z D Z^T,
+// V = L^{-T} Z (so V^T M V = I).
+int fd_eigen(double rho, int n, double h, double K, double m0, double m1, double* V, double* lambda) {
     if (n < 1) return -1;
-    // 1-D stiffness (dense symmetric Toeplitz) and lumped mass h I (the Cholesky
-    // factor below is then sqrt(h) I; the general tridiagonal form is kept)
     std::vector<double> col(n);
     for (int l = 0; l < n; ++l) col[l] = mgrit_fd_stiffness_entry(rho, h, K, l);
-    const double m0 = h, m1 = 0.0;
     // Cholesky of the tridiagonal mass: L = bidiag(dl on the diagonal, el below)
     std::vector<double> dl(n), el(n, 0.0);
     dl[0] = std::sqrt(m0);
@@ -204,4 +210,16 @@ extern "C" int mgrit_fd_eigen(double rho, int n, double h, double K, double* V, 
         lambda[i] = d[i];
     }
     return 0;
+}
+
+}  // namespace
+
+// lumped mass h I (the preconditioner of the P1 scheme)
+extern "C" int mgrit_fd_eigen(double rho, int n, double h, double K, double* V, double* lambda) {
+    return fd_eigen(rho, n, h, K, h, 0.0, V, lambda);
+}
+
+// consistent mass h/6 tridiag(1, 4, 1) (the exact inverse of the Q1 step matrix)
+extern "C" int mgrit_fd_eigen_consistent(double rho, int n, double h, double K, double* V, double* lambda) {
+    return fd_eigen(rho, n, h, K, 4.0 * h / 6.0, h / 6.0, V, lambda);
 }

@@ -152,13 +152,24 @@ __device__ __forceinline__ void tile_epilogue(const Geom& g, const T* __restrict
             const long long o = (long long)j * nx + i;
             const T c = v[o];
             const bool hl = i > 0, hr = i + 1 < nx, hd = j > 0, hu = j + 1 < ny;
-            T m7 = T(6) * c;
-            m7 += hl ? v[o - 1] : T(0);
-            m7 += hr ? v[o + 1] : T(0);
-            m7 += hd ? v[o - nx] : T(0);
-            m7 += hu ? v[o + nx] : T(0);
-            m7 += (hr && hu) ? v[o + nx + 1] : T(0);
-            m7 += (hl && hd) ? v[o - nx - 1] : T(0);
+            T m7;
+            if (g.q1) {                   // bilinear: (4, 1, 1) in y times (4, 1, 1) in x
+                m7 = T(16) * c;
+                m7 += T(4) * ((hl ? v[o - 1] : T(0)) + (hr ? v[o + 1] : T(0)) + (hd ? v[o - nx] : T(0)) +
+                              (hu ? v[o + nx] : T(0)));
+                m7 += (hr && hu) ? v[o + nx + 1] : T(0);
+                m7 += (hl && hd) ? v[o - nx - 1] : T(0);
+                m7 += (hl && hu) ? v[o + nx - 1] : T(0);
+                m7 += (hr && hd) ? v[o - nx + 1] : T(0);
+            } else {
+                m7 = T(6) * c;
+                m7 += hl ? v[o - 1] : T(0);
+                m7 += hr ? v[o + 1] : T(0);
+                m7 += hd ? v[o - nx] : T(0);
+                m7 += hu ? v[o + nx] : T(0);
+                m7 += (hr && hu) ? v[o + nx + 1] : T(0);
+                m7 += (hl && hd) ? v[o - nx - 1] : T(0);
+            }
             T val = sign * (mass * m7 + theta * epi[jl * (TT + 1) + il]);
             if (add) val += add[o];
             out[o] = val;
@@ -1697,13 +1708,20 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
                 c2 = {theta * c2.x, theta * c2.y};
                 c3 = {theta * c3.x, theta * c3.y};
                 // the mass stencil as three more kernels of the x pass: 6 v + v(i-1) + v(i+1)
-                // on line j, v(i) + v(i+1) on line j+1, v(i) + v(i-1) on line j-1
+                // on line j, v(i) + v(i+1) on line j+1, v(i) + v(i-1) on line j-1 (P1); the
+                // bilinear one: 4 (4 v + v(i-1) + v(i+1)) on line j, 4 v + v(i-1) + v(i+1) on j +- 1
                 const cpx<T> w = tw[k];
-                c1.x += mlen * (T(6) + T(2) * w.x);
-                c2.x += mlen * (T(1) + w.x);
-                c2.y -= mlen * w.y;
-                c3.x += mlen * (T(1) + w.x);
-                c3.y += mlen * w.y;
+                if (g.q1) {
+                    c1.x += mlen * (T(16) + T(8) * w.x);
+                    c2.x += mlen * (T(4) + T(2) * w.x);
+                    c3.x += mlen * (T(4) + T(2) * w.x);
+                } else {
+                    c1.x += mlen * (T(6) + T(2) * w.x);
+                    c2.x += mlen * (T(1) + w.x);
+                    c2.y -= mlen * w.y;
+                    c3.x += mlen * (T(1) + w.x);
+                    c3.y += mlen * w.y;
+                }
             }
             const cpx<T> xa = cadd(cadd(cmul(c1, v0), cmul(c2, vp)), cmul(c3, vm));
             const cpx<T> xb = cadd(cadd(cmul(c1, vp), cmul(c2, vq)), cmul(c3, v0));

@@ -410,15 +410,31 @@ int build_sequences(mgrit_handle* h) {
     const mgrit_problem& p = h->prob;
     const int nx = p.Mx - 1, ny = p.My - 1;
     const double hx = (p.b - p.a) / p.Mx, hy = (p.d - p.c) / p.My;
-    h->cx = mgrit_stiffness_scale(p.beta, hx, hy);
-    h->cy = mgrit_stiffness_scale(p.gamma, hy, hx);
     h->host_seq_x.assign(3 * (size_t)nx, 0.0);
     h->host_seq_y.assign(3 * (size_t)ny, 0.0);
-    mgrit_toeplitz_sequences(p.beta, nx, &h->host_seq_x[0], &h->host_seq_x[nx], &h->host_seq_x[2 * nx]);
-    mgrit_toeplitz_sequences(p.gamma, ny, &h->host_seq_y[0], &h->host_seq_y[ny], &h->host_seq_y[2 * ny]);
-    const double sx = p.Kx * h->cx, sy = p.Ky * h->cy;
-    for (double& v : h->host_seq_x) v *= sx;
-    for (double& v : h->host_seq_y) v *= sy;
+    if (h->opt.element == MGRIT_ELEMENT_Q1) {
+        // K_x M_y (x) A_x: column j of the grid array gets (4 h_y / 6) A_x v_j + (h_y / 6) A_x (v_j+1 + v_j-1),
+        // the three factors of the x contraction; likewise for y with h_x
+        h->cx = h->cy = 1.0;
+        for (int l = 0; l < nx; ++l) {
+            const double a = p.Kx * mgrit_fd_stiffness_entry(p.beta, hx, 1.0, l);
+            h->host_seq_x[l] = 4.0 * hy / 6.0 * a;
+            h->host_seq_x[nx + l] = h->host_seq_x[2 * nx + l] = hy / 6.0 * a;
+        }
+        for (int l = 0; l < ny; ++l) {
+            const double a = p.Ky * mgrit_fd_stiffness_entry(p.gamma, hy, 1.0, l);
+            h->host_seq_y[l] = 4.0 * hx / 6.0 * a;
+            h->host_seq_y[ny + l] = h->host_seq_y[2 * ny + l] = hx / 6.0 * a;
+        }
+    } else {
+        h->cx = mgrit_stiffness_scale(p.beta, hx, hy);
+        h->cy = mgrit_stiffness_scale(p.gamma, hy, hx);
+        mgrit_toeplitz_sequences(p.beta, nx, &h->host_seq_x[0], &h->host_seq_x[nx], &h->host_seq_x[2 * nx]);
+        mgrit_toeplitz_sequences(p.gamma, ny, &h->host_seq_y[0], &h->host_seq_y[ny], &h->host_seq_y[2 * ny]);
+        const double sx = p.Kx * h->cx, sy = p.Ky * h->cy;
+        for (double& v : h->host_seq_x) v *= sx;
+        for (double& v : h->host_seq_y) v *= sy;
+    }
 
     Geom& g = h->geom;
     const int offx = g.seq_off_x, offy = g.seq_off_y;
@@ -560,8 +576,13 @@ int build_fd(mgrit_handle* h) {
     const int nx = p.Mx - 1, ny = p.My - 1;
     const double hx = (p.b - p.a) / p.Mx, hy = (p.d - p.c) / p.My;
     std::vector<double> Vx((size_t)nx * nx), lx(nx), Vy((size_t)ny * ny), ly(ny);
-    if (mgrit_fd_eigen(p.beta, nx, hx, FD_STIFFNESS_WEIGHT * p.Kx, Vx.data(), lx.data()) != 0 ||
-        mgrit_fd_eigen(p.gamma, ny, hy, FD_STIFFNESS_WEIGHT * p.Ky, Vy.data(), ly.data()) != 0)
+    // P1: lumped mass and a lightened stiffness (an approximation of the step matrix); Q1: the consistent
+    // 1-D mass and the unweighted stiffness, whose Kronecker form is the step matrix itself
+    const bool q1 = h->opt.element == MGRIT_ELEMENT_Q1;
+    auto eig = q1 ? mgrit_fd_eigen_consistent : mgrit_fd_eigen;
+    const double wgt = q1 ? 1.0 : FD_STIFFNESS_WEIGHT;
+    if (eig(p.beta, nx, hx, wgt * p.Kx, Vx.data(), lx.data()) != 0 ||
+        eig(p.gamma, ny, hy, wgt * p.Ky, Vy.data(), ly.data()) != 0)
         return fail(MGRIT_EINVAL, "eigen-decomposition of the preconditioner failed");
     std::vector<double> VxT(Vx.size()), VyT(Vy.size());
     for (int i = 0; i < nx; ++i)
@@ -1333,6 +1354,7 @@ void mgrit_default_options(mgrit_options* o) {
     o->graphs = 0;
     o->op = MGRIT_OP_AUTO;
     o->coarse_relax = -1;
+    o->element = MGRIT_ELEMENT_P1;
 }
 
 const char* mgrit_last_error(void) { return g_err; }
@@ -1367,6 +1389,7 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
     if (o.op < MGRIT_OP_AUTO || o.op > MGRIT_OP_FFT) return fail(MGRIT_EINVAL, "unknown operator kind");
     if (o.coarse_relax != -1 && o.coarse_relax != MGRIT_RELAX_F && o.coarse_relax != MGRIT_RELAX_FCF)
         return fail(MGRIT_EINVAL, "unknown coarse relaxation");
+    if (o.element != MGRIT_ELEMENT_P1 && o.element != MGRIT_ELEMENT_Q1) return fail(MGRIT_EINVAL, "unknown element");
     if (o.precond < MGRIT_PRECOND_NONE || o.precond > MGRIT_PRECOND_FD_BF16)
         return fail(MGRIT_EINVAL, "unknown preconditioner");
     if (!(o.cg_rtol_coarse >= 0.0 && o.cg_rtol_coarse < 1.0)) return fail(MGRIT_EINVAL, "bad cg_rtol_coarse");
@@ -1416,7 +1439,9 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
     h->nop = h->use_fft ? (int)((nx + MGRIT_FFT_LINES - 1) / MGRIT_FFT_LINES) : g.ntiles[1];
     g.seq_off_x = g.tiles_x[0] * 64 + 64 + MGRIT_KC;
     g.seq_off_y = g.tiles_y[0] * 64 + 64 + MGRIT_KC;
-    g.mass = ((p.b - p.a) / p.Mx) * ((p.d - p.c) / p.My) / 12.0;
+    g.q1 = o.element == MGRIT_ELEMENT_Q1 ? 1 : 0;
+    g.pad_ = 0;
+    g.mass = ((p.b - p.a) / p.Mx) * ((p.d - p.c) / p.My) / (g.q1 ? 36.0 : 12.0);
     int rc = build_sequences(h);
     if (!rc && h->use_fft) rc = build_fft_plan(h);
     if (!rc && o.precond != MGRIT_PRECOND_NONE) rc = build_fd(h);

@@ -51,7 +51,10 @@ typedef struct {
     int pmax;                   // partial sums stored per slice
     long long stride;           // doubles per slice = nx * ny
     int seq_off_x, seq_off_y;   // index of distance 0 in the padded sequence arrays
-    double mass;                // h_x h_y / 12
+    double mass;                // h_x h_y / 12 (P1) or h_x h_y / 36 (Q1)
+    int q1;                     // mass stencil: 0 the 7-point P1 stencil (6; 1 on the x, y and
+                                // (+1,+1), (-1,-1) neighbours), 1 the 9-point Q1 one (16; 4; 1)
+    int pad_;
 } Geom;
 
 // Padded generating sequences on the device, already multiplied by K c:
@@ -122,6 +125,7 @@ double mgrit_stiffness_scale(double rho, double h_par, double h_perp);
 // Fast-diagonalisation preconditioner set-up (fd_setup.cpp).
 double mgrit_fd_stiffness_entry(double rho, double h, double K, int l);
 int mgrit_fd_eigen(double rho, int n, double h, double K, double* V, double* lambda);
+int mgrit_fd_eigen_consistent(double rho, int n, double h, double K, double* V, double* lambda);
 
 // Kernel launchers (kernels.hip).  All return a hipError_t as int.  `tv`
 // selects the operator/preconditioner tile edge (0: 64, 1: 32).  Partial-sum

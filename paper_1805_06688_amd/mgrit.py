@@ -21,6 +21,7 @@ PRECISION = {"fp64": 0, "mixed": 1, "mixed-coarse": 2, "mixed-bf16": 3}
 PRECOND = {"none": 0, "fd": 1, "fd-bf16": 2}
 TILE = {"auto": 0, "rule": 1, "64": 2, "32": 3}
 OPERATOR = {"auto": 0, "dense": 1, "fft": 2}
+ELEMENT = {"p1": 0, "q1": 1}
 
 
 class _Problem(ctypes.Structure):
@@ -38,7 +39,8 @@ class _Options(ctypes.Structure):
                 ("warm_start", ctypes.c_int),
                 ("divergence_factor", ctypes.c_double), ("tile_policy", ctypes.c_int),
                 ("cg_rtol_coarse", ctypes.c_double), ("inner_rtol", ctypes.c_double),
-                ("graphs", ctypes.c_int), ("op", ctypes.c_int), ("coarse_relax", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("op", ctypes.c_int), ("coarse_relax", ctypes.c_int),
+                ("element", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -60,7 +62,8 @@ SYMBOLS = ("mgrit_default_options", "mgrit_setup", "mgrit_solve", "mgrit_iterate
            "mgrit_propagate", "mgrit_apply", "mgrit_apply_noalloc", "mgrit_apply_f32", "mgrit_rhs_f32", "mgrit_residual_f32",
            "mgrit_sequences", "mgrit_levels", "mgrit_destroy",
            "mgrit_last_error", "mgrit_toeplitz_sequences", "mgrit_stiffness_scale", "mgrit_profile_enable",
-           "mgrit_profile_read", "mgrit_fd_stiffness_entry", "mgrit_fd_eigen", "mgrit_footprint",
+           "mgrit_profile_read", "mgrit_fd_stiffness_entry", "mgrit_fd_eigen", "mgrit_fd_eigen_consistent",
+           "mgrit_footprint",
            "mgrit_device_bytes", "mgrit_server_create", "mgrit_server_submit", "mgrit_server_wait",
            "mgrit_server_poll", "mgrit_server_destroy")
 
@@ -113,6 +116,8 @@ def load_library(path=_LIB_PATH):
     lib.mgrit_fd_stiffness_entry.restype = c_dbl
     lib.mgrit_fd_eigen.argtypes = [c_dbl, c_int, c_dbl, c_dbl, ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl)]
     lib.mgrit_fd_eigen.restype = c_int
+    lib.mgrit_fd_eigen_consistent.argtypes = lib.mgrit_fd_eigen.argtypes
+    lib.mgrit_fd_eigen_consistent.restype = c_int
     lib.mgrit_footprint.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Options), c_int,
                                     ctypes.POINTER(ctypes.c_size_t)]
     lib.mgrit_footprint.restype = c_int
@@ -196,12 +201,14 @@ def fd_stiffness_entry(rho, h, K, l):
     return _lib.mgrit_fd_stiffness_entry(float(rho), float(h), float(K), int(l))
 
 
-def fd_eigen(rho, n, h, K):
-    """Generalised eigenpairs of the 1-D (K, M) pair of the preconditioner: (V [n, n], lambda [n])."""
+def fd_eigen(rho, n, h, K, consistent=False):
+    """Generalised eigenpairs of the 1-D (K, M) pair of the preconditioner: (V [n, n], lambda [n]); M = h I, or
+    h/6 tridiag(1, 4, 1) with consistent=True."""
     V = np.empty((n, n))
     lam = np.empty(n)
     dp = ctypes.POINTER(ctypes.c_double)
-    rc = _lib.mgrit_fd_eigen(float(rho), int(n), float(h), float(K), V.ctypes.data_as(dp), lam.ctypes.data_as(dp))
+    fn = _lib.mgrit_fd_eigen_consistent if consistent else _lib.mgrit_fd_eigen
+    rc = fn(float(rho), int(n), float(h), float(K), V.ctypes.data_as(dp), lam.ctypes.data_as(dp))
     if rc != 0:
         raise MgritError(rc, "eigen-iteration failed")
     return V, lam
@@ -224,8 +231,9 @@ def make_problem(beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0)):
 def make_options(m=8, max_levels=30, relax="FCF", coarse="cn", precision="fp64", max_iter=100, tol_abs=1e-9,
                  tol_rel=0.0, cg_rtol=1e-9, cg_maxit=10000, precond="none", cg_rtol_adapt=0.0, warm_start=True,
                  divergence_factor=0.0, tile="auto", cg_rtol_coarse=0.0, inner_rtol=0.0, graphs=False,
-                 op="auto", coarse_relax=None):
+                 op="auto", coarse_relax=None, element="p1"):
     o = default_options()
+    o.element = ELEMENT[element]
     o.coarse_relax = -1 if coarse_relax is None else RELAX[coarse_relax]
     o.op = OPERATOR[op]
     o.graphs = 1 if graphs else 0

@@ -136,3 +136,19 @@ def test_server_rejects_bad_arguments_without_gpu_work():
         mg.Server(0, 1)
     with pytest.raises(mg.MgritError):
         mg.Server(1 << 20, 0)
+
+
+@pytest.mark.parametrize("rho,n,h,K", [(0.75, 255, 1 / 256, 2.0), (0.6, 40, 0.025, 1.0), (0.8, 1, 0.5, 1.0)])
+def test_fd_eigen_consistent_matches_q1_oracle(rho, n, h, K):
+    """The exact inverse of the bilinear step matrix: generalised eigenpairs of the oracle's 1-D stiffness and
+    consistent mass h/6 tridiag(1, 4, 1) (oracle/q1.py) equal scipy's eigh, V^T M V = I."""
+    import scipy.linalg as sl
+    from oracle import q1
+    mg = _lib()
+    V, lam = mg.fd_eigen(rho, n, h, K, consistent=True)
+    Kd = K * q1.stiffness_1d(rho, n, h)
+    M = q1.mass_1d(n, h)
+    ref = sl.eigh(Kd, M, eigvals_only=True)
+    assert np.allclose(np.sort(lam), ref, rtol=1e-11, atol=1e-12 * ref.max())
+    assert np.abs(V.T @ M @ V - np.eye(n)).max() < 1e-12
+    assert np.abs(V.T @ Kd @ V - np.diag(lam)).max() < 1e-11 * np.abs(lam).max()
