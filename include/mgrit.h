@@ -209,6 +209,32 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
 int mgrit_solve(mgrit_handle* h, const double* F, const double* psi0, const double* U_init,
                 double* U, int mem, mgrit_stats* st);
 
+/* Several independent problems on one mesh solved together: probs[0..nprob)
+ * share Mx, My and the domain and take the same options; each has its own
+ * beta, gamma, K_x, K_y, time grid and N_t (all must give the same number of
+ * levels; cg_rtol_adapt must be 0).  Every sweep of a level (each F- and
+ * C-relaxation step, the C-point residual, each coarse step) gathers the
+ * slices of all problems still iterating into one set of kernel launches.
+ * Each problem stops on its own test (tolerances as in mgrit_solve) and leaves
+ * the batches; every slice is computed as it would be alone, so a problem's
+ * result equals its own mgrit_solve (bitwise, except that with FD_BF16 the
+ * preconditioner chooses its small-batch kernel by the batch width, which
+ * changes the rounding).  The handle owns a copy of all problems' loads and
+ * states (the footprint grows by sum (2 N_t + 1) n_x n_y doubles).
+ * Errors: EINVAL (as mgrit_setup, or meshes, domains or level counts that
+ * differ), ENOMEM, EHIP. */
+int mgrit_setup_group(const mgrit_problem* probs, int nprob, const mgrit_options* opt, void* stream,
+                      mgrit_handle** out);
+
+/* Solve every problem of a group handle.  F[p] (may be NULL, or F itself NULL:
+ * zero loads), psi0[p] and U[p] as in mgrit_solve for problem p, all in the
+ * memory space `mem`; st: nprob stats (may be NULL): iterations, converged and
+ * residual_history per problem, phi_applications, cg_iterations and
+ * refinements of the whole group.  Returns OK when all converged, EDIVERGED
+ * when one diverged, else ENOCONV; every U[p] is written. */
+int mgrit_solve_group(mgrit_handle* h, const double* const* F, const double* const* psi0, double* const* U,
+                      int mem, mgrit_stats* st);
+
 /* Exactly `iterations` MGRIT iterations (relaxation, C-point residual, coarse
  * solve, C-point correction) followed by a final F-relaxation, with no stop
  * test: the iterate the algorithm has after that many steps.  Arguments as in

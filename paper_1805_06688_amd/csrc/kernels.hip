@@ -105,6 +105,18 @@ __device__ __forceinline__ void decode_block(int ntiles, int S, int& s, int& til
 
 inline int grid_blocks(int ntiles, int S) { return S < 8 ? ntiles * S : ntiles * ((S + 7) / 8) * 8; }
 
+// The tables of problem p of a batch of several problems (Geom strides; p = 0 for one problem).
+template <typename S>
+__device__ __forceinline__ S seqs_of(const S& sq, const Geom& g, int p) {
+    S r = sq;
+    const long long o = (long long)p * g.ps_seq;
+    r.T1x += o;
+    r.A2x += o;
+    r.T1y += o;
+    r.A2y += o;
+    return r;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -339,7 +351,7 @@ __global__ __launch_bounds__(NT) void k_apply(Geom g, Seqs sq, const ApplyDesc* 
 // mode 1: initial residual r = b - (M x + theta_lhs A x), partial ||r||^2 (ubase = x base)
 // mode 2: q = M p + theta_lhs A p (active slices), partial p.q
 template <int TT, int MODE>
-__global__ __launch_bounds__(NT) void k_prop_apply(Geom g, Seqs sq, const PropDesc* __restrict__ desc, int S,
+__global__ __launch_bounds__(NT) void k_prop_apply(Geom g, Seqs sq0, const PropDesc* __restrict__ desc, int S,
                                                    const double* ubase, const double* fbase, const double* wsin,
                                                    double* wsout, double* partial, const int* active) {
     const int tv = TT == 64 ? 0 : 1;
@@ -352,6 +364,7 @@ __global__ __launch_bounds__(NT) void k_prop_apply(Geom g, Seqs sq, const PropDe
     const PropDesc d = desc[s];
     const long long so = (long long)s * g.stride;
     double* part = partial + (long long)s * g.pmax;
+    const Seqs sq = seqs_of(sq0, g, d.prob);
     if (MODE == 0) {
         const double* f = (fbase && d.f >= 0) ? fbase + d.f * g.stride : nullptr;
         apply_tile<TT, double>(g, sq, ubase + d.u * g.stride, wsout + so, f, d.theta_rhs, 1.0, 2, tile, lds, red, part);
@@ -396,8 +409,9 @@ __global__ __launch_bounds__(NT) void k_apply32(Geom g, Seqs32 sq, const PropDes
     __shared__ float lds[TC<TT>::LDS];
     __shared__ double red[4];
     const long long so = (long long)s * g.stride;
-    apply_tile<TT, float>(g, sq, pws + so, qws + so, nullptr, desc[s].theta_lhs, 1.0, 1, tile, lds, red,
-                          partial + (long long)s * g.pmax);
+    const PropDesc d = desc[s];
+    apply_tile<TT, float>(g, seqs_of(sq, g, d.prob), pws + so, qws + so, nullptr, d.theta_lhs, 1.0, 1, tile, lds,
+                          red, partial + (long long)s * g.pmax);
 }
 
 // q32 = M p32 + theta_lhs A p32 with the Toeplitz products in BF16 on the matrix cores
@@ -432,7 +446,7 @@ __device__ __forceinline__ unsigned int split_pair(float x0, float x1, unsigned 
            ((unsigned int)__builtin_bit_cast(unsigned short, h1) << 16);
 }
 
-__global__ __launch_bounds__(NT) void k_apply_bf16(Geom g, Seqs32 sq, const PropDesc* __restrict__ desc, int S,
+__global__ __launch_bounds__(NT) void k_apply_bf16(Geom g, Seqs32 sq0, const PropDesc* __restrict__ desc, int S,
                                                    const float* pws, float* qws, double* partial,
                                                    const int* active) {
     using namespace obf;
@@ -440,6 +454,7 @@ __global__ __launch_bounds__(NT) void k_apply_bf16(Geom g, Seqs32 sq, const Prop
     decode_block(g.ntiles[0], S, s, tile);
     if (s < 0) return;
     if (active && !active[s]) return;
+    const Seqs32 sq = seqs_of(sq0, g, desc[s].prob);
     __shared__ __attribute__((aligned(16))) unsigned char raw[BYTES];
     __shared__ double red[4];
     __bf16* Shi = (__bf16*)raw;                      // strip [row][k]
@@ -590,7 +605,8 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
                                                  const double* partial_rr, int np, double rtol2, double eta_min2,
                                                  int first, double* bb, double* scale, double* eta2, int* oact,
                                                  int* iact, int* iters, float* r32, float* d32, float* p32,
-                                                 double* partial_rr32, int* host_act, int* host_iters) {
+                                                 double* partial_rr32, int* host_act, int* host_iters,
+                                                 const int* trust_in, int* trust_out) {
     int s, c;
     decode_block(g.nchunk, S, s, c);
     if (s < 0) return;
@@ -598,7 +614,10 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
     const double b2 = slice_sum(partial_bb, g.pmax, s, np);
     const double r2 = slice_sum(partial_rr, g.pmax, s, np);
     const bool zero = !(b2 > 0.0);
-    const bool active = !zero && r2 > rtol2 * b2;
+    // a slice whose previous step was settled by its own inner test is done, whatever the other slices of
+    // the batch need (so that each slice's result does not depend on the batch)
+    const bool settled = !first && trust_in[s];
+    const bool active = !settled && !zero && r2 > rtol2 * b2;
     const long long so = (long long)s * g.stride;
     long long lo, hi;
     chunk_range(g, c, lo, hi);
@@ -630,6 +649,7 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
         // inner solve's own test settles the slice (see the refinement loop)
         const int flag = active ? (e2 >= 1e2 * eta_min2 ? 2 : 1) : 0;
         iact[s] = flag;
+        trust_out[s] = (settled || flag == 2) ? 1 : 0;
         if (host_act) host_act[s] = flag;
         scale[s] = active ? sqrt(r2) : 0.0;
         eta2[s] = e2;
@@ -909,6 +929,12 @@ __global__ __launch_bounds__(NT) void k_fd_gemm(Geom g, int S, const double* __r
     decode_block(g.ntiles[tv], S, s, tile);
     if (s < 0) return;
     if (active && !active[s]) return;
+    {
+        const long long o = (long long)desc[s].prob * g.ps_fd;
+        mat += o;
+        lx += o;
+        ly += o;
+    }
     __shared__ double lds[C::FD_LDS];
     __shared__ double red[4];
     const int nx = g.nx, ny = g.ny;
@@ -1043,6 +1069,12 @@ __global__ __launch_bounds__(NT, EPI == 2 ? 8 : 1) void k_fdb_gemm(Geom g, int S
     decode_block(g.ntiles[0], S, s, tile);
     if (s < 0) return;
     if (active && !active[s]) return;
+    {
+        const int pr = desc[s].prob;
+        mat += (long long)pr * g.ps_fdb;
+        lx += (long long)pr * g.ps_fde;
+        ly += (long long)pr * g.ps_fde;
+    }
     __shared__ __attribute__((aligned(16))) unsigned char raw[2 * 64 * BLD * 2 > 64 * 65 * 4 ? 2 * 64 * BLD * 2
                                                                                               : 64 * 65 * 4];
     __shared__ double red[4];
@@ -1210,6 +1242,12 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm32(Geom g, int S, const __bf16* 
     decode_block(tx * ty, S, s, tile);
     if (s < 0) return;
     if (active && !active[s]) return;
+    {
+        const int pr = desc[s].prob;
+        mat += (long long)pr * g.ps_fdb;
+        lx += (long long)pr * g.ps_fde;
+        ly += (long long)pr * g.ps_fde;
+    }
     __shared__ __attribute__((aligned(16))) unsigned char raw[2 * 32 * SLD * 2 > 4 * 32 * 33 * 4 ? 2 * 32 * SLD * 2
                                                                                                  : 4 * 32 * 33 * 4];
     __shared__ double red[4];
@@ -1559,7 +1597,7 @@ __device__ __forceinline__ double block_sum8(double v, double* red) {
 template <typename T, typename TV, typename TA, int MODE>
 __device__ __forceinline__ void fft_operands(const Geom& g, const void* desc, int s, const TV* vbase,
                                              const void* wsin, const TA* addbase, T* outbase, const TV*& v,
-                                             const TA*& add, T*& out, double& theta) {
+                                             const TA*& add, T*& out, double& theta, int& prob) {
     const long long so = (long long)s * g.stride;
     if (MODE == 3) {
         const ApplyDesc d = ((const ApplyDesc*)desc)[s];
@@ -1567,9 +1605,11 @@ __device__ __forceinline__ void fft_operands(const Geom& g, const void* desc, in
         add = (addbase && d.add >= 0) ? addbase + d.add * g.stride : nullptr;
         out = outbase + d.out * g.stride;
         theta = d.theta;
+        prob = 0;
         return;
     }
     const PropDesc d = ((const PropDesc*)desc)[s];
+    prob = d.prob;
     if (MODE == 0) {
         v = vbase + d.u * g.stride;
         add = (addbase && d.f >= 0) ? addbase + d.f * g.stride : nullptr;
@@ -1605,7 +1645,8 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
     const TA* add;
     T* out;
     double theta_d;
-    fft_operands<T, TV, TA, MODE>(g, desc, s, vbase, wsin, addbase, outbase, v, add, out, theta_d);
+    int prob;
+    fft_operands<T, TV, TA, MODE>(g, desc, s, vbase, wsin, addbase, outbase, v, add, out, theta_d, prob);
     const T theta = (T)theta_d;
     const T sign = (T)sign_d;
     constexpr int FE = FftLen<L>::FE;
@@ -1616,8 +1657,9 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
     const int l0 = blk * FJ;                 // first output line
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const cpx<T>* tw = (const cpx<T>*)(sizeof(T) == 8 ? (const void*)pl.tw : (const void*)pl.tw32);
-    const cpx<T>* K = (const cpx<T>*)(sizeof(T) == 8 ? (const void*)(DIR == 0 ? pl.kx : pl.ky)
-                                                      : (const void*)(DIR == 0 ? pl.kx32 : pl.ky32));
+    const long long kof = (long long)prob * g.ps_spec;
+    const cpx<T>* K = (const cpx<T>*)(sizeof(T) == 8 ? (const void*)((DIR == 0 ? pl.kx : pl.ky) + kof)
+                                                      : (const void*)((DIR == 0 ? pl.kx32 : pl.ky32) + kof));
     cpx<T>* buf = lds + wave * FPAD;
     // FP32, 512 points: the kernel spectra and twiddles (4 x 512 values) are staged in LDS; their
     // loads are issued together with those of the lines, so the combination step waits for nothing
@@ -2041,17 +2083,17 @@ int launch_mx_begin(const Geom* g, const PropDesc* desc, int S, double* xbase, c
                     const double* partial_bb, const double* partial_rr, int np, double rtol2, double eta_min2,
                     int first, double* bb, double* scale, double* eta2, int* oact, int* iact, int* iters, float* r32,
                     float* d32, float* p32, double* partial_rr32, int* host_act, int* host_iters,
-                    void* stream) {
+                    const int* trust_in, int* trust_out, void* stream) {
     if (S <= 0) return 0;
     const dim3 grid(grid_blocks(g->nchunk, S)), blk(NT);
     if (rws)
         hipLaunchKernelGGL(k_mx_begin<double>, grid, blk, 0, (hipStream_t)stream, *g, desc, S, xbase, rws,
                            partial_bb, partial_rr, np, rtol2, eta_min2, first, bb, scale, eta2, oact, iact, iters, r32,
-                           d32, p32, partial_rr32, host_act, host_iters);
+                           d32, p32, partial_rr32, host_act, host_iters, trust_in, trust_out);
     else
         hipLaunchKernelGGL(k_mx_begin<float>, grid, blk, 0, (hipStream_t)stream, *g, desc, S, xbase,
                            (const float*)r32, partial_bb, partial_rr, np, rtol2, eta_min2, first, bb, scale, eta2,
-                           oact, iact, iters, r32, d32, p32, partial_rr32, host_act, host_iters);
+                           oact, iact, iters, r32, d32, p32, partial_rr32, host_act, host_iters, trust_in, trust_out);
     return (int)hipGetLastError();
 }
 

@@ -87,27 +87,50 @@ struct IndexPair {           // y[yi[s]] (+)= a x[xi[s]]
     int* xi = nullptr;
 };
 
+// One problem of a handle: its statement, time grid and level hierarchy, and where its slices sit in
+// the state arrays the handle's batches index.  A handle set up by mgrit_setup has one member; one set
+// up by mgrit_setup_group has several on one mesh, whose sweeps share the batches of every level.
+struct Member {
+    mgrit_problem prob{};
+    std::vector<double> t;
+    std::vector<int> N;                       // intervals per level
+    std::vector<std::vector<int>> fine;       // level-0 index of each point, per level
+    std::vector<std::vector<double>> tau;     // tau[l][k], k = 1..N[l]
+    std::vector<long long> off;               // first slice of the member in each level's state
+    long long f_off = 0;                      // first load slice of the member in the level-0 loads
+    std::vector<double> seq_x, seq_y;         // host generating sequences, scaled (as the device uses them)
+};
+
+// A level of the hierarchy over all members: batches gather the slices of the members that are still
+// iterating, in member order.
 struct Level {
-    int N = 0;                       // intervals
-    std::vector<int> fine;           // level-0 index of each point
-    std::vector<double> tau;         // tau[k], k = 1..N
-    double* U = nullptr;             // [N+1] slices (levels >= 1; level 0 uses the caller's array)
-    double* G = nullptr;             // [N+1] slices (levels >= 1)
+    int N = 0;                       // intervals (the most of any member)
+    long long ns = 0;                // slices of the level's state, all members
+    double* U = nullptr;             // [ns] slices (levels >= 1; level 0 uses U0)
+    double* G = nullptr;             // [ns] slices (levels >= 1)
     std::vector<Batch> frelax;       // F-relaxation, one batch per F sub-step
     Batch crelax;                    // C-relaxation
     Batch resid;                     // residual propagation into the next level's G
-    std::vector<Batch> step_list;    // per-step batches of one slice (coarsest level / sequential)
+    std::vector<Batch> step_list;    // per-step batches (coarsest level / sequential stepping)
     IndexPair correct;               // U[km] += E[k]
     IndexPair subtract;              // Gnext[k] -= U[km]
-    int* all_idx = nullptr;          // 0..N (zeroing)
+    std::vector<int> sub_count;      // subtract pairs of each batched member (per-member norms)
+    int* all_idx = nullptr;          // 0..ns-1 (zeroing)
+    int* first_idx = nullptr;        // first slice of every member (E_0 = 0, G_0 = 0)
+    int nfirst = 0;
 };
 
 }  // namespace
 
 struct mgrit_handle {
-    mgrit_problem prob;
+    mgrit_problem prob;                      // the first member's (mesh and domain are common)
     mgrit_options opt;
-    std::vector<double> t;
+    std::vector<double> t;                   // the first member's time grid
+    std::vector<Member> mem;                 // the problems (one unless set up as a group)
+    std::vector<char> batched;               // members whose slices the current batches hold
+    std::vector<void*> batch_allocs;         // device descriptors of the current batches
+    double* gU = nullptr;                    // groups: level-0 state and loads of all members
+    double* gF = nullptr;
     hipStream_t stream = nullptr;
     int device = 0;                          // device current at set-up
     void* scratch = nullptr;                 // device address of that device's scratch array
@@ -140,6 +163,7 @@ struct mgrit_handle {
     float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
     double *mx_scale = nullptr, *mx_eta2 = nullptr, *pout = nullptr;
     int* mx_oact = nullptr;
+    int* mx_trust = nullptr;                 // 2 x Smax: settled slices of a refinement step (parity buffers)
     long long refine_count = 0;             // refinement steps summed over slices
     int* act[2] = {nullptr, nullptr};
     int* iters = nullptr;
@@ -226,10 +250,19 @@ int dalloc(mgrit_handle* h, T** p, size_t count) {
     return dmalloc(h, (void**)p, count * sizeof(T));
 }
 
+// Device memory of the current batches (descriptors, index pairs): freed when the batches are rebuilt.
+int batch_alloc(mgrit_handle* h, void** p, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return alloc_failed(e, bytes);
+    h->batch_allocs.push_back(*p);
+    return 0;
+}
+
 int upload_pass(mgrit_handle* h, Pass& ps) {
     ps.S = (int)ps.h.size();
     if (ps.S == 0) return 0;
-    CHK(dalloc(h, &ps.d, ps.h.size()));
+    CHK(batch_alloc(h, (void**)&ps.d, ps.h.size() * sizeof(PropDesc)));
     HIPCHK(hipMemcpy(ps.d, ps.h.data(), ps.h.size() * sizeof(PropDesc), hipMemcpyHostToDevice));
     return 0;
 }
@@ -237,34 +270,36 @@ int upload_pass(mgrit_handle* h, Pass& ps) {
 int upload_pairs(mgrit_handle* h, IndexPair& ip, const std::vector<int>& y, const std::vector<int>& x) {
     ip.S = (int)y.size();
     if (ip.S == 0) return 0;
-    CHK(dalloc(h, &ip.yi, y.size()));
-    CHK(dalloc(h, &ip.xi, x.size()));
+    CHK(batch_alloc(h, (void**)&ip.yi, y.size() * sizeof(int)));
+    CHK(batch_alloc(h, (void**)&ip.xi, x.size() * sizeof(int)));
     HIPCHK(hipMemcpy(ip.yi, y.data(), y.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ip.xi, x.data(), x.size() * sizeof(int), hipMemcpyHostToDevice));
     return 0;
 }
 
-// Descriptor of one application of the level-l propagator from point k-1 to k,
-// reading slice `u`, writing slice `x`; x0 is the slice of the level's state
-// that holds the previous value of point k (-1: none).  One or two passes.
-void make_step(const mgrit_handle* h, int l, int k, int u, int x, int tmp_slot, Batch& b, int x0 = -1) {
-    const double tau = h->lv[l].tau[k];
+// Descriptor of one application of member p's level-l propagator from point k-1 to k, reading slice `u`
+// and writing slice `x` of the level's state (indices include the member's offset); x0 is the slice that
+// holds the previous value of point k (-1: none).  The loads (level 0) and affine terms (levels >= 1) are
+// the member's own.  One or two passes.
+void make_step(const mgrit_handle* h, int p, int l, int k, int u, int x, int tmp_slot, Batch& b, int x0 = -1) {
+    const Member& M = h->mem[p];
+    const double tau = M.tau[l][k];
     PropDesc d;
     d.u = u;
     d.x = x;
     d.f = -1;
     d.g = -1;
     d.x0 = x0;
-    d.pad_ = 0;
+    d.prob = p;
     if (l == 0) {
-        d.f = k - 1;                   // load F_k
+        d.f = (int)(M.f_off + k - 1);  // load F_k
         d.theta_rhs = -0.5 * tau;
         d.theta_lhs = 0.5 * tau;
         b.pass[0].h.push_back(d);
         b.npass = 1;
         return;
     }
-    d.g = k;                            // affine term G^(l)_k
+    d.g = (int)(M.off[l] + k);          // affine term G^(l)_k
     if (h->opt.coarse == MGRIT_COARSE_BE) {
         d.theta_rhs = 0.0;
         d.theta_lhs = tau;
@@ -275,9 +310,9 @@ void make_step(const mgrit_handle* h, int l, int k, int u, int x, int tmp_slot, 
         if (h->opt.coarse == MGRIT_COARSE_OPT) {
             // Match the product of the level-0 Crank-Nicolson factors inside
             // this coarse step at small and at large tau~ sigma.
-            const int i0 = h->lv[l].fine[k - 1], i1 = h->lv[l].fine[k];
+            const int i0 = M.fine[l][k - 1], i1 = M.fine[l][k];
             double inv = 0.0;
-            for (int n = i0 + 1; n <= i1; ++n) inv += 1.0 / (h->t[n] - h->t[n - 1]);
+            for (int n = i0 + 1; n <= i1; ++n) inv += 1.0 / (M.t[n] - M.t[n - 1]);
             const double c = 4.0 * tau * inv;
             const double dd = std::sqrt(c * c / 16.0 - c);
             const double a1 = c / 4.0 + dd, a2 = c / 4.0 - dd;
@@ -309,154 +344,248 @@ int upload_batch(mgrit_handle* h, Batch& b) {
     return 0;
 }
 
-int build_levels(mgrit_handle* h) {
+// Level hierarchy of one member (Section 3.1): t^(l+1) = t^(l)[::m] while the coarse grid keeps at
+// least two intervals, at most max_levels levels.
+void member_levels(const mgrit_handle* h, Member& M) {
     const int m = h->opt.m;
-    const int Nt = h->prob.Nt;
-    h->lv.clear();
-    Level l0;
-    l0.N = Nt;
-    l0.fine.resize(Nt + 1);
-    for (int i = 0; i <= Nt; ++i) l0.fine[i] = i;
-    h->lv.push_back(l0);
-    while ((int)h->lv.size() < h->opt.max_levels) {
-        const Level& pr = h->lv.back();
-        const int Nc = pr.N / m;
+    M.N.assign(1, M.prob.Nt);
+    M.fine.assign(1, std::vector<int>(M.prob.Nt + 1));
+    for (int i = 0; i <= M.prob.Nt; ++i) M.fine[0][i] = i;
+    while ((int)M.N.size() < h->opt.max_levels) {
+        const int Nc = M.N.back() / m;
         if (Nc < 2) break;
-        Level nl;
-        nl.N = Nc;
-        nl.fine.resize(Nc + 1);
-        for (int k = 0; k <= Nc; ++k) nl.fine[k] = pr.fine[k * m];
-        h->lv.push_back(nl);
+        std::vector<int> f(Nc + 1);
+        for (int k = 0; k <= Nc; ++k) f[k] = M.fine.back()[k * m];
+        M.N.push_back(Nc);
+        M.fine.push_back(f);
     }
-    if (h->lv.size() < 2) return fail(MGRIT_EINVAL, "time grid too short for one coarsening (Nt=%d, m=%d)", Nt, m);
-    for (Level& L : h->lv) {
-        L.tau.assign(L.N + 1, 0.0);
-        for (int k = 1; k <= L.N; ++k) L.tau[k] = h->t[L.fine[k]] - h->t[L.fine[k - 1]];
+    M.tau.assign(M.N.size(), std::vector<double>());
+    for (size_t l = 0; l < M.N.size(); ++l) {
+        M.tau[l].assign(M.N[l] + 1, 0.0);
+        for (int k = 1; k <= M.N[l]; ++k) M.tau[l][k] = M.t[M.fine[l][k]] - M.t[M.fine[l][k - 1]];
     }
-    // batches
-    int smax = 1;
+}
+
+// (Re)build every level's batches over the members marked in h->batched, in member order: the slices
+// of all of them go into one set of launches per relaxation step, residual and coarse step.  *smax: the
+// largest batch.
+int build_batches(mgrit_handle* h, int* smax_out = nullptr) {
+    if (!h->batch_allocs.empty()) {
+        HIPCHK(hipStreamSynchronize(h->stream));         // nothing queued still reads the old batches
+        for (void* q : h->batch_allocs) (void)hipFree(q);
+        h->batch_allocs.clear();
+    }
+    const int m = h->opt.m;
     const int nl = (int)h->lv.size();
+    const int P = (int)h->mem.size();
+    int smax = 1;
     for (int l = 0; l < nl; ++l) {
         Level& L = h->lv[l];
+        L.frelax.clear();
+        L.crelax = Batch();
+        L.resid = Batch();
+        L.step_list.clear();
+        L.correct = IndexPair();
+        L.subtract = IndexPair();
+        L.sub_count.clear();
         const bool coarsest = (l == nl - 1);
         if (!coarsest) {
-            const int Nc = h->lv[l + 1].N;
             L.frelax.assign(m - 1, Batch());
             for (int j = 1; j < m; ++j) {
                 Batch& b = L.frelax[j - 1];
                 int slot = 0;
-                for (int c = 0; c + j <= L.N; c += m) make_step(h, l, c + j, c + j - 1, c + j, slot++, b, c + j);
+                for (int p = 0; p < P; ++p) {
+                    if (!h->batched[p]) continue;
+                    const Member& M = h->mem[p];
+                    const int o = (int)M.off[l];
+                    for (int c = 0; c + j <= M.N[l]; c += m)
+                        make_step(h, p, l, c + j, o + c + j - 1, o + c + j, slot++, b, o + c + j);
+                }
                 smax = std::max(smax, (int)b.pass[0].h.size());
             }
-            int slot = 0;
-            for (int k = 1; k <= Nc; ++k) make_step(h, l, k * m, k * m - 1, k * m, slot++, L.crelax, k * m);
-            slot = 0;
-            for (int k = 1; k <= Nc; ++k) make_step(h, l, k * m, k * m - 1, k, slot++, L.resid, k * m);
-            smax = std::max(smax, Nc);
-            std::vector<int> y, x;
-            for (int k = 0; k <= Nc; ++k) {
-                y.push_back(k * m);
-                x.push_back(k);
+            int slot = 0, slot2 = 0;
+            std::vector<int> y, x, y2, x2;
+            for (int p = 0; p < P; ++p) {
+                if (!h->batched[p]) continue;
+                const Member& M = h->mem[p];
+                const int o = (int)M.off[l], oc = (int)M.off[l + 1], Nc = M.N[l + 1];
+                for (int k = 1; k <= Nc; ++k) make_step(h, p, l, k * m, o + k * m - 1, o + k * m, slot++, L.crelax, o + k * m);
+                for (int k = 1; k <= Nc; ++k) make_step(h, p, l, k * m, o + k * m - 1, oc + k, slot2++, L.resid, o + k * m);
+                for (int k = 0; k <= Nc; ++k) {
+                    y.push_back(o + k * m);
+                    x.push_back(oc + k);
+                }
+                for (int k = 1; k <= Nc; ++k) {
+                    y2.push_back(oc + k);
+                    x2.push_back(o + k * m);
+                }
+                L.sub_count.push_back(Nc);
             }
+            smax = std::max(smax, slot);
             CHK(upload_pairs(h, L.correct, y, x));
-            std::vector<int> y2, x2;
-            for (int k = 1; k <= Nc; ++k) {
-                y2.push_back(k);
-                x2.push_back(k * m);
-            }
             CHK(upload_pairs(h, L.subtract, y2, x2));
+            for (Batch& b : L.frelax) CHK(upload_batch(h, b));
+            CHK(upload_batch(h, L.crelax));
+            CHK(upload_batch(h, L.resid));
         }
-        // single-step batches: for the coarsest level (E_k = Phi(E_k-1)) and for
-        // sequential stepping on level 0
+        // single-step batches: for the coarsest level (E_k = Phi(E_k-1)) and for sequential stepping on
+        // level 0: step k of every member that has it
         if (coarsest || l == 0) {
-            L.step_list.assign(L.N, Batch());
-            for (int k = 1; k <= L.N; ++k) make_step(h, l, k, k - 1, k, 0, L.step_list[k - 1]);
-        }
-    }
-    h->Smax = smax;
-    for (int l = 0; l < nl; ++l) {
-        Level& L = h->lv[l];
-        for (Batch& b : L.frelax) CHK(upload_batch(h, b));
-        CHK(upload_batch(h, L.crelax));
-        CHK(upload_batch(h, L.resid));
-        if (!L.step_list.empty()) {
+            int kmax = 0;
+            for (int p = 0; p < P; ++p)
+                if (h->batched[p]) kmax = std::max(kmax, h->mem[p].N[l]);
+            L.step_list.assign(kmax, Batch());
+            for (int k = 1; k <= kmax; ++k) {
+                int slot = 0;
+                for (int p = 0; p < P; ++p) {
+                    if (!h->batched[p] || h->mem[p].N[l] < k) continue;
+                    const int o = (int)h->mem[p].off[l];
+                    make_step(h, p, l, k, o + k - 1, o + k, slot++, L.step_list[k - 1]);
+                }
+                smax = std::max(smax, slot);
+            }
             // one device array for all single-step descriptors (pass by pass)
-            const int np = L.step_list[0].npass;
+            const int np = kmax ? L.step_list[0].npass : 0;
             for (int pi = 0; pi < np; ++pi) {
                 std::vector<PropDesc> all;
-                for (Batch& b : L.step_list) all.push_back(b.pass[pi].h[0]);
+                std::vector<size_t> first;
+                for (Batch& b : L.step_list) {
+                    first.push_back(all.size());
+                    all.insert(all.end(), b.pass[pi].h.begin(), b.pass[pi].h.end());
+                }
                 PropDesc* d = nullptr;
-                CHK(dalloc(h, &d, all.size()));
+                CHK(batch_alloc(h, (void**)&d, all.size() * sizeof(PropDesc)));
                 HIPCHK(hipMemcpy(d, all.data(), all.size() * sizeof(PropDesc), hipMemcpyHostToDevice));
                 for (size_t k = 0; k < L.step_list.size(); ++k) {
-                    L.step_list[k].pass[pi].S = 1;
-                    L.step_list[k].pass[pi].d = d + k;
+                    L.step_list[k].pass[pi].S = (int)L.step_list[k].pass[pi].h.size();
+                    L.step_list[k].pass[pi].d = d + first[k];
                 }
             }
         }
-        std::vector<int> all(L.N + 1);
-        for (int i = 0; i <= L.N; ++i) all[i] = i;
-        CHK(dalloc(h, &L.all_idx, all.size()));
-        HIPCHK(hipMemcpy(L.all_idx, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice));
-        if (l > 0) {
-            CHK(dalloc(h, &L.U, (size_t)(L.N + 1) * h->geom.stride));
-            CHK(dalloc(h, &L.G, (size_t)(L.N + 1) * h->geom.stride));
-        }
     }
+    if (smax_out) *smax_out = smax;
     return 0;
 }
 
-int build_sequences(mgrit_handle* h) {
-    const mgrit_problem& p = h->prob;
+// Levels over all members: slice offsets, the level state arrays (levels >= 1) and the zeroing index
+// lists; then the batches with every member.
+int build_levels(mgrit_handle* h) {
+    const int P = (int)h->mem.size();
+    for (Member& M : h->mem) member_levels(h, M);
+    const int nl = (int)h->mem[0].N.size();
+    if (nl < 2)
+        return fail(MGRIT_EINVAL, "time grid too short for one coarsening (Nt=%d, m=%d)", h->mem[0].prob.Nt, h->opt.m);
+    for (int p = 1; p < P; ++p)
+        if ((int)h->mem[p].N.size() != nl)
+            return fail(MGRIT_EINVAL, "the problems of a group need the same number of levels (problem %d: %d, not %d)",
+                        p, (int)h->mem[p].N.size(), nl);
+    h->lv.assign(nl, Level());
+    long long f = 0;
+    for (int p = 0; p < P; ++p) {
+        h->mem[p].f_off = f;
+        f += h->mem[p].prob.Nt;
+    }
+    for (int l = 0; l < nl; ++l) {
+        Level& L = h->lv[l];
+        long long o = 0;
+        std::vector<int> first;
+        for (int p = 0; p < P; ++p) {
+            Member& M = h->mem[p];
+            M.off.resize(nl);
+            M.off[l] = o;
+            first.push_back((int)o);
+            o += M.N[l] + 1;
+            L.N = std::max(L.N, M.N[l]);
+        }
+        L.ns = o;
+        if (o >= (1LL << 31)) return fail(MGRIT_EINVAL, "too many slices in one level (%lld)", o);
+        std::vector<int> all(o);
+        for (long long i = 0; i < o; ++i) all[i] = (int)i;
+        CHK(dalloc(h, &L.all_idx, all.size()));
+        HIPCHK(hipMemcpy(L.all_idx, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice));
+        L.nfirst = P;
+        CHK(dalloc(h, &L.first_idx, first.size()));
+        HIPCHK(hipMemcpy(L.first_idx, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice));
+        if (l > 0) {
+            CHK(dalloc(h, &L.U, (size_t)o * h->geom.stride));
+            CHK(dalloc(h, &L.G, (size_t)o * h->geom.stride));
+        }
+    }
+    h->batched.assign(P, 1);
+    return build_batches(h, &h->Smax);
+}
+
+// Host generating sequences of one member, scaled as the device uses them (see mgrit_sequences).
+void member_sequences(const mgrit_handle* h, Member& M, double* cx, double* cy) {
+    const mgrit_problem& p = M.prob;
     const int nx = p.Mx - 1, ny = p.My - 1;
     const double hx = (p.b - p.a) / p.Mx, hy = (p.d - p.c) / p.My;
-    h->host_seq_x.assign(3 * (size_t)nx, 0.0);
-    h->host_seq_y.assign(3 * (size_t)ny, 0.0);
+    M.seq_x.assign(3 * (size_t)nx, 0.0);
+    M.seq_y.assign(3 * (size_t)ny, 0.0);
     if (h->opt.element == MGRIT_ELEMENT_Q1) {
         // K_x M_y (x) A_x: column j of the grid array gets (4 h_y / 6) A_x v_j + (h_y / 6) A_x (v_j+1 + v_j-1),
         // the three factors of the x contraction; likewise for y with h_x
-        h->cx = h->cy = 1.0;
+        *cx = *cy = 1.0;
         for (int l = 0; l < nx; ++l) {
             const double a = p.Kx * mgrit_fd_stiffness_entry(p.beta, hx, 1.0, l);
-            h->host_seq_x[l] = 4.0 * hy / 6.0 * a;
-            h->host_seq_x[nx + l] = h->host_seq_x[2 * nx + l] = hy / 6.0 * a;
+            M.seq_x[l] = 4.0 * hy / 6.0 * a;
+            M.seq_x[nx + l] = M.seq_x[2 * nx + l] = hy / 6.0 * a;
         }
         for (int l = 0; l < ny; ++l) {
             const double a = p.Ky * mgrit_fd_stiffness_entry(p.gamma, hy, 1.0, l);
-            h->host_seq_y[l] = 4.0 * hx / 6.0 * a;
-            h->host_seq_y[ny + l] = h->host_seq_y[2 * ny + l] = hx / 6.0 * a;
+            M.seq_y[l] = 4.0 * hx / 6.0 * a;
+            M.seq_y[ny + l] = M.seq_y[2 * ny + l] = hx / 6.0 * a;
         }
-    } else {
-        h->cx = mgrit_stiffness_scale(p.beta, hx, hy);
-        h->cy = mgrit_stiffness_scale(p.gamma, hy, hx);
-        mgrit_toeplitz_sequences(p.beta, nx, &h->host_seq_x[0], &h->host_seq_x[nx], &h->host_seq_x[2 * nx]);
-        mgrit_toeplitz_sequences(p.gamma, ny, &h->host_seq_y[0], &h->host_seq_y[ny], &h->host_seq_y[2 * ny]);
-        const double sx = p.Kx * h->cx, sy = p.Ky * h->cy;
-        for (double& v : h->host_seq_x) v *= sx;
-        for (double& v : h->host_seq_y) v *= sy;
+        return;
     }
+    *cx = mgrit_stiffness_scale(p.beta, hx, hy);
+    *cy = mgrit_stiffness_scale(p.gamma, hy, hx);
+    mgrit_toeplitz_sequences(p.beta, nx, &M.seq_x[0], &M.seq_x[nx], &M.seq_x[2 * nx]);
+    mgrit_toeplitz_sequences(p.gamma, ny, &M.seq_y[0], &M.seq_y[ny], &M.seq_y[2 * ny]);
+    const double sx = p.Kx * *cx, sy = p.Ky * *cy;
+    for (double& v : M.seq_x) v *= sx;
+    for (double& v : M.seq_y) v *= sy;
+}
 
+// Padded generating sequences on the device: one block [T1x | A2x | T1y | A2y] per member.
+int build_sequences(mgrit_handle* h) {
+    const int nx = h->geom.nx, ny = h->geom.ny;
+    const int P = (int)h->mem.size();
+    for (int p = 0; p < P; ++p) {
+        double cx, cy;
+        member_sequences(h, h->mem[p], &cx, &cy);
+        if (p == 0) {
+            h->cx = cx;
+            h->cy = cy;
+            h->host_seq_x = h->mem[0].seq_x;
+            h->host_seq_y = h->mem[0].seq_y;
+        }
+    }
     Geom& g = h->geom;
     const int offx = g.seq_off_x, offy = g.seq_off_y;
     const size_t lx = 2 * (size_t)offx + 1, ly = 2 * (size_t)offy + 1;
-    std::vector<double> buf(2 * lx + 2 * ly, 0.0);
-    double* T1x = &buf[0];
-    double* A2x = T1x + lx;
-    double* T1y = A2x + lx;
-    double* A2y = T1y + ly;
-    const double* tx = &h->host_seq_x[0];
-    const double* ux = &h->host_seq_x[nx];
-    const double* wx = &h->host_seq_x[2 * nx];
-    for (int d = -(nx - 1); d <= nx - 1; ++d) {
-        T1x[offx + d] = tx[std::abs(d)];
-        A2x[offx + d] = d >= 0 ? ux[d] : wx[-d];
-    }
-    const double* ty = &h->host_seq_y[0];
-    const double* uy = &h->host_seq_y[ny];
-    const double* wy = &h->host_seq_y[2 * ny];
-    for (int d = -(ny - 1); d <= ny - 1; ++d) {
-        T1y[offy + d] = ty[std::abs(d)];
-        A2y[offy + d] = d >= 0 ? uy[d] : wy[-d];
+    const size_t blk = 2 * lx + 2 * ly;
+    g.ps_seq = (long long)blk;
+    std::vector<double> buf(blk * P, 0.0);
+    for (int p = 0; p < P; ++p) {
+        double* T1x = &buf[blk * p];
+        double* A2x = T1x + lx;
+        double* T1y = A2x + lx;
+        double* A2y = T1y + ly;
+        const double* tx = &h->mem[p].seq_x[0];
+        const double* ux = &h->mem[p].seq_x[nx];
+        const double* wx = &h->mem[p].seq_x[2 * nx];
+        for (int d = -(nx - 1); d <= nx - 1; ++d) {
+            T1x[offx + d] = tx[std::abs(d)];
+            A2x[offx + d] = d >= 0 ? ux[d] : wx[-d];
+        }
+        const double* ty = &h->mem[p].seq_y[0];
+        const double* uy = &h->mem[p].seq_y[ny];
+        const double* wy = &h->mem[p].seq_y[2 * ny];
+        for (int d = -(ny - 1); d <= ny - 1; ++d) {
+            T1y[offy + d] = ty[std::abs(d)];
+            A2y[offy + d] = d >= 0 ? uy[d] : wy[-d];
+        }
     }
     CHK(dalloc(h, &h->d_seq, buf.size()));
     HIPCHK(hipMemcpy(h->d_seq, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -523,28 +652,31 @@ int build_fft_plan(mgrit_handle* h) {
             }
         }
     };
-    std::vector<double> kx, ky;
-    spectra(h->host_seq_x, g.nx, kx);
-    spectra(h->host_seq_y, g.ny, ky);
+    // [tw | kx, ky of member 0 | kx, ky of member 1 | ...]
+    std::vector<double> all(tw);
+    const size_t kn = 3 * 2 * (size_t)L;
+    for (const Member& M : h->mem) {
+        std::vector<double> kx, ky;
+        spectra(M.seq_x, g.nx, kx);
+        spectra(M.seq_y, g.ny, ky);
+        all.insert(all.end(), kx.begin(), kx.end());
+        all.insert(all.end(), ky.begin(), ky.end());
+    }
+    h->geom.ps_spec = (long long)(2 * kn);
     double* d = nullptr;
-    CHK(dalloc(h, &d, tw.size() + kx.size() + ky.size()));
-    HIPCHK(hipMemcpy(d, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(d + tw.size(), kx.data(), kx.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(d + tw.size() + kx.size(), ky.data(), ky.size() * sizeof(double), hipMemcpyHostToDevice));
+    CHK(dalloc(h, &d, all.size()));
+    HIPCHK(hipMemcpy(d, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice));
     h->plan.tw = d;
     h->plan.kx = d + tw.size();
-    h->plan.ky = d + tw.size() + kx.size();
+    h->plan.ky = d + tw.size() + kn;
     if (h->opt.precision != MGRIT_PREC_FP64) {
-        std::vector<float> f;
-        for (double v : tw) f.push_back((float)v);
-        for (double v : kx) f.push_back((float)v);
-        for (double v : ky) f.push_back((float)v);
+        std::vector<float> f(all.begin(), all.end());
         float* d32 = nullptr;
         CHK(dalloc(h, &d32, f.size()));
         HIPCHK(hipMemcpy(d32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
         h->plan.tw32 = d32;
         h->plan.kx32 = d32 + tw.size();
-        h->plan.ky32 = d32 + tw.size() + kx.size();
+        h->plan.ky32 = d32 + tw.size() + kn;
     }
     h->plan.nbx = (g.ny + MGRIT_FFT_LINES - 1) / MGRIT_FFT_LINES;
     h->plan.nby = (g.nx + MGRIT_FFT_LINES - 1) / MGRIT_FFT_LINES;
@@ -572,73 +704,86 @@ constexpr double FD_STIFFNESS_WEIGHT = 0.9;
 constexpr double COARSE_FP32_RTOL = 1e-4;
 
 int build_fd(mgrit_handle* h) {
-    const mgrit_problem& p = h->prob;
-    const int nx = p.Mx - 1, ny = p.My - 1;
-    const double hx = (p.b - p.a) / p.Mx, hy = (p.d - p.c) / p.My;
-    std::vector<double> Vx((size_t)nx * nx), lx(nx), Vy((size_t)ny * ny), ly(ny);
+    const int nx = h->geom.nx, ny = h->geom.ny;
+    const int P = (int)h->mem.size();
+    const bool bf16 = h->opt.precond == MGRIT_PRECOND_FD_BF16;
+    const int npx = h->geom.tiles_x[0] * 64, npy = h->geom.tiles_y[0] * 64;
+    // per member: FP64 [Vx | VxT | Vy | VyT | lx | ly]; BF16 [VxT | Vx | VyT | Vy] (padded); FP32 [lx | ly] (padded)
+    const size_t b64 = 2 * (size_t)nx * nx + 2 * (size_t)ny * ny + nx + ny;
+    const size_t b16 = 2 * (size_t)npx * npx + 2 * (size_t)npy * npy;
+    const size_t bf = (size_t)npx + npy;
+    h->geom.ps_fd = (long long)b64;
+    h->geom.ps_fdb = bf16 ? (long long)b16 : 0;
+    h->geom.ps_fde = bf16 ? (long long)bf : 0;
+    std::vector<double> all64(b64 * P);
+    std::vector<unsigned short> all16(bf16 ? b16 * P : 0, 0);
+    std::vector<float> allf(bf16 ? bf * P : 0, 0.f);
     // P1: lumped mass and a lightened stiffness (an approximation of the step matrix); Q1: the consistent
     // 1-D mass and the unweighted stiffness, whose Kronecker form is the step matrix itself
     const bool q1 = h->opt.element == MGRIT_ELEMENT_Q1;
     auto eig = q1 ? mgrit_fd_eigen_consistent : mgrit_fd_eigen;
     const double wgt = q1 ? 1.0 : FD_STIFFNESS_WEIGHT;
-    if (eig(p.beta, nx, hx, wgt * p.Kx, Vx.data(), lx.data()) != 0 ||
-        eig(p.gamma, ny, hy, wgt * p.Ky, Vy.data(), ly.data()) != 0)
-        return fail(MGRIT_EINVAL, "eigen-decomposition of the preconditioner failed");
-    std::vector<double> VxT(Vx.size()), VyT(Vy.size());
-    for (int i = 0; i < nx; ++i)
-        for (int k = 0; k < nx; ++k) VxT[(size_t)i * nx + k] = Vx[(size_t)k * nx + i];
-    for (int i = 0; i < ny; ++i)
-        for (int k = 0; k < ny; ++k) VyT[(size_t)i * ny + k] = Vy[(size_t)k * ny + i];
+    for (int m = 0; m < P; ++m) {
+        const mgrit_problem& p = h->mem[m].prob;
+        const double hx = (p.b - p.a) / p.Mx, hy = (p.d - p.c) / p.My;
+        std::vector<double> Vx((size_t)nx * nx), lx(nx), Vy((size_t)ny * ny), ly(ny);
+        if (eig(p.beta, nx, hx, wgt * p.Kx, Vx.data(), lx.data()) != 0 ||
+            eig(p.gamma, ny, hy, wgt * p.Ky, Vy.data(), ly.data()) != 0)
+            return fail(MGRIT_EINVAL, "eigen-decomposition of the preconditioner failed");
+        double* B = &all64[b64 * m];
+        double* VxT = B + (size_t)nx * nx;
+        double* VyB = VxT + (size_t)nx * nx;
+        double* VyT = VyB + (size_t)ny * ny;
+        std::copy(Vx.begin(), Vx.end(), B);
+        std::copy(Vy.begin(), Vy.end(), VyB);
+        for (int i = 0; i < nx; ++i)
+            for (int k = 0; k < nx; ++k) VxT[(size_t)i * nx + k] = Vx[(size_t)k * nx + i];
+        for (int i = 0; i < ny; ++i)
+            for (int k = 0; k < ny; ++k) VyT[(size_t)i * ny + k] = Vy[(size_t)k * ny + i];
+        std::copy(lx.begin(), lx.end(), VyT + (size_t)ny * ny);
+        std::copy(ly.begin(), ly.end(), VyT + (size_t)ny * ny + nx);
+        if (!bf16) continue;
+        // zero-padded BF16 copies: A operands of the products over x are row-major
+        // [i][k] (VxT for Vx^T X, Vx for Vx X); B^T operands of the products over y
+        // are row-major [j][k] (VyT for X Vy, Vy for X Vy^T)
+        unsigned short* bx1 = &all16[b16 * m];
+        unsigned short* bx2 = bx1 + (size_t)npx * npx;
+        unsigned short* by1 = bx2 + (size_t)npx * npx;
+        unsigned short* by2 = by1 + (size_t)npy * npy;
+        for (int i = 0; i < nx; ++i)
+            for (int k = 0; k < nx; ++k) {
+                bx1[(size_t)i * npx + k] = to_bf16(Vx[(size_t)k * nx + i]);    // (Vx^T)[i][k]
+                bx2[(size_t)i * npx + k] = to_bf16(Vx[(size_t)i * nx + k]);    // Vx[i][k]
+            }
+        for (int j = 0; j < ny; ++j)
+            for (int k = 0; k < ny; ++k) {
+                by1[(size_t)j * npy + k] = to_bf16(Vy[(size_t)k * ny + j]);    // B = Vy: B^T[j][k] = Vy[k][j]
+                by2[(size_t)j * npy + k] = to_bf16(Vy[(size_t)j * ny + k]);    // B = Vy^T: B^T[j][k] = Vy[j][k]
+            }
+        float* lf = &allf[bf * m];
+        for (int i = 0; i < nx; ++i) lf[i] = (float)lx[i];
+        for (int j = 0; j < ny; ++j) lf[npx + j] = (float)ly[j];
+    }
     double* d = nullptr;
-    const size_t total = 2 * Vx.size() + 2 * Vy.size() + nx + ny;
-    CHK(dalloc(h, &d, total));
-    size_t o = 0;
-    auto put = [&](const std::vector<double>& v, const double** dst) -> int {
-        HIPCHK(hipMemcpy(d + o, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
-        *dst = d + o;
-        o += v.size();
-        return 0;
-    };
-    CHK(put(Vx, &h->fd.Vx));
-    CHK(put(VxT, &h->fd.VxT));
-    CHK(put(Vy, &h->fd.Vy));
-    CHK(put(VyT, &h->fd.VyT));
-    CHK(put(lx, &h->fd.lx));
-    CHK(put(ly, &h->fd.ly));
-    if (h->opt.precond != MGRIT_PRECOND_FD_BF16) return 0;
-    // zero-padded BF16 copies: A operands of the products over x are row-major
-    // [i][k] (VxT for Vx^T X, Vx for Vx X); B^T operands of the products over y
-    // are row-major [j][k] (VyT for X Vy, Vy for X Vy^T)
-    const int npx = h->geom.tiles_x[0] * 64, npy = h->geom.tiles_y[0] * 64;
-    std::vector<unsigned short> bx1((size_t)npx * npx, 0), bx2((size_t)npx * npx, 0);
-    std::vector<unsigned short> by1((size_t)npy * npy, 0), by2((size_t)npy * npy, 0);
-    for (int i = 0; i < nx; ++i)
-        for (int k = 0; k < nx; ++k) {
-            bx1[(size_t)i * npx + k] = to_bf16(Vx[(size_t)k * nx + i]);    // (Vx^T)[i][k]
-            bx2[(size_t)i * npx + k] = to_bf16(Vx[(size_t)i * nx + k]);    // Vx[i][k]
-        }
-    for (int j = 0; j < ny; ++j)
-        for (int k = 0; k < ny; ++k) {
-            by1[(size_t)j * npy + k] = to_bf16(Vy[(size_t)k * ny + j]);    // B = Vy: B^T[j][k] = Vy[k][j]
-            by2[(size_t)j * npy + k] = to_bf16(Vy[(size_t)j * ny + k]);    // B = Vy^T: B^T[j][k] = Vy[j][k]
-        }
-    std::vector<float> lxf(npx, 0.f), lyf(npy, 0.f);
-    for (int i = 0; i < nx; ++i) lxf[i] = (float)lx[i];
-    for (int j = 0; j < ny; ++j) lyf[j] = (float)ly[j];
+    CHK(dalloc(h, &d, all64.size()));
+    HIPCHK(hipMemcpy(d, all64.data(), all64.size() * sizeof(double), hipMemcpyHostToDevice));
+    h->fd.Vx = d;
+    h->fd.VxT = d + (size_t)nx * nx;
+    h->fd.Vy = d + 2 * (size_t)nx * nx;
+    h->fd.VyT = h->fd.Vy + (size_t)ny * ny;
+    h->fd.lx = h->fd.VyT + (size_t)ny * ny;
+    h->fd.ly = h->fd.lx + nx;
+    if (!bf16) return 0;
     unsigned short* b = nullptr;
-    CHK(dalloc(h, &b, bx1.size() * 2 + by1.size() * 2));
-    HIPCHK(hipMemcpy(b, bx1.data(), bx1.size() * 2, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(b + bx1.size(), bx2.data(), bx2.size() * 2, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(b + 2 * bx1.size(), by1.data(), by1.size() * 2, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(b + 2 * bx1.size() + by1.size(), by2.data(), by2.size() * 2, hipMemcpyHostToDevice));
+    CHK(dalloc(h, &b, all16.size()));
+    HIPCHK(hipMemcpy(b, all16.data(), all16.size() * 2, hipMemcpyHostToDevice));
     h->fdb.VxT = b;
-    h->fdb.Vx = b + bx1.size();
-    h->fdb.VyT = b + 2 * bx1.size();
-    h->fdb.Vy = b + 2 * bx1.size() + by1.size();
+    h->fdb.Vx = b + (size_t)npx * npx;
+    h->fdb.VyT = b + 2 * (size_t)npx * npx;
+    h->fdb.Vy = h->fdb.VyT + (size_t)npy * npy;
     float* f = nullptr;
-    CHK(dalloc(h, &f, (size_t)npx + npy));
-    HIPCHK(hipMemcpy(f, lxf.data(), npx * sizeof(float), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(f + npx, lyf.data(), npy * sizeof(float), hipMemcpyHostToDevice));
+    CHK(dalloc(h, &f, allf.size()));
+    HIPCHK(hipMemcpy(f, allf.data(), allf.size() * sizeof(float), hipMemcpyHostToDevice));
     h->fdb.lx = f;
     h->fdb.ly = f + npx;
     return 0;
@@ -688,6 +833,7 @@ int alloc_workspace(mgrit_handle* h, int S) {
         CHK(dalloc(h, &h->mx_scale, S));
         CHK(dalloc(h, &h->mx_eta2, S));
         CHK(dalloc(h, &h->mx_oact, S));
+        CHK(dalloc(h, &h->mx_trust, 2 * (size_t)S));
         CHK(dalloc(h, &h->pout, S * nt));
         if (!h->prz[0]) {
             CHK(dalloc(h, &h->prz[0], S * nt));
@@ -1059,7 +1205,9 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
     for (int outer = 0; outer < 32; ++outer) {
         HIPCHK(launch_mx_begin(g, ps.d, S, xbase, all32 ? nullptr : h->r, h->pbb, h->pout, nop, rtol2, eta * eta,
                                outer == 0 ? 1 : 0, h->bb, h->mx_scale, h->mx_eta2, h->mx_oact, h->act[0], h->iters,
-                               h->r32, h->d32, pc ? nullptr : h->p32, h->prr[0], h->d_start, h->d_iters, st));
+                               h->r32, h->d32, pc ? nullptr : h->p32, h->prr[0], h->d_start, h->d_iters,
+                               h->mx_trust + (size_t)(outer & 1) * h->Smax,
+                               h->mx_trust + (size_t)((outer + 1) & 1) * h->Smax, st));
         if (tv32 < 0) {
             if (h->opt.precision == MGRIT_PREC_MIXED_BF16) tv32 = 0;     // one tile size
             else CHK(tile_variant(h, &ps, S, &tv32, true));
@@ -1107,11 +1255,12 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
             nrec = outer + 1;
         }
         HIPCHK(launch_mx_refine(g, ps.d, S, xbase, h->d32, h->mx_scale, h->mx_oact, st));
-        // When every inner solve of this step had the pass tolerance itself as its target and that
-        // target is at least 10 x the FP32 floor (inner flag 2), its own test settles the slice:
-        // the FP32 residual it reached agrees with the FP64 one to FP32 rounding (about 1e-6 of the
-        // step's starting residual, 1 % of the smallest such target), so the FP64 check is skipped.  Steps
-        // that ran to the floor (the first ones at tight tolerances) are always checked in FP64.
+        // An inner solve whose target was the pass tolerance itself and at least 10 x the FP32 floor
+        // (inner flag 2) settles its slice by its own test: the FP32 residual it reached agrees with the
+        // FP64 one to FP32 rounding (about 1e-6 of the step's starting residual, 1 % of the smallest such
+        // target), so such slices get no FP64 check (k_mx_begin keeps them inactive); when every slice
+        // of the step is one of them the pass ends here.  Steps that ran to the floor (the first ones at
+        // tight tolerances) are checked in FP64.
         if (untrusted == 0 || all32) break;
         HIPCHK(op_resid(h, tv, ps, xbase, h->pout));
     }
@@ -1181,32 +1330,37 @@ int relax(mgrit_handle* h, int l, int warm) {
     return 0;
 }
 
-// G^(l+1)_k = Phi^(l)_km(U_km-1) - U_km; optionally the squared norm of the residual.
-int residual(mgrit_handle* h, int l, double* norm2) {
+// G^(l+1)_k = Phi^(l)_km(U_km-1) - U_km; optionally the squared norm of the residual of every batched
+// member (in member order).
+int residual(mgrit_handle* h, int l, std::vector<double>* norm2) {
     Level& L = h->lv[l];
     Level& C = h->lv[l + 1];
     CHK(run_batch(h, l, L.resid, C.G, 1));
     const Geom* g = &h->geom;
     Bases B = bases(h, l);
-    HIPCHK(launch_zero_slices(g, 1, C.all_idx, C.G, (void*)h->stream));       // G_0 = 0
+    HIPCHK(launch_zero_slices(g, C.nfirst, C.first_idx, C.G, (void*)h->stream));       // G_0 = 0
     HIPCHK(launch_axpy_slices(g, L.subtract.S, L.subtract.yi, C.G, L.subtract.xi, B.U, -1.0,
                               norm2 ? h->pnorm : nullptr, (void*)h->stream));
     if (norm2) {
         const size_t n = (size_t)L.subtract.S * g->pmax;
         HIPCHK(hipMemcpyAsync(h->h_norm, h->pnorm, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
-        double acc = 0.0;
-        for (int s = 0; s < L.subtract.S; ++s)
-            for (int c = 0; c < g->nchunk; ++c) acc += h->h_norm[(size_t)s * g->pmax + c];
-        *norm2 = acc;
+        norm2->clear();
+        int s = 0;
+        for (int cnt : L.sub_count) {
+            double acc = 0.0;
+            for (int e = 0; e < cnt; ++e, ++s)
+                for (int c = 0; c < g->nchunk; ++c) acc += h->h_norm[(size_t)s * g->pmax + c];
+            norm2->push_back(acc);
+        }
     }
     return 0;
 }
 
 int coarsest_solve(mgrit_handle* h, int l) {
     Level& L = h->lv[l];
-    HIPCHK(launch_zero_slices(&h->geom, 1, L.all_idx, L.U, (void*)h->stream));   // E_0 = G_0 = 0
-    for (int k = 1; k <= L.N; ++k) CHK(run_batch(h, l, L.step_list[k - 1]));
+    HIPCHK(launch_zero_slices(&h->geom, L.nfirst, L.first_idx, L.U, (void*)h->stream));   // E_0 = G_0 = 0
+    for (const Batch& b : L.step_list) CHK(run_batch(h, l, b));
     return 0;
 }
 
@@ -1216,7 +1370,7 @@ int cycle(mgrit_handle* h, int l) {
     CHK(relax(h, l, 0));
     CHK(residual(h, l, nullptr));
     Level& C = h->lv[l + 1];
-    HIPCHK(launch_zero_slices(&h->geom, C.N + 1, C.all_idx, C.U, (void*)h->stream));
+    HIPCHK(launch_zero_slices(&h->geom, (int)C.ns, C.all_idx, C.U, (void*)h->stream));
     CHK(cycle(h, l + 1));
     HIPCHK(launch_axpy_slices(&h->geom, L.correct.S, L.correct.yi, L.U, L.correct.xi, C.U, 1.0, nullptr,
                               (void*)h->stream));
@@ -1227,7 +1381,7 @@ int cycle(mgrit_handle* h, int l) {
 int coarse_correct0(mgrit_handle* h) {
     Level& L = h->lv[0];
     Level& C = h->lv[1];
-    HIPCHK(launch_zero_slices(&h->geom, C.N + 1, C.all_idx, C.U, (void*)h->stream));
+    HIPCHK(launch_zero_slices(&h->geom, (int)C.ns, C.all_idx, C.U, (void*)h->stream));
     CHK(cycle(h, 1));
     HIPCHK(launch_axpy_slices(&h->geom, L.correct.S, L.correct.yi, h->U0, L.correct.xi, C.U, 1.0, nullptr,
                               (void*)h->stream));
@@ -1359,19 +1513,33 @@ void mgrit_default_options(mgrit_options* o) {
 
 const char* mgrit_last_error(void) { return g_err; }
 
-int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* stream, mgrit_handle** out) {
-    if (!prob || !opt || !out) return fail(MGRIT_EINVAL, "NULL argument");
+}  // extern "C"
+
+namespace {
+
+// Set-up of one problem (group = false) or of several problems on one mesh (group = true).
+int setup_impl(const mgrit_problem* probs, int nprob, const mgrit_options* opt, void* stream, mgrit_handle** out,
+               bool group) {
+    if (!probs || !opt || !out || nprob < 1) return fail(MGRIT_EINVAL, "NULL argument or no problem");
     *out = nullptr;
-    const mgrit_problem& p = *prob;
-    if (!(p.beta > 0.5 && p.beta < 1.0) || !(p.gamma > 0.5 && p.gamma < 1.0))
-        return fail(MGRIT_EINVAL, "orders must satisfy 1/2 < beta, gamma < 1");
-    if (!(p.Kx > 0.0) || !(p.Ky > 0.0)) return fail(MGRIT_EINVAL, "K_x, K_y must be positive");
-    if (!(p.a < p.b) || !(p.c < p.d)) return fail(MGRIT_EINVAL, "domain must satisfy a < b, c < d");
-    if (p.Mx < 2 || p.My < 2) return fail(MGRIT_EINVAL, "Mx, My must be >= 2");
-    if (p.Nt < 1 || !p.t) return fail(MGRIT_EINVAL, "Nt >= 1 and a time grid are required");
-    if (p.t[0] != 0.0) return fail(MGRIT_EINVAL, "t[0] must be 0");
-    for (int i = 1; i <= p.Nt; ++i)
-        if (!(p.t[i] > p.t[i - 1])) return fail(MGRIT_EINVAL, "time grid must increase strictly (index %d)", i);
+    for (int q = 0; q < nprob; ++q) {
+        const mgrit_problem& p = probs[q];
+        if (!(p.beta > 0.5 && p.beta < 1.0) || !(p.gamma > 0.5 && p.gamma < 1.0))
+            return fail(MGRIT_EINVAL, "orders must satisfy 1/2 < beta, gamma < 1");
+        if (!(p.Kx > 0.0) || !(p.Ky > 0.0)) return fail(MGRIT_EINVAL, "K_x, K_y must be positive");
+        if (!(p.a < p.b) || !(p.c < p.d)) return fail(MGRIT_EINVAL, "domain must satisfy a < b, c < d");
+        if (p.Mx < 2 || p.My < 2) return fail(MGRIT_EINVAL, "Mx, My must be >= 2");
+        if (p.Nt < 1 || !p.t) return fail(MGRIT_EINVAL, "Nt >= 1 and a time grid are required");
+        if (p.t[0] != 0.0) return fail(MGRIT_EINVAL, "t[0] must be 0");
+        for (int i = 1; i <= p.Nt; ++i)
+            if (!(p.t[i] > p.t[i - 1])) return fail(MGRIT_EINVAL, "time grid must increase strictly (index %d)", i);
+        if (p.Mx != probs[0].Mx || p.My != probs[0].My || p.a != probs[0].a || p.b != probs[0].b ||
+            p.c != probs[0].c || p.d != probs[0].d)
+            return fail(MGRIT_EINVAL, "the problems of a group need one mesh and domain (problem %d differs)", q);
+    }
+    if (group && opt->cg_rtol_adapt > 0.0)
+        return fail(MGRIT_EINVAL, "a group takes no adaptive CG tolerance (cg_rtol_adapt = 0)");
+    const mgrit_problem& p = probs[0];
     const mgrit_options& o = *opt;
     if (o.m < 2) return fail(MGRIT_EINVAL, "m must be >= 2");
     if (o.max_levels < 2) return fail(MGRIT_EINVAL, "max_levels must be >= 2");
@@ -1403,9 +1571,16 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
 
     mgrit_handle* h = new (std::nothrow) mgrit_handle();
     if (!h) return fail(MGRIT_ENOMEM, "host allocation failed");
-    h->prob = p;
     h->opt = o;
-    h->t.assign(p.t, p.t + p.Nt + 1);
+    h->mem.resize(nprob);
+    for (int q = 0; q < nprob; ++q) {
+        Member& M = h->mem[q];
+        M.prob = probs[q];
+        M.t.assign(probs[q].t, probs[q].t + probs[q].Nt + 1);
+        M.prob.t = M.t.data();
+    }
+    h->t = h->mem[0].t;
+    h->prob = h->mem[0].prob;
     h->prob.t = h->t.data();
     h->stream = (hipStream_t)stream;
     Geom& g = h->geom;
@@ -1447,6 +1622,12 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
     if (!rc && o.precond != MGRIT_PRECOND_NONE) rc = build_fd(h);
     if (!rc) rc = build_levels(h);
     if (!rc) rc = alloc_workspace(h, h->Smax);
+    if (!rc && group) {
+        long long nf = 0;
+        for (const Member& M : h->mem) nf += M.prob.Nt;
+        rc = dalloc(h, &h->gU, (size_t)h->lv[0].ns * h->geom.stride);
+        if (!rc) rc = dalloc(h, &h->gF, (size_t)nf * h->geom.stride);
+    }
     if (rc) {
         mgrit_destroy(h);
         return rc;
@@ -1455,11 +1636,124 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* strea
     return MGRIT_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int mgrit_setup(const mgrit_problem* prob, const mgrit_options* opt, void* stream, mgrit_handle** out) {
+    return setup_impl(prob, 1, opt, stream, out, false);
+}
+
+int mgrit_setup_group(const mgrit_problem* probs, int nprob, const mgrit_options* opt, void* stream,
+                      mgrit_handle** out) {
+    return setup_impl(probs, nprob, opt, stream, out, true);
+}
+
+int mgrit_solve_group(mgrit_handle* h, const double* const* F, const double* const* psi0, double* const* U, int mem,
+                      mgrit_stats* st) {
+    if (!h) return fail(MGRIT_EINVAL, "NULL handle");
+    if (!h->gU) return fail(MGRIT_EINVAL, "the handle was not set up by mgrit_setup_group");
+    CHK(check_mem(mem));
+    const int P = (int)h->mem.size();
+    if (!psi0 || !U) return fail(MGRIT_EINVAL, "psi0 and U must not be NULL");
+    for (int p = 0; p < P; ++p)
+        if (!psi0[p] || !U[p]) return fail(MGRIT_EINVAL, "psi0[%d] and U[%d] must not be NULL", p, p);
+    const size_t st1 = (size_t)h->geom.stride;
+    const hipMemcpyKind in = mem == MGRIT_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    for (int p = 0; p < P; ++p) {       // the members' loads and initial values into the group's arrays
+        const Member& M = h->mem[p];
+        double* f = h->gF + (size_t)M.f_off * st1;
+        if (F && F[p]) HIPCHK(hipMemcpyAsync(f, F[p], (size_t)M.prob.Nt * st1 * sizeof(double), in, h->stream));
+        else HIPCHK(hipMemsetAsync(f, 0, (size_t)M.prob.Nt * st1 * sizeof(double), h->stream));
+        double* u = h->gU + (size_t)M.off[0] * st1;
+        HIPCHK(hipMemcpyAsync(u, psi0[p], st1 * sizeof(double), in, h->stream));
+        HIPCHK(hipMemsetAsync(u + st1, 0, (size_t)M.prob.Nt * st1 * sizeof(double), h->stream));
+    }
+    h->U0 = h->gU;
+    h->F0 = h->gF;
+    h->cur_rtol = 0.0;
+    h->phi_count = h->cg_count = h->refine_count = 0;
+    const double hxy = ((h->prob.b - h->prob.a) / h->prob.Mx) * ((h->prob.d - h->prob.c) / h->prob.My);
+    std::vector<std::vector<double>> hist(P);
+    std::vector<int> its(P, 0), conv(P, 0), div(P, 0);
+    bool all = true;
+    for (char b : h->batched) all = all && b;
+    if (!all) {
+        h->batched.assign(P, 1);
+        CHK(build_batches(h));
+    }
+    // MGRIT iterations of every member still iterating, their sweeps in shared batches; a member leaves
+    // the batches when its own stop test (or divergence guard) ends its solve, as it would alone
+    int it = 0;
+    while (it < h->opt.max_iter) {
+        CHK(relax(h, 0, it > 0 ? 1 : 0));
+        std::vector<double> n2;
+        CHK(residual(h, 0, &n2));
+        bool changed = false;
+        int k = 0;
+        for (int p = 0; p < P; ++p) {
+            if (!h->batched[p]) continue;
+            const double norm = std::sqrt(hxy * n2[k++]);
+            hist[p].push_back(norm);
+            if (norm < h->opt.tol_abs || norm < h->opt.tol_rel * hist[p][0]) conv[p] = 1;
+            else if (h->opt.divergence_factor > 0.0 && norm > h->opt.divergence_factor * hist[p][0]) div[p] = 1;
+            else ++its[p];
+            if (conv[p] || div[p]) {
+                h->batched[p] = 0;
+                changed = true;
+            }
+        }
+        ++it;
+        int left = 0;
+        for (char b : h->batched) left += b;
+        if (left == 0) break;
+        if (changed) CHK(build_batches(h));
+        CHK(coarse_correct0(h));
+    }
+    // members without convergence end with an F-relaxation (Remark 3.1)
+    std::vector<char> fin(P, 0);
+    bool any = false;
+    for (int p = 0; p < P; ++p) {
+        fin[p] = !conv[p];
+        any = any || fin[p];
+    }
+    if (any) {
+        if (h->batched != fin) {
+            h->batched = fin;
+            CHK(build_batches(h));
+        }
+        CHK(f_relax(h, 0, 1));
+    }
+    const hipMemcpyKind outk = mem == MGRIT_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    for (int p = 0; p < P; ++p) {
+        const Member& M = h->mem[p];
+        HIPCHK(hipMemcpyAsync(U[p], h->gU + (size_t)M.off[0] * st1, ((size_t)M.prob.Nt + 1) * st1 * sizeof(double),
+                              outk, h->stream));
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->U0 = nullptr;
+    h->F0 = nullptr;
+    int rc = MGRIT_OK;
+    for (int p = 0; p < P; ++p) {
+        if (st) fill_stats(h, &st[p], its[p], conv[p], hist[p]);
+        if (div[p]) rc = MGRIT_EDIVERGED;
+        else if (!conv[p] && rc == MGRIT_OK) rc = MGRIT_ENOCONV;
+    }
+    if (rc == MGRIT_EDIVERGED) return fail(rc, "a residual norm grew beyond the divergence guard");
+    if (rc == MGRIT_ENOCONV) return fail(rc, "no convergence in %d iterations", h->opt.max_iter);
+    return MGRIT_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
 void mgrit_destroy(mgrit_handle* h) {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
     for (void* p : h->allocations) (void)hipFree(p);
+    for (void* p : h->batch_allocs) (void)hipFree(p);
     for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : h->tune_ev)
         if (e) (void)hipEventDestroy(e);
@@ -1489,9 +1783,9 @@ int mgrit_solve(mgrit_handle* h, const double* F, const double* psi0, const doub
             h->cur_rtol = std::min(1e-4, std::max(h->opt.cg_rtol, h->opt.cg_rtol_adapt * rho));
         }
         CHK(relax(h, 0, it > 0 ? 1 : 0));
-        double n2 = 0.0;
+        std::vector<double> n2;
         CHK(residual(h, 0, &n2));
-        const double norm = std::sqrt(hxy * n2);
+        const double norm = std::sqrt(hxy * n2[0]);
         hist.push_back(norm);
         if (norm < h->opt.tol_abs || norm < h->opt.tol_rel * hist[0]) {
             conv = 1;
@@ -1555,7 +1849,8 @@ int mgrit_propagate(mgrit_handle* h, int level, const int* step, int nslices, co
     if (nslices < 0 || (nslices > 0 && (!step || !u_in || !u_out))) return fail(MGRIT_EINVAL, "bad slices");
     if (nslices == 0) return MGRIT_OK;
     for (int s = 0; s < nslices; ++s)
-        if (step[s] < 1 || step[s] > h->lv[level].N) return fail(MGRIT_EINVAL, "step index %d out of range", step[s]);
+        if (step[s] < 1 || step[s] > h->mem[0].N[level])
+            return fail(MGRIT_EINVAL, "step index %d out of range", step[s]);
     const size_t st = (size_t)h->geom.stride;
     Staging sg{h};
     const double *du, *dg;
@@ -1569,7 +1864,7 @@ int mgrit_propagate(mgrit_handle* h, int level, const int* step, int nslices, co
         Batch b;
         for (int s = 0; s < S; ++s) {
             Batch one;
-            make_step(h, level, step[s0 + s], s, s, s, one);
+            make_step(h, 0, level, step[s0 + s], s, s, s, one);
             for (int pi = 0; pi < one.npass; ++pi) {
                 PropDesc d = one.pass[pi].h[0];
                 if (level == 0) d.f = dg ? s : -1;
@@ -1856,7 +2151,7 @@ int mgrit_footprint(const mgrit_problem* p, const mgrit_options* o, int mem, siz
     }
     if (o->precision != MGRIT_PREC_FP64) {
         b += 4.0 * (2 * (npx + 96) + 1) * 2 + 4.0 * (2 * (npy + 96) + 1) * 2;          // FP32 sequences
-        b += 4.0 * 5 * smax * st + 20.0 * smax;                                        // FP32 workspace, flags
+        b += 4.0 * 5 * smax * st + 28.0 * smax;                                        // FP32 workspace, flags
         d += smax * pmax * (pc ? 1 : 3);                                                // partials
     }
     const double total = 8 * d + b + desc + smax * 12;
@@ -1867,7 +2162,7 @@ int mgrit_footprint(const mgrit_problem* p, const mgrit_options* o, int mem, siz
 int mgrit_levels(const mgrit_handle* h, int* n_per_level, int cap) {
     if (!h) return fail(MGRIT_EINVAL, "NULL handle");
     const int L = (int)h->lv.size();
-    for (int l = 0; l < L && l < cap; ++l) n_per_level[l] = h->lv[l].N + 1;
+    for (int l = 0; l < L && l < cap; ++l) n_per_level[l] = h->mem[0].N[l] + 1;
     return L;
 }
 

@@ -28,7 +28,7 @@ typedef struct {
     int g;            // slice added after the solve, -1 = none
     int x0;           // slice of the level's state holding the previous value of the
                       // target point (CG start vector when warm starts are on), -1 = none
-    int pad_;
+    int prob;         // problem of the slice (tables at prob x the strides of Geom); 0 for one problem
     double theta_rhs; // right-hand side M u + theta_rhs A u (+ F)
     double theta_lhs; // system matrix M + theta_lhs A
 } PropDesc;
@@ -55,6 +55,13 @@ typedef struct {
     int q1;                     // mass stencil: 0 the 7-point P1 stencil (6; 1 on the x, y and
                                 // (+1,+1), (-1,-1) neighbours), 1 the 9-point Q1 one (16; 4; 1)
     int pad_;
+    // Several problems of one mesh in one batch: each table holds one block per problem, problem p's
+    // block p x stride elements after problem 0's (the pointers in Seqs, FftPlan, FdMats, FdMatsB)
+    long long ps_seq;           // padded generating sequences (FP64 and FP32 copies alike)
+    long long ps_spec;          // FFT kernel spectra (kx, ky and their FP32 copies)
+    long long ps_fd;            // FP64 preconditioner matrices and eigenvalues
+    long long ps_fdb;           // BF16 preconditioner matrices
+    long long ps_fde;           // FP32 preconditioner eigenvalues
 } Geom;
 
 // Padded generating sequences on the device, already multiplied by K c:
@@ -189,11 +196,14 @@ int launch_apply_bf16(const Geom* g, const Seqs32* sq, const PropDesc* desc, int
 // eta^2 = max(rtol^2 ||b||^2 / ||r||^2, eta_min2), r32 = r / ||r||, d32 = 0, and p32 = r32
 // with partial r32.r32 when p32 != NULL; first: x = 0 where b = 0, counts reset.  The flags
 // are also stored into host_act and the reset counts into host_iters (pinned host memory, either
-// may be NULL).
+// may be NULL).  trust_out[s] = 1 when the step's inner target is the pass tolerance itself (inner flag
+// 2) or the slice was already settled; a slice with trust_in[s] = 1 (the previous step's trust_out) is
+// settled and stays inactive (not read on the first step).
 int launch_mx_begin(const Geom* g, const PropDesc* desc, int S, double* xbase, const double* rws,
                     const double* partial_bb, const double* partial_rr, int np, double rtol2, double eta_min2,
                     int first, double* bb, double* scale, double* eta2, int* oact, int* iact, int* iters, float* r32,
-                    float* d32, float* p32, double* partial_rr32, int* host_act, int* host_iters, void* stream);
+                    float* d32, float* p32, double* partial_rr32, int* host_act, int* host_iters,
+                    const int* trust_in, int* trust_out, void* stream);
 // alpha = rho / p.q; d32 += alpha p32, r32 -= alpha q32; partial r32.r32.
 int launch_mx_update(const Geom* g, int S, float* d32, float* r32, const float* p32, const float* q32,
                      const double* partial_rho, int nrho, const double* partial_pq, int npq, double* partial_rr_new,

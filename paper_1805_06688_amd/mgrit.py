@@ -58,7 +58,7 @@ class RequestInfo(ctypes.Structure):
                 ("start_s", ctypes.c_double), ("finish_s", ctypes.c_double), ("bytes", ctypes.c_size_t)]
 
 
-SYMBOLS = ("mgrit_default_options", "mgrit_setup", "mgrit_solve", "mgrit_iterate", "mgrit_sequential",
+SYMBOLS = ("mgrit_default_options", "mgrit_setup", "mgrit_setup_group", "mgrit_solve_group", "mgrit_solve", "mgrit_iterate", "mgrit_sequential",
            "mgrit_propagate", "mgrit_apply", "mgrit_apply_noalloc", "mgrit_apply_f32", "mgrit_rhs_f32", "mgrit_residual_f32",
            "mgrit_sequences", "mgrit_levels", "mgrit_destroy",
            "mgrit_last_error", "mgrit_toeplitz_sequences", "mgrit_stiffness_scale", "mgrit_profile_enable",
@@ -77,6 +77,11 @@ def load_library(path=_LIB_PATH):
     lib.mgrit_default_options.restype = None
     lib.mgrit_setup.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Options), P, ctypes.POINTER(P)]
     lib.mgrit_setup.restype = c_int
+    lib.mgrit_setup_group.argtypes = [ctypes.POINTER(_Problem), c_int, ctypes.POINTER(_Options), P, ctypes.POINTER(P)]
+    lib.mgrit_setup_group.restype = c_int
+    lib.mgrit_solve_group.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), c_int,
+                                      ctypes.POINTER(Stats)]
+    lib.mgrit_solve_group.restype = c_int
     lib.mgrit_solve.argtypes = [P, P, P, P, P, c_int, ctypes.POINTER(Stats)]
     lib.mgrit_solve.restype = c_int
     lib.mgrit_iterate.argtypes = [P, P, P, P, c_int, P, c_int, ctypes.POINTER(Stats)]
@@ -430,6 +435,62 @@ class Solver:
         buf = (ctypes.c_int * 64)()
         L = _lib.mgrit_levels(self._h, buf, 64)
         return [buf[i] - 1 for i in range(L)]
+
+
+class Group:
+    """Several problems on one mesh whose sweeps share kernel launches (mgrit_setup_group).
+
+    problems: list of dicts with beta, gamma, Kx, Ky and t (each its own time grid); Mx, My and the domain are
+    common."""
+
+    def __init__(self, problems, Mx, My, domain=(0.0, 1.0, 0.0, 1.0), stream=None, **opts):
+        self._h = None
+        made = [make_problem(q["beta"], q["gamma"], q["Kx"], q["Ky"], Mx, My, q["t"], domain) for q in problems]
+        self._ts = [t for _, t in made]
+        arr = (_Problem * len(made))(*[p for p, _ in made])
+        o = make_options(**opts)
+        if stream is None:
+            stream = Solver._torch_stream()
+        h = ctypes.c_void_p()
+        _check(_lib.mgrit_setup_group(arr, len(made), ctypes.byref(o), stream, ctypes.byref(h)))
+        self._h = h
+        self.nx, self.ny = int(Mx) - 1, int(My) - 1
+        self.Nts = [len(t) - 1 for t in self._ts]
+
+    def close(self):
+        if self._h is not None:
+            _lib.mgrit_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def solve(self, Fs, psi0s, outs=None, allow_noconv=True):
+        """Solve all problems: returns ([U_p [Nt_p+1, ny, nx]], [Stats], return code)."""
+        P = len(self.Nts)
+        mem = _mem_of(psi0s[0])
+        n = self.nx * self.ny
+        if outs is None:
+            outs = []
+            for Nt, p0 in zip(self.Nts, psi0s):
+                if _is_torch(p0):
+                    import torch
+                    outs.append(torch.empty((Nt + 1) * n, dtype=torch.float64, device=p0.device))
+                else:
+                    outs.append(np.empty((Nt + 1) * n))
+        PA = ctypes.c_void_p * P
+        f = PA(*[_ptr(F, mem, Nt * n) if F is not None else None for F, Nt in zip(Fs, self.Nts)])
+        p0 = PA(*[_ptr(x, mem, n) for x in psi0s])
+        u = PA(*[_ptr(x, mem, (Nt + 1) * n) for x, Nt in zip(outs, self.Nts)])
+        st = (Stats * P)()
+        rc = _check(_lib.mgrit_solve_group(self._h, f, p0, u, mem, st), allow=(ENOCONV, EDIVERGED) if allow_noconv else ())
+        return [x.reshape(Nt + 1, self.ny, self.nx) for x, Nt in zip(outs, self.Nts)], list(st), rc
 
 
 class Request:
