@@ -250,6 +250,51 @@ def many_instance(mgrit, wl, torch, n_problems, max_concurrent):
                     f"m in {{4, 8, 16}}, beta, gamma ~ U(0.55, 0.95), K = 1; the headline's options")}
 
 
+def many_same_mesh(mgrit, wl, torch, n_problems, n):
+    """Independent problems on one mesh: one group (their sweeps in shared launches) against the server
+    (concurrent solves on 4 streams) and against one solve after another; aggregate DOF/s each, and the
+    largest difference between a problem's group and solo results."""
+    probs = wl.many_same_mesh(6, n_problems, n=n)
+    dev = [wl.device_inputs(r["input_seed"], r["Nt"], r["nx"], r["ny"]) for r in probs]
+    dof = sum(r["nx"] * r["ny"] * r["Nt"] for r in probs)
+    opts = dict(BASE, **HEADLINE)
+    out = {"problems": n_problems, "n": n,
+           "set": (f"seed 6: {n_problems} problems on one {n} x {n} mesh, N_t ~ U{{256..2048}} (multiple of 8), m = 8, "
+                   f"beta, gamma ~ U(0.55, 0.95), K = 1; the headline's options")}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with mgrit.Group([dict(beta=r["beta"], gamma=r["gamma"], Kx=r["Kx"], Ky=r["Ky"], t=r["t"]) for r in probs],
+                     n + 1, n + 1, m=8, **opts) as g:
+        g.solve([F for F, _ in dev], [p for _, p in dev])          # cold: set-up and first solve
+        torch.cuda.synchronize()
+        cold = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        Ug, stg, rc = g.solve([F for F, _ in dev], [p for _, p in dev])
+        torch.cuda.synchronize()
+        out["group"] = {"dof_per_s": dof / (time.perf_counter() - t0), "rc": rc,
+                        "dof_per_s_with_setup": dof / cold,
+                        "mgrit_iterations": [st.iterations for st in stg]}
+    Us = []
+    t0 = time.perf_counter()
+    for r, (F, p) in zip(probs, dev):
+        with mgrit.Solver(r["beta"], r["gamma"], r["Kx"], r["Ky"], n + 1, n + 1, r["t"], m=8, **opts) as s:
+            U, st, rc = s.solve(F, p)
+            Us.append(U)
+    torch.cuda.synchronize()
+    out["one_after_another"] = {"dof_per_s": dof / (time.perf_counter() - t0),
+                                "note": "includes each solve's set-up"}
+    out["max_rel_diff_group_vs_solo"] = max(float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+                                            for a, b in zip(Ug, Us))
+    t0 = time.perf_counter()
+    with mgrit.Server(200 << 30, max_concurrent=4) as srv:
+        hs = [srv.submit(F, p, r["beta"], r["gamma"], r["Kx"], r["Ky"], n + 1, n + 1, r["t"], m=8, **opts)
+              for r, (F, p) in zip(probs, dev)]
+        infos = [h.wait()[1] for h in hs]
+    out["server_4_streams"] = {"dof_per_s": dof / (time.perf_counter() - t0),
+                               "all_converged": all(i.rc == 0 for i in infos), "note": "includes each solve's set-up"}
+    return out
+
+
 def cpu_baseline(W, t, F, psi0, steps, start):
     """The CPU oracle as it stands: sequential stepping over `steps` steps of the time grid from step `start`."""
     from oracle import fem, propagator
@@ -431,6 +476,8 @@ def main():
         torch.cuda.empty_cache()
         out["many_instance"] = many_instance(mgrit, wl, torch, args.many, 4)
         note("many-instance set done")
+        out["many_instance_same_mesh"] = many_same_mesh(mgrit, wl, torch, args.many, 127)
+        note("same-mesh set done (group, one after another, server)")
         out["serving"] = serving(mgrit, wl, torch, args.serving_requests, 20.0, args.serving_nt_scale, 4, 200)
         note("serving trace done")
     if not args.no_cpu and not args.skip_reference:

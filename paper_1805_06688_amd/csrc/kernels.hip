@@ -109,7 +109,7 @@ inline int grid_blocks(int ntiles, int S) { return S < 8 ? ntiles * S : ntiles *
 template <typename S>
 __device__ __forceinline__ S seqs_of(const S& sq, const Geom& g, int p) {
     S r = sq;
-    const long long o = (long long)p * g.ps_seq;
+    const long long o = (long long)__builtin_amdgcn_readfirstlane(p) * g.ps_seq;
     r.T1x += o;
     r.A2x += o;
     r.T1y += o;
@@ -930,7 +930,7 @@ __global__ __launch_bounds__(NT) void k_fd_gemm(Geom g, int S, const double* __r
     if (s < 0) return;
     if (active && !active[s]) return;
     {
-        const long long o = (long long)desc[s].prob * g.ps_fd;
+        const long long o = (long long)__builtin_amdgcn_readfirstlane(desc[s].prob) * g.ps_fd;
         mat += o;
         lx += o;
         ly += o;
@@ -1070,7 +1070,7 @@ __global__ __launch_bounds__(NT, EPI == 2 ? 8 : 1) void k_fdb_gemm(Geom g, int S
     if (s < 0) return;
     if (active && !active[s]) return;
     {
-        const int pr = desc[s].prob;
+        const int pr = __builtin_amdgcn_readfirstlane(desc[s].prob);     // uniform: scalar offsets
         mat += (long long)pr * g.ps_fdb;
         lx += (long long)pr * g.ps_fde;
         ly += (long long)pr * g.ps_fde;
@@ -1243,7 +1243,7 @@ __global__ __launch_bounds__(NT) void k_fdb_gemm32(Geom g, int S, const __bf16* 
     if (s < 0) return;
     if (active && !active[s]) return;
     {
-        const int pr = desc[s].prob;
+        const int pr = __builtin_amdgcn_readfirstlane(desc[s].prob);     // uniform: scalar offsets
         mat += (long long)pr * g.ps_fdb;
         lx += (long long)pr * g.ps_fde;
         ly += (long long)pr * g.ps_fde;
@@ -1657,7 +1657,7 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
     const int l0 = blk * FJ;                 // first output line
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const cpx<T>* tw = (const cpx<T>*)(sizeof(T) == 8 ? (const void*)pl.tw : (const void*)pl.tw32);
-    const long long kof = (long long)prob * g.ps_spec;
+    const long long kof = (long long)__builtin_amdgcn_readfirstlane(prob) * g.ps_spec;
     const cpx<T>* K = (const cpx<T>*)(sizeof(T) == 8 ? (const void*)((DIR == 0 ? pl.kx : pl.ky) + kof)
                                                       : (const void*)((DIR == 0 ? pl.kx32 : pl.ky32) + kof));
     cpx<T>* buf = lds + wave * FPAD;
@@ -1735,6 +1735,12 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
         const cpx<T>* Z2 = buf + FPAD;       // lines oa + 1, oa + 2
         const T half = (T)0.5;
         const T mlen = (T)(g.mass / FL);     // spectra carry the 1 / FL of the inverse
+        // the mass stencil as three more kernels of the x pass, a0 + a1 cos on line j and b0 + b1 cos -+ i bs sin
+        // on lines j +- 1: P1: 6 v + v(i-1) + v(i+1) on line j, v(i) + v(i+1) on line j+1, v(i) + v(i-1) on
+        // line j-1 (6, 2; 1, 1, 1); bilinear: 4 (4 v + v(i-1) + v(i+1)) on line j, 4 v + v(i-1) + v(i+1) on
+        // j +- 1 (16, 8; 4, 2, 0)
+        const T ma0 = mlen * (g.q1 ? T(16) : T(6)), ma1 = mlen * (g.q1 ? T(8) : T(2));
+        const T mb0 = mlen * (g.q1 ? T(4) : T(1)), mb1 = mlen * (g.q1 ? T(2) : T(1)), mbs = g.q1 ? T(0) : mlen;
 #pragma unroll
         for (int r = 0; r < NP; ++r) {
             const int k = lane + 64 * r, kk = (FL - k) & (FL - 1);
@@ -1749,21 +1755,12 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
                 c1 = {theta * c1.x, theta * c1.y};
                 c2 = {theta * c2.x, theta * c2.y};
                 c3 = {theta * c3.x, theta * c3.y};
-                // the mass stencil as three more kernels of the x pass: 6 v + v(i-1) + v(i+1)
-                // on line j, v(i) + v(i+1) on line j+1, v(i) + v(i-1) on line j-1 (P1); the
-                // bilinear one: 4 (4 v + v(i-1) + v(i+1)) on line j, 4 v + v(i-1) + v(i+1) on j +- 1
                 const cpx<T> w = tw[k];
-                if (g.q1) {
-                    c1.x += mlen * (T(16) + T(8) * w.x);
-                    c2.x += mlen * (T(4) + T(2) * w.x);
-                    c3.x += mlen * (T(4) + T(2) * w.x);
-                } else {
-                    c1.x += mlen * (T(6) + T(2) * w.x);
-                    c2.x += mlen * (T(1) + w.x);
-                    c2.y -= mlen * w.y;
-                    c3.x += mlen * (T(1) + w.x);
-                    c3.y += mlen * w.y;
-                }
+                c1.x += ma0 + ma1 * w.x;
+                c2.x += mb0 + mb1 * w.x;
+                c2.y -= mbs * w.y;
+                c3.x += mb0 + mb1 * w.x;
+                c3.y += mbs * w.y;
             }
             const cpx<T> xa = cadd(cadd(cmul(c1, v0), cmul(c2, vp)), cmul(c3, vm));
             const cpx<T> xb = cadd(cadd(cmul(c1, vp), cmul(c2, vq)), cmul(c3, v0));

@@ -119,6 +119,19 @@ def many_problem_set(seed, n_problems, n_range=(127, 383), nt_range=(256, 2048),
     return out
 
 
+def many_same_mesh(seed, n_problems, n=127, nt_range=(256, 2048), m=8):
+    """Independent problems on one n x n mesh: N_t ~ U{nt_range} (a multiple of m), beta, gamma ~ U(0.55, 0.95),
+    K = 1, uniform grid; F, psi_0 from device_inputs with each problem's input_seed."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_problems):
+        Nt = max(2 * m, int(rng.integers(nt_range[0], nt_range[1] + 1)) // m * m)
+        beta, gamma = (float(v) for v in rng.uniform(0.55, 0.95, 2))
+        out.append(dict(nx=n, ny=n, Nt=Nt, m=m, beta=beta, gamma=gamma, Kx=1.0, Ky=1.0, t=uniform_grid(Nt),
+                        input_seed=seed * 100000 + 50000 + k))
+    return out
+
+
 def serving_trace(seed, n_requests, rate, n_range=(63, 255), nt_range=(64, 512), m=8):
     """Poisson arrivals (rate per second) of solves with n_x, n_y ~ U{n_range}, N_t ~ U{nt_range}
     (a multiple of m), beta, gamma ~ U(0.55, 0.95), K = 1, T = 1, uniform grid; F ~ N(0,1), psi_0 ~ U[0,1].

@@ -152,3 +152,30 @@ def test_fd_eigen_consistent_matches_q1_oracle(rho, n, h, K):
     assert np.allclose(np.sort(lam), ref, rtol=1e-11, atol=1e-12 * ref.max())
     assert np.abs(V.T @ M @ V - np.eye(n)).max() < 1e-12
     assert np.abs(V.T @ Kd @ V - np.diag(lam)).max() < 1e-11 * np.abs(lam).max()
+
+
+@pytest.mark.slow
+def test_hot_kernels_do_not_spill_registers(tmp_path):
+    """The operator (FFT passes, tiled matrix-core kernels) and the CG vector kernels fit their registers: a
+    spill to scratch memory in any of them costs the solver a large factor (the compiler's resource report)."""
+    import os
+    import re
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    csrc = os.path.join(root, "paper_1805_06688_amd", "csrc")
+    cmd = ["/opt/rocm/bin/hipcc", "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature",
+           "-Xclang", "-packed-fp32-ops", "-I", os.path.join(root, "include"), "-I", csrc, "--cuda-device-only", "-c",
+           os.path.join(csrc, "kernels.hip"), "-o", str(tmp_path / "k.o"), "-Rpass-analysis=kernel-resource-usage"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    spills, cur = {}, None
+    for line in r.stderr.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = m.group(1)
+            continue
+        m = re.search(r"remark:\s+VGPRs Spill: (\d+)", line)
+        if m and cur:
+            spills[cur] = int(m.group(1))
+    hot = {k: v for k, v in spills.items() if re.search(r"k_fft_line|k_apply|k_prop_apply|k_mx_|k_cg_", k)}
+    assert len(hot) >= 30, sorted(hot)
+    assert all(v == 0 for v in hot.values()), {k: v for k, v in hot.items() if v}
