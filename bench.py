@@ -292,6 +292,15 @@ def many_same_mesh(mgrit, wl, torch, n_problems, n):
         infos = [h.wait()[1] for h in hs]
     out["server_4_streams"] = {"dof_per_s": dof / (time.perf_counter() - t0),
                                "all_converged": all(i.rc == 0 for i in infos), "note": "includes each solve's set-up"}
+    t0 = time.perf_counter()
+    with mgrit.Server(200 << 30, max_concurrent=4, group_limit=8) as srv:
+        hs = [srv.submit(F, p, r["beta"], r["gamma"], r["Kx"], r["Ky"], n + 1, n + 1, r["t"], m=8, **opts)
+              for r, (F, p) in zip(probs, dev)]
+        infos = [h.wait()[1] for h in hs]
+    out["server_4_streams_groups_of_8"] = {
+        "dof_per_s": dof / (time.perf_counter() - t0), "all_converged": all(i.rc == 0 for i in infos),
+        "group_sizes": sorted(set(i.group_size for i in infos)),
+        "note": "queued requests of one mesh taken into group solves of up to 8; includes set-up"}
     return out
 
 

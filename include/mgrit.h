@@ -401,12 +401,22 @@ typedef struct {
     double submit_s;      /* seconds since server creation                           */
     double start_s;       /* admitted                                                */
     double finish_s;      /* result written                                          */
-    size_t bytes;         /* footprint charged against the budget                    */
+    size_t bytes;         /* footprint of the request alone                          */
+    int group_size;       /* requests solved together in its group solve (1: alone)  */
 } mgrit_request_info;
 
 /* device_budget_bytes: memory the server may commit to solves at once;
  * max_concurrent >= 1.  Errors: EINVAL. */
 int mgrit_server_create(size_t device_budget_bytes, int max_concurrent, mgrit_server** out);
+/* Batching of requests: a worker that admits the oldest queued request also
+ * takes up to max_members - 1 more queued requests with the same mesh, domain,
+ * options and memory space (while the budget holds their footprints plus the
+ * group's copies of their loads and states) and solves them as one group
+ * (mgrit_setup_group): their propagator sweeps share kernel launches and each
+ * result equals its solo solve (see mgrit_setup_group).  A group that cannot be
+ * set up (different level counts) runs its requests one after another.
+ * Default 1: every request alone.  Errors: EINVAL. */
+int mgrit_server_set_group_limit(mgrit_server* s, int max_members);
 /* Queue one solve (arguments as in mgrit_setup and mgrit_solve; the problem's
  * time grid is copied).  Returns EINVAL at once for invalid arguments or a
  * footprint above the whole budget.  *id identifies the request. */

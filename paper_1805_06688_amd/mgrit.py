@@ -55,17 +55,18 @@ class Stats(ctypes.Structure):
 
 class RequestInfo(ctypes.Structure):
     _fields_ = [("rc", ctypes.c_int), ("stats", Stats), ("submit_s", ctypes.c_double),
-                ("start_s", ctypes.c_double), ("finish_s", ctypes.c_double), ("bytes", ctypes.c_size_t)]
+                ("start_s", ctypes.c_double), ("finish_s", ctypes.c_double), ("bytes", ctypes.c_size_t),
+                ("group_size", ctypes.c_int)]
 
 
-SYMBOLS = ("mgrit_default_options", "mgrit_setup", "mgrit_setup_group", "mgrit_solve_group", "mgrit_solve", "mgrit_iterate", "mgrit_sequential",
-           "mgrit_propagate", "mgrit_apply", "mgrit_apply_noalloc", "mgrit_apply_f32", "mgrit_rhs_f32", "mgrit_residual_f32",
-           "mgrit_sequences", "mgrit_levels", "mgrit_destroy",
-           "mgrit_last_error", "mgrit_toeplitz_sequences", "mgrit_stiffness_scale", "mgrit_profile_enable",
-           "mgrit_profile_read", "mgrit_fd_stiffness_entry", "mgrit_fd_eigen", "mgrit_fd_eigen_consistent",
-           "mgrit_footprint",
-           "mgrit_device_bytes", "mgrit_server_create", "mgrit_server_submit", "mgrit_server_wait",
-           "mgrit_server_poll", "mgrit_server_destroy")
+SYMBOLS = ("mgrit_default_options", "mgrit_setup", "mgrit_setup_group", "mgrit_solve", "mgrit_solve_group",
+           "mgrit_iterate", "mgrit_sequential", "mgrit_propagate", "mgrit_apply", "mgrit_apply_noalloc",
+           "mgrit_apply_f32", "mgrit_rhs_f32", "mgrit_residual_f32", "mgrit_sequences", "mgrit_levels",
+           "mgrit_destroy", "mgrit_last_error", "mgrit_toeplitz_sequences", "mgrit_stiffness_scale",
+           "mgrit_profile_enable", "mgrit_profile_read", "mgrit_fd_stiffness_entry", "mgrit_fd_eigen",
+           "mgrit_fd_eigen_consistent", "mgrit_footprint", "mgrit_device_bytes", "mgrit_server_create",
+           "mgrit_server_set_group_limit", "mgrit_server_submit", "mgrit_server_wait", "mgrit_server_poll",
+           "mgrit_server_destroy")
 
 
 def load_library(path=_LIB_PATH):
@@ -130,6 +131,8 @@ def load_library(path=_LIB_PATH):
     lib.mgrit_device_bytes.restype = c_int
     lib.mgrit_server_create.argtypes = [ctypes.c_size_t, c_int, ctypes.POINTER(P)]
     lib.mgrit_server_create.restype = c_int
+    lib.mgrit_server_set_group_limit.argtypes = [P, c_int]
+    lib.mgrit_server_set_group_limit.restype = c_int
     lib.mgrit_server_submit.argtypes = [P, ctypes.POINTER(_Problem), ctypes.POINTER(_Options), P, P, P, c_int,
                                         ctypes.POINTER(ctypes.c_longlong)]
     lib.mgrit_server_submit.restype = c_int
@@ -514,12 +517,13 @@ class Request:
 class Server:
     """Admission by device-memory footprint, concurrent solves on separate streams (C ABI mgrit_server_*)."""
 
-    def __init__(self, device_budget_bytes, max_concurrent=4):
+    def __init__(self, device_budget_bytes, max_concurrent=4, group_limit=1):
         self._s = None
         s = ctypes.c_void_p()
         _check(_lib.mgrit_server_create(ctypes.c_size_t(int(device_budget_bytes)), int(max_concurrent),
                                         ctypes.byref(s)))
         self._s = s
+        _check(_lib.mgrit_server_set_group_limit(s, int(group_limit)))
 
     def submit(self, F, psi0, beta, gamma, Kx, Ky, Mx, My, t, domain=(0.0, 1.0, 0.0, 1.0), out=None, **opts):
         p, tt = make_problem(beta, gamma, Kx, Ky, Mx, My, t, domain)

@@ -94,3 +94,40 @@ def test_oversized_request_is_rejected():
     with mg.Server(1 << 20, max_concurrent=1) as srv:
         with pytest.raises(mg.MgritError):
             srv.submit(r["F"], r["psi0"], r["beta"], r["gamma"], r["Kx"], r["Ky"], r["Mx"], r["My"], r["t"], **OPTS)
+
+
+def test_queued_same_mesh_requests_share_one_group_solve():
+    """With a group limit, a worker takes the queued requests of the oldest one's mesh into one group solve
+    (their sweeps share launches); requests on another mesh run on their own; every result equals its solo
+    solve (FP64, no preconditioner: bit for bit)."""
+    mg = _mg()
+    opts = dict(OPTS, precond="none")
+    Mx, My = 60, 52
+    reqs = []
+    for k in range(5):
+        Nt = 32 + 8 * k
+        t = wl.uniform_grid(Nt) if k % 2 else wl.graded_grid(Nt)
+        F, psi0 = wl.random_inputs(900 + k, Nt, Mx - 1, My - 1)
+        reqs.append(dict(beta=0.6 + 0.05 * k, gamma=0.9 - 0.05 * k, Kx=1.0, Ky=1.5, Mx=Mx, My=My, t=t,
+                         F=torch.from_numpy(F).cuda(), psi0=torch.from_numpy(psi0).cuda()))
+    other = _requests(1, 4)[0]
+    reqs.insert(2, other)                      # a request on another mesh in the middle of the queue
+    ref = []
+    for r in reqs:
+        with mg.Solver(r["beta"], r["gamma"], r["Kx"], r["Ky"], r["Mx"], r["My"], r["t"], **opts) as s:
+            U, st, rc = s.solve(r["F"], r["psi0"])
+            ref.append((U.clone(), st.iterations))
+    blocker = _requests(1, 5)[0]
+    with mg.Server(8 << 30, max_concurrent=1, group_limit=8) as srv:
+        # the first request occupies the only slot while the others queue behind it
+        h0 = srv.submit(blocker["F"], blocker["psi0"], blocker["beta"], blocker["gamma"], blocker["Kx"], blocker["Ky"],
+                        blocker["Mx"], blocker["My"], blocker["t"], **opts)
+        hs = [srv.submit(r["F"], r["psi0"], r["beta"], r["gamma"], r["Kx"], r["Ky"], r["Mx"], r["My"], r["t"], **opts)
+              for r in reqs]
+        out = [h.wait() for h in hs]
+        h0.wait()
+    sizes = [info.group_size for _, info in out]
+    assert sizes == [5, 5, 1, 5, 5, 5], sizes
+    for (U, info), (R, its) in zip(out, ref):
+        assert info.rc == 0 and info.stats.iterations == its
+        assert torch.equal(U.reshape(R.shape), R)
