@@ -660,9 +660,28 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
     }
 }
 
-// alpha = rho / p.q; d32 += alpha p32, r32 -= alpha q32; partial r32.r32.
-// The element loads are issued before the partial sums are reduced, so the two
-// memory round trips overlap (as in k_mx_direction).
+// 16-byte groups of chunk [lo, hi) of an FP32 workspace slice: with base = the chunk's first element in
+// the array, the elements before the first 16-byte boundary (head) and after the last one (tail) are done
+// one by one, the rest as float4 groups (GPT per thread: group tid + NT j).  The launchers require every
+// array to start on a 16-byte boundary, so one split holds for all of a kernel's vectors.
+constexpr int GPT = CH / (NT * 4);
+static_assert(CH % (NT * 4) == 0, "chunk must hold whole float4 groups per thread");
+
+struct Split16 {
+    int head, ngr, tail0, len;
+};
+
+__device__ __forceinline__ Split16 split16(long long base, int len) {
+    Split16 sp;
+    sp.len = len;
+    sp.head = (int)((4 - (base & 3)) & 3);
+    if (sp.head > len) sp.head = len;
+    sp.ngr = (len - sp.head) >> 2;
+    sp.tail0 = sp.head + 4 * sp.ngr;
+    return sp;
+}
+
+// alpha = rho / p.q; d32 += alpha p32, r32 -= alpha q32 on active slices; partial r32.r32 per chunk.
 __global__ __launch_bounds__(NT) void k_mx_update(Geom g, int S, float* __restrict__ d32, float* __restrict__ r32,
                                                   const float* __restrict__ p32, const float* __restrict__ q32,
                                                   const double* partial_rho, int nrho, const double* partial_pq,
@@ -674,35 +693,79 @@ __global__ __launch_bounds__(NT) void k_mx_update(Geom g, int S, float* __restri
     const long long so = (long long)s * g.stride;
     long long lo, hi;
     chunk_range(g, c, lo, hi);
-    const long long e0 = so + lo + threadIdx.x, last = so + hi - 1;
-    float dv[PT], rv[PT], pv[PT], qv[PT];
+    const long long base = so + lo;
+    const Split16 sp = split16(base, (int)(hi - lo));
+    const int tid = threadIdx.x;
+    float4* D = (float4*)(d32 + base + sp.head);
+    float4* R = (float4*)(r32 + base + sp.head);
+    const float4* P = (const float4*)(p32 + base + sp.head);
+    const float4* Q = (const float4*)(q32 + base + sp.head);
+    float4 dv[GPT], rv[GPT], pv[GPT], qv[GPT];
 #pragma unroll
-    for (int k = 0; k < PT; ++k) {
-        const long long e = e0 + (long long)k * NT < last ? e0 + (long long)k * NT : last;
-        dv[k] = d32[e];
-        rv[k] = r32[e];
-        pv[k] = p32[e];
-        qv[k] = q32[e];
+    for (int j = 0; j < GPT; ++j) {
+        const int k = tid + NT * j;
+        if (k < sp.ngr) {
+            dv[j] = D[k];
+            rv[j] = R[k];
+            pv[j] = P[k];
+            qv[j] = Q[k];
+        }
+    }
+    // the one-by-one elements: thread t < head takes element t, thread t < len - tail0 element tail0 + t
+    const bool hh = tid < sp.head, ht = tid < sp.len - sp.tail0;
+    const long long eh = base + tid, et = base + sp.tail0 + tid;
+    float dh = 0.f, rh = 0.f, ph = 0.f, qh = 0.f, dt = 0.f, rt = 0.f, pt = 0.f, qt = 0.f;
+    if (hh) {
+        dh = d32[eh];
+        rh = r32[eh];
+        ph = p32[eh];
+        qh = q32[eh];
+    }
+    if (ht) {
+        dt = d32[et];
+        rt = r32[et];
+        pt = p32[et];
+        qt = q32[et];
     }
     const float alpha = (float)(slice_sum(partial_rho, g.pmax, s, nrho) / slice_sum(partial_pq, g.pmax, s, npq));
     double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < PT; ++k) {
-        const long long e = e0 + (long long)k * NT;
-        const float rn = rv[k] - alpha * qv[k];
-        if (e <= last) {
-            d32[e] = dv[k] + alpha * pv[k];
-            r32[e] = rn;
-            acc += (double)rn * (double)rn;
+    for (int j = 0; j < GPT; ++j) {
+        const int k = tid + NT * j;
+        if (k < sp.ngr) {
+            float4 rn;
+            rn.x = rv[j].x - alpha * qv[j].x;
+            rn.y = rv[j].y - alpha * qv[j].y;
+            rn.z = rv[j].z - alpha * qv[j].z;
+            rn.w = rv[j].w - alpha * qv[j].w;
+            float4 dn;
+            dn.x = dv[j].x + alpha * pv[j].x;
+            dn.y = dv[j].y + alpha * pv[j].y;
+            dn.z = dv[j].z + alpha * pv[j].z;
+            dn.w = dv[j].w + alpha * pv[j].w;
+            D[k] = dn;
+            R[k] = rn;
+            acc += (double)rn.x * (double)rn.x + (double)rn.y * (double)rn.y + (double)rn.z * (double)rn.z +
+                   (double)rn.w * (double)rn.w;
         }
     }
+    if (hh) {
+        const float rn = rh - alpha * qh;
+        d32[eh] = dh + alpha * ph;
+        r32[eh] = rn;
+        acc += (double)rn * (double)rn;
+    }
+    if (ht) {
+        const float rn = rt - alpha * qt;
+        d32[et] = dt + alpha * pt;
+        r32[et] = rn;
+        acc += (double)rn * (double)rn;
+    }
     acc = block_sum(acc, red);
-    if (threadIdx.x == 0) partial_rr_new[(long long)s * g.pmax + c] = acc;
+    if (tid == 0) partial_rr_new[(long long)s * g.pmax + c] = acc;
 }
 
-// p32 = z32 + (rho_new / rho) p32; the inner solve of slice s stops when
-// ||r32||^2 <= eta2[s] (its right-hand side has unit norm) or at maxit
-// iterations in all (counted over the refinement steps).
+// p32 = z32 + (rho_new / rho) p32 on active slices; next flags from ||r32||^2 <= eta2[s] and the count.
 __global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float* __restrict__ z32,
                                                      float* __restrict__ p32,
                                                      const double* partial_rho, int nrho,
@@ -723,19 +786,47 @@ __global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float*
     const long long so = (long long)s * g.stride;
     long long lo, hi;
     chunk_range(g, c, lo, hi);
-    const long long e0 = so + lo + threadIdx.x, last = so + hi - 1;
-    float zv[PT], pv[PT];
+    const long long base = so + lo;
+    const Split16 sp = split16(base, (int)(hi - lo));
+    const int tid = threadIdx.x;
+    const float4* Z = (const float4*)(z32 + base + sp.head);
+    float4* P = (float4*)(p32 + base + sp.head);
+    float4 zv[GPT], pv[GPT];
 #pragma unroll
-    for (int k = 0; k < PT; ++k) {
-        const long long e = e0 + (long long)k * NT < last ? e0 + (long long)k * NT : last;
-        zv[k] = z32[e];
-        pv[k] = p32[e];
+    for (int j = 0; j < GPT; ++j) {
+        const int k = tid + NT * j;
+        if (k < sp.ngr) {
+            zv[j] = Z[k];
+            pv[j] = P[k];
+        }
+    }
+    const bool hh = tid < sp.head, ht = tid < sp.len - sp.tail0;
+    const long long eh = base + tid, et = base + sp.tail0 + tid;
+    float zh = 0.f, ph = 0.f, zt = 0.f, pt = 0.f;
+    if (hh) {
+        zh = z32[eh];
+        ph = p32[eh];
+    }
+    if (ht) {
+        zt = z32[et];
+        pt = p32[et];
     }
     const float beta = (float)(slice_sum(partial_rho_new, g.pmax, s, nrho_new) / slice_sum(partial_rho, g.pmax, s, nrho));
 #pragma unroll
-    for (int k = 0; k < PT; ++k)
-        if (e0 + (long long)k * NT <= last) p32[e0 + (long long)k * NT] = zv[k] + beta * pv[k];
-    if (c == 0 && threadIdx.x == 0) {
+    for (int j = 0; j < GPT; ++j) {
+        const int k = tid + NT * j;
+        if (k < sp.ngr) {
+            float4 pn;
+            pn.x = zv[j].x + beta * pv[j].x;
+            pn.y = zv[j].y + beta * pv[j].y;
+            pn.z = zv[j].z + beta * pv[j].z;
+            pn.w = zv[j].w + beta * pv[j].w;
+            P[k] = pn;
+        }
+    }
+    if (hh) p32[eh] = zh + beta * ph;
+    if (ht) p32[et] = zt + beta * pt;
+    if (c == 0 && tid == 0) {
         const double rrn = slice_sum(partial_rr_new, g.pmax, s, g.nchunk);
         const int it = iters[s] + 1;
         iters[s] = it;
@@ -2094,10 +2185,13 @@ int launch_mx_begin(const Geom* g, const PropDesc* desc, int S, double* xbase, c
     return (int)hipGetLastError();
 }
 
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
 int launch_mx_update(const Geom* g, int S, float* d32, float* r32, const float* p32, const float* q32,
                      const double* partial_rho, int nrho, const double* partial_pq, int npq, double* partial_rr_new,
                      const int* active, void* stream) {
     if (S <= 0) return 0;
+    if (!aligned16(d32) || !aligned16(r32) || !aligned16(p32) || !aligned16(q32)) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL(k_mx_update, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, S, d32,
                        r32, p32, q32, partial_rho, nrho, partial_pq, npq, partial_rr_new, active);
     return (int)hipGetLastError();
@@ -2108,6 +2202,7 @@ int launch_mx_direction(const Geom* g, int S, const float* z32, float* p32, cons
                         int maxit, const int* active, int* active_next, int* iters, int* host_next,
                         int* host_iters, void* stream) {
     if (S <= 0) return 0;
+    if (!aligned16(z32) || !aligned16(p32)) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL(k_mx_direction, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, S,
                        z32, p32, partial_rho, nrho, partial_rho_new, nrho_new, partial_rr_new, eta2, maxit, active,
                        active_next, iters, host_next, host_iters);
