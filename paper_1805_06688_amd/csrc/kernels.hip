@@ -133,11 +133,36 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__device__ __forceinline__ double slice_sum(const double* partial, int pmax, int s, int count) {
+// Sums of a slice's partials (entries i < count of row s) by the whole block in a fixed order: thread t adds
+// entries t, t + NT, ... in turn, then the wave tree and waves 0..3, so every block and batch that reduces a
+// slice gets the same value.  Every thread of the block must call these (no divergent call sites); all get
+// the sums.  red holds 8 doubles.
+__device__ __forceinline__ void slice_sums(const double* pa, int na, const double* pb, int nb, int pmax, int s,
+                                           double* red, double& a, double& b) {
+    const int t = threadIdx.x;
+    pa += (long long)s * pmax;
+    pb += (long long)s * pmax;
+    double va = 0.0, vb = 0.0;
+    for (int i = t; i < na; i += NT) va += pa[i];
+    for (int i = t; i < nb; i += NT) vb += pb[i];
+    va = wave_sum(va);
+    vb = wave_sum(vb);
+    const int w = t >> 6;
+    __syncthreads();
+    if ((t & 63) == 0) {
+        red[w] = va;
+        red[4 + w] = vb;
+    }
+    __syncthreads();
+    a = (red[0] + red[1]) + (red[2] + red[3]);
+    b = (red[4] + red[5]) + (red[6] + red[7]);
+}
+
+__device__ __forceinline__ double slice_sum(const double* partial, int count, int pmax, int s, double* red) {
     const double* p = partial + (long long)s * pmax;
-    double acc = 0.0;
-    for (int i = 0; i < count; ++i) acc += p[i];
-    return acc;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < count; i += NT) v += p[i];
+    return block_sum(v, red);
 }
 
 // Epilogue of an operator tile: epi[jl][il] (ld TT + 1) holds A v on the tile; writes
@@ -610,9 +635,9 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
     int s, c;
     decode_block(g.nchunk, S, s, c);
     if (s < 0) return;
-    __shared__ double red[4];
-    const double b2 = slice_sum(partial_bb, g.pmax, s, np);
-    const double r2 = slice_sum(partial_rr, g.pmax, s, np);
+    __shared__ double red[8];
+    double b2, r2;
+    slice_sums(partial_bb, np, partial_rr, np, g.pmax, s, red, b2, r2);
     const bool zero = !(b2 > 0.0);
     // a slice whose previous step was settled by its own inner test is done, whatever the other slices of
     // the batch need (so that each slice's result does not depend on the batch)
@@ -689,7 +714,7 @@ __global__ __launch_bounds__(NT) void k_mx_update(Geom g, int S, float* __restri
     int s, c;
     decode_block(g.nchunk, S, s, c);
     if (s < 0 || !active[s]) return;
-    __shared__ double red[4];
+    __shared__ double red[8];
     const long long so = (long long)s * g.stride;
     long long lo, hi;
     chunk_range(g, c, lo, hi);
@@ -727,7 +752,9 @@ __global__ __launch_bounds__(NT) void k_mx_update(Geom g, int S, float* __restri
         pt = p32[et];
         qt = q32[et];
     }
-    const float alpha = (float)(slice_sum(partial_rho, g.pmax, s, nrho) / slice_sum(partial_pq, g.pmax, s, npq));
+    double rho, pq;
+    slice_sums(partial_rho, nrho, partial_pq, npq, g.pmax, s, red, rho, pq);
+    const float alpha = (float)(rho / pq);
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < GPT; ++j) {
@@ -783,6 +810,7 @@ __global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float*
         }
         return;
     }
+    __shared__ double red[8];
     const long long so = (long long)s * g.stride;
     long long lo, hi;
     chunk_range(g, c, lo, hi);
@@ -811,7 +839,9 @@ __global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float*
         zt = z32[et];
         pt = p32[et];
     }
-    const float beta = (float)(slice_sum(partial_rho_new, g.pmax, s, nrho_new) / slice_sum(partial_rho, g.pmax, s, nrho));
+    double rhon, rho;
+    slice_sums(partial_rho_new, nrho_new, partial_rho, nrho, g.pmax, s, red, rhon, rho);
+    const float beta = (float)(rhon / rho);
 #pragma unroll
     for (int j = 0; j < GPT; ++j) {
         const int k = tid + NT * j;
@@ -826,8 +856,9 @@ __global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float*
     }
     if (hh) p32[eh] = zh + beta * ph;
     if (ht) p32[et] = zt + beta * pt;
-    if (c == 0 && tid == 0) {
-        const double rrn = slice_sum(partial_rr_new, g.pmax, s, g.nchunk);
+    if (c != 0) return;
+    const double rrn = slice_sum(partial_rr_new, g.nchunk, g.pmax, s, red);
+    if (tid == 0) {
         const int it = iters[s] + 1;
         iters[s] = it;
         if (host_iters) host_iters[s] = it;
@@ -887,8 +918,9 @@ __global__ __launch_bounds__(NT) void k_cg_start(Geom g, const PropDesc* __restr
     decode_block(g.nchunk, S, s, c);
     if (s < 0) return;
     const PropDesc d = desc[s];
-    const double b2 = slice_sum(partial_bb, g.pmax, s, nbb);
-    const double r2 = slice_sum(partial_rr, g.pmax, s, nrr);
+    __shared__ double red[8];
+    double b2, r2;
+    slice_sums(partial_bb, nbb, partial_rr, nrr, g.pmax, s, red, b2, r2);
     double* x = xbase + d.x * g.stride;
     const double* z = zws + (long long)s * g.stride;
     double* p = pws + (long long)s * g.stride;
@@ -917,9 +949,9 @@ __global__ __launch_bounds__(NT) void k_cg_update(Geom g, const PropDesc* __rest
     int s, c;
     decode_block(g.nchunk, S, s, c);
     if (s < 0 || !active[s]) return;
-    __shared__ double red[4];
-    const double rho = slice_sum(partial_rho, g.pmax, s, nrho);
-    const double pq = slice_sum(partial_pq, g.pmax, s, npq);
+    __shared__ double red[8];
+    double rho, pq;
+    slice_sums(partial_rho, nrho, partial_pq, npq, g.pmax, s, red, rho, pq);
     const double alpha = rho / pq;
     double* __restrict__ x = xbase + desc[s].x * g.stride;
     const long long so = (long long)s * g.stride;
@@ -973,9 +1005,7 @@ __global__ __launch_bounds__(NT) void k_cg_direction(Geom g, int S, const double
         }
         return;
     }
-    const double rho = slice_sum(partial_rho, g.pmax, s, nrho);
-    const double rhon = slice_sum(partial_rho_new, g.pmax, s, nrho_new);
-    const double beta = rhon / rho;
+    __shared__ double red[8];
     const long long so = (long long)s * g.stride;
     const double* __restrict__ z = zws + so;
     double* __restrict__ p = pws + so;
@@ -989,11 +1019,15 @@ __global__ __launch_bounds__(NT) void k_cg_direction(Geom g, int S, const double
         zv[k] = z[e];
         pv[k] = p[e];
     }
+    double rho, rhon;
+    slice_sums(partial_rho, nrho, partial_rho_new, nrho_new, g.pmax, s, red, rho, rhon);
+    const double beta = rhon / rho;
 #pragma unroll
     for (int k = 0; k < PT; ++k)
         if (e0 + (long long)k * NT <= last) p[e0 + (long long)k * NT] = zv[k] + beta * pv[k];
-    if (c == 0 && threadIdx.x == 0) {
-        const double rrn = slice_sum(partial_rr_new, g.pmax, s, g.nchunk);
+    if (c != 0) return;
+    const double rrn = slice_sum(partial_rr_new, g.nchunk, g.pmax, s, red);
+    if (threadIdx.x == 0) {
         const int it = iters[s] + 1;
         iters[s] = it;
         if (host_iters) host_iters[s] = it;
