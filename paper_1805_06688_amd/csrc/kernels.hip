@@ -1546,7 +1546,7 @@ constexpr int FNT = 512;             // threads per workgroup: 8 waves, one inpu
 template <int L>
 struct FftLen {
     static constexpr int NP = L / 64;                     // points per lane
-    static constexpr int PAD = L + L / 8;                 // padded LDS length of one transform
+    static constexpr int PAD = L + L / (L == 1024 ? 16 : 8);   // padded LDS length of one transform
     static constexpr int FE = (L / 2 * FJ + FNT - 1) / FNT;   // epilogue elements per thread (n <= L / 2)
 };
 
@@ -1571,7 +1571,11 @@ template <typename T>
 __device__ __forceinline__ cpx<T> cmi(cpx<T> a) {   // a * (-i)
     return {a.y, -a.x};
 }
-__device__ __forceinline__ int fpidx(int k) { return k + (k >> 3); }
+// LDS index of entry k of a transform: one pad entry per 8 (512 points) or 16 (1024 points) entries, so that
+// the first pass's stores (lane l writes entries 8 l + r, resp. 16 l + r) hit distinct banks in every group of
+// 16 lanes (strides of 9 and 17 entries), and runs of consecutive entries stay conflict-free.
+template <int L>
+__device__ __forceinline__ int fpidx(int k) { return L == 1024 ? k + (k >> 4) : k + (k >> 3); }
 
 // Forward DFT of 8 points in registers (two radix-2 splittings in frequency).
 template <typename T>
@@ -1612,19 +1616,19 @@ template <typename T>
 __device__ __forceinline__ void fft512(cpx<T>* a, cpx<T>* buf, const cpx<T>* __restrict__ tw, int lane) {
     dft8(a);                                              // sub-transforms of length 1 -> 8
 #pragma unroll
-    for (int r = 0; r < 8; ++r) buf[fpidx(8 * lane + r)] = a[r];
+    for (int r = 0; r < 8; ++r) buf[fpidx<512>(8 * lane + r)] = a[r];
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) a[r] = buf[fpidx(lane + 64 * r)];
+    for (int r = 0; r < 8; ++r) a[r] = buf[fpidx<512>(lane + 64 * r)];
     twiddle8(a, tw[(lane & 7) * 8]);                      // 8 -> 64
     dft8(a);
     const int d1 = (lane >> 3) * 64 + (lane & 7);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) buf[fpidx(d1 + 8 * r)] = a[r];
+    for (int r = 0; r < 8; ++r) buf[fpidx<512>(d1 + 8 * r)] = a[r];
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) a[r] = buf[fpidx(lane + 64 * r)];
+    for (int r = 0; r < 8; ++r) a[r] = buf[fpidx<512>(lane + 64 * r)];
     twiddle8(a, tw[lane]);                                // 64 -> 512
     dft8(a);
     __builtin_amdgcn_wave_barrier();
@@ -1658,14 +1662,14 @@ template <typename T>
 __device__ __forceinline__ void fft1024(cpx<T>* a, cpx<T>* buf, const cpx<T>* __restrict__ tw, int lane) {
     dft16(a);                                             // length 1 -> 16
 #pragma unroll
-    for (int r = 0; r < 16; ++r) buf[fpidx(16 * lane + r)] = a[r];
+    for (int r = 0; r < 16; ++r) buf[fpidx<1024>(16 * lane + r)] = a[r];
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int half = 0; half < 2; ++half) {                // 16 -> 128
         const int j = lane + 64 * half;
         cpx<T>* v = a + 8 * half;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = buf[fpidx(j + 128 * r)];
+        for (int r = 0; r < 8; ++r) v[r] = buf[fpidx<1024>(j + 128 * r)];
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -1676,7 +1680,7 @@ __device__ __forceinline__ void fft1024(cpx<T>* a, cpx<T>* buf, const cpx<T>* __
         dft8(v);
         const int d = (j >> 4) * 128 + (j & 15);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) buf[fpidx(d + 16 * r)] = v[r];
+        for (int r = 0; r < 8; ++r) buf[fpidx<1024>(d + 16 * r)] = v[r];
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -1684,7 +1688,7 @@ __device__ __forceinline__ void fft1024(cpx<T>* a, cpx<T>* buf, const cpx<T>* __
         const int j = lane + 64 * half;
         cpx<T>* v = a + 8 * half;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = buf[fpidx(j + 128 * r)];
+        for (int r = 0; r < 8; ++r) v[r] = buf[fpidx<1024>(j + 128 * r)];
         twiddle8(v, tw[j]);
         dft8(v);
     }
@@ -1849,7 +1853,7 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
     }
     fft<T, L>(a, buf, tw, lane);
 #pragma unroll
-    for (int r = 0; r < NP; ++r) buf[fpidx(lane + 64 * r)] = a[r];
+    for (int r = 0; r < NP; ++r) buf[fpidx<L>(lane + 64 * r)] = a[r];
     __syncthreads();
 
     // ---- spectra of the output pair (lines oa = l0 + 2 wave, ob = oa + 1) ----
@@ -1869,7 +1873,7 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
 #pragma unroll
         for (int r = 0; r < NP; ++r) {
             const int k = lane + 64 * r, kk = (FL - k) & (FL - 1);
-            const cpx<T> z1 = Z1[fpidx(k)], z1c = Z1[fpidx(kk)], z2 = Z2[fpidx(k)], z2c = Z2[fpidx(kk)];
+            const cpx<T> z1 = Z1[fpidx<L>(k)], z1c = Z1[fpidx<L>(kk)], z2 = Z2[fpidx<L>(k)], z2c = Z2[fpidx<L>(kk)];
             // unpack: first line (z + conj z(-k)) / 2, second line (z - conj z(-k)) / (2 i)
             const cpx<T> vm = {half * (z1.x + z1c.x), half * (z1.y - z1c.y)};
             const cpx<T> v0 = {half * (z1.y + z1c.y), half * (z1c.x - z1.x)};
