@@ -1870,8 +1870,15 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
         // j +- 1 (16, 8; 4, 2, 0)
         const T ma0 = mlen * (g.q1 ? T(16) : T(6)), ma1 = mlen * (g.q1 ? T(8) : T(2));
         const T mb0 = mlen * (g.q1 ? T(4) : T(1)), mb1 = mlen * (g.q1 ? T(2) : T(1)), mbs = g.q1 ? T(0) : mlen;
-#pragma unroll
-        for (int r = 0; r < NP; ++r) {
+        // The lines are real, the kernel of A_1 is symmetric (real spectrum; its rounding residue in the
+        // imaginary part is dropped) and the spectrum of A_2^T is the conjugate of A_2's, so the combined
+        // spectra at L - k are the conjugates of those at k.  Each lane combines its rows r < NP / 2 (k < L / 2)
+        // and passes the value at L - k to the lane that holds it: lane 64 - lane, row NP - 1 - r (lane 0
+        // keeps it: row NP - r).  Lane 0 also combines row NP / 2 itself (k = L / 2).
+        constexpr int NH = NP / 2;
+        const int src = (64 - lane) & 63;
+        // packed output at k (own) and at L - k (mirror) of row r
+        auto combine = [&](int r, cpx<T>& own, cpx<T>& mirror) {
             const int k = lane + 64 * r, kk = (FL - k) & (FL - 1);
             const cpx<T> z1 = Z1[fpidx<L>(k)], z1c = Z1[fpidx<L>(kk)], z2 = Z2[fpidx<L>(k)], z2c = Z2[fpidx<L>(kk)];
             // unpack: first line (z + conj z(-k)) / 2, second line (z - conj z(-k)) / (2 i)
@@ -1879,23 +1886,32 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
             const cpx<T> v0 = {half * (z1.y + z1c.y), half * (z1c.x - z1.x)};
             const cpx<T> vp = {half * (z2.x + z2c.x), half * (z2.y - z2c.y)};
             const cpx<T> vq = {half * (z2.y + z2c.y), half * (z2c.x - z2.x)};
-            cpx<T> c1 = K[k], c2 = K[FL + k], c3 = K[2 * FL + k];
+            T c1 = K[k].x;
+            cpx<T> c2 = K[FL + k];
             if (DIR == 0) {                  // (the y pass applies theta to its output instead)
-                c1 = {theta * c1.x, theta * c1.y};
-                c2 = {theta * c2.x, theta * c2.y};
-                c3 = {theta * c3.x, theta * c3.y};
                 const cpx<T> w = tw[k];
-                c1.x += ma0 + ma1 * w.x;
-                c2.x += mb0 + mb1 * w.x;
-                c2.y -= mbs * w.y;
-                c3.x += mb0 + mb1 * w.x;
-                c3.y += mbs * w.y;
+                c1 = theta * c1 + (ma0 + ma1 * w.x);
+                c2 = {theta * c2.x + (mb0 + mb1 * w.x), theta * c2.y - mbs * w.y};
             }
-            const cpx<T> xa = cadd(cadd(cmul(c1, v0), cmul(c2, vp)), cmul(c3, vm));
-            const cpx<T> xb = cadd(cadd(cmul(c1, vp), cmul(c2, vq)), cmul(c3, v0));
-            // W = xa + i xb; the inverse transform is conj(FFT(conj W))
-            a[r] = {xa.x - xb.y, -(xa.y + xb.x)};
+            // xa = c1 v0 + c2 vp + conj(c2) vm,  xb = c1 vp + c2 vq + conj(c2) v0
+            const cpx<T> sa = cadd(vp, vm), da = csub(vp, vm), sb = cadd(vq, v0), db = csub(vq, v0);
+            const cpx<T> xa = {c1 * v0.x + c2.x * sa.x - c2.y * da.y, c1 * v0.y + c2.x * sa.y + c2.y * da.x};
+            const cpx<T> xb = {c1 * vp.x + c2.x * sb.x - c2.y * db.y, c1 * vp.y + c2.x * sb.y + c2.y * db.x};
+            // W = xa + i xb; the inverse transform is conj(FFT(conj W)); at L - k, conj W = xa - i xb
+            own = {xa.x - xb.y, -(xa.y + xb.x)};
+            mirror = {xa.x + xb.y, xa.y - xb.x};
+        };
+#pragma unroll
+        for (int r = 0; r < NH; ++r) {
+            cpx<T> m;
+            combine(r, a[r], m);
+            const cpx<T> got = {__shfl(m.x, src, 64), __shfl(m.y, src, 64)};
+            if (lane != 0) a[NP - 1 - r] = got;
+            if (r > 0 && lane == 0) a[NP - r] = m;
         }
+        cpx<T> mid, unused;
+        combine(NH, mid, unused);
+        if (lane == 0) a[NH] = mid;
     }
     __syncthreads();
     if (work) fft<T, L>(a, buf, tw, lane);      // a[r] = conj of the packed output at lane + 64 r
