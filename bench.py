@@ -67,11 +67,13 @@ def fft_flops(nx, ny):
     """Flops of one operator application by FFT as the kernels compute them: per direction ceil(lines / 2)
     packed line pairs, each one forward and one inverse transform of L points (L = 512: a radix-8 DFT (56 flops)
     and two twiddled ones (78 + 56) per lane, 64 lanes: 20736; L = 1024: a radix-16 DFT (192) and two passes of
-    two twiddled radix-8 DFTs (268 each): 46592) and the spectral combination with the three kernels (76 flops
-    per frequency)."""
+    two twiddled radix-8 DFTs (268 each): 46592) and the spectral combination at L / 2 + 64 frequencies (half
+    the spectrum plus one row, the other half being conjugates): 59 flops each in the x pass (unpacking 16,
+    kernel and mass coefficients 11, the two outputs 32) and 48 in the y pass (no coefficients)."""
     L = 512 if 2 * max(nx, ny) - 1 <= 512 else 1024
     tflops = 20736 if L == 512 else 46592
-    return float(((ny + 1) // 2 + (nx + 1) // 2) * (2 * tflops + 76 * L)), L
+    freq = L // 2 + 64
+    return float(((ny + 1) // 2) * (2 * tflops + 59 * freq) + ((nx + 1) // 2) * (2 * tflops + 48 * freq)), L
 
 
 def kernel_models(nx, ny, fft, precond):
