@@ -1100,7 +1100,12 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     CHK(tile_variant(h, &ps, S, &tv));
     HIPCHK(launch_cg_init_x(g, ps.d, S, ubase, x0base, (x0base && warm && h->opt.warm_start) ? 1 : 0, xbase, st));
     HIPCHK(op_resid(h, tv, ps, xbase, h->prr[0]));
-    if (pc) HIPCHK(precondition(h->prz[0], nullptr));
+    const bool prof = h->prof_on;
+    if (pc) {
+        if (prof) CHK(prof_record(h, MGRIT_PROF_PRECOND));
+        HIPCHK(precondition(h->prz[0], nullptr));
+        if (prof) CHK(prof_record(h, -1));
+    }
     double* zws = pc ? h->z : h->r;
     double** prho = pc ? h->prz : h->prr;        // rho = r.z (r.r without preconditioner)
     HIPCHK(launch_cg_start(g, ps.d, S, ubase, xbase, zws, h->p, h->pbb, nop, h->prr[0], nop, rtol2, h->bb, h->act[0],
@@ -1113,7 +1118,6 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
     // The first chunk covers what this pass needed last time, later chunks are
     // short, so few launches find every slice converged.
     const int first = ps.last_iters > 0 ? ps.last_iters : (pc ? 8 : 16);
-    const bool prof = h->prof_on;
     auto iter = [&](int c0, int nr) -> int {
         const int nxt = c0 ^ 1;
         if (prof) CHK(prof_record(h, tv));
@@ -1153,7 +1157,8 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
         h->prof_slices[tv] += its;
         h->prof_slices[MGRIT_PROF_UPDATE64] += its;
         h->prof_slices[MGRIT_PROF_DIRECTION64] += its;
-        if (pc) h->prof_slices[MGRIT_PROF_PRECOND] += its;
+        // the preconditioner also starts the pass, on every slice
+        if (pc) h->prof_slices[MGRIT_PROF_PRECOND] += its + S;
     }
     h->phi_count += S;
     return 0;
@@ -1213,9 +1218,12 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
             else CHK(tile_variant(h, &ps, S, &tv32, true));
             op32_class = h->opt.precision == MGRIT_PREC_MIXED_BF16 ? MGRIT_PROF_OP_BF16 : MGRIT_PROF_OP32_T64 + tv32;
         }
-        if (pc)
+        if (pc) {
+            if (prof) CHK(prof_record(h, MGRIT_PROF_PRECOND));
             HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, h->p32, h->tb1, h->tb2, h->prz[0],
                                       h->act[0], st));
+            if (prof) CHK(prof_record(h, -1));
+        }
         int cur = 0, it = 0, nact = 0;
         int nrho = pc ? npc : nc;
         const int nrho_next = pc ? npc : nc;
@@ -1284,7 +1292,8 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
         h->prof_slices[op32_class] += its;
         h->prof_slices[MGRIT_PROF_UPDATE32] += its;
         h->prof_slices[MGRIT_PROF_DIRECTION32] += its;
-        if (pc) h->prof_slices[MGRIT_PROF_PRECOND] += its;
+        // the preconditioner also starts each refinement step of its active slices
+        if (pc) h->prof_slices[MGRIT_PROF_PRECOND] += its + steps;
     }
     h->phi_count += S;
     return 0;
