@@ -419,7 +419,10 @@ int mgrit_server_create(size_t device_budget_bytes, int max_concurrent, mgrit_se
 int mgrit_server_set_group_limit(mgrit_server* s, int max_members);
 /* Queue one solve (arguments as in mgrit_setup and mgrit_solve; the problem's
  * time grid is copied).  Returns EINVAL at once for invalid arguments or a
- * footprint above the whole budget.  *id identifies the request. */
+ * footprint above the whole budget.  *id identifies the request.  The solve
+ * runs on the server's own stream, which waits for no other stream: device
+ * inputs must be complete when this is called, and F, psi0 and U must stay
+ * allocated until mgrit_server_wait (or poll) reports the request done. */
 int mgrit_server_submit(mgrit_server* s, const mgrit_problem* prob, const mgrit_options* opt, const double* F,
                         const double* psi0, double* U, int mem, long long* id);
 /* Block until request `id` has finished; fill *info (may be NULL). */

@@ -537,6 +537,10 @@ class Server:
                 out = torch.empty((Nt + 1) * n, dtype=torch.float64, device=psi0.device)
             else:
                 out = np.empty((Nt + 1) * n)
+        if mem == MEM_DEVICE:
+            # the server's stream waits for no other: finish the work that wrote the inputs first
+            import torch
+            torch.cuda.current_stream(psi0.device).synchronize()
         rid = ctypes.c_longlong()
         _check(_lib.mgrit_server_submit(self._s, ctypes.byref(p), ctypes.byref(o), _ptr(F, mem, Nt * n),
                                         _ptr(psi0, mem, n), _ptr(out, mem, (Nt + 1) * n), mem, ctypes.byref(rid)))
