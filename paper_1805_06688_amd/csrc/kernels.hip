@@ -617,6 +617,24 @@ __global__ __launch_bounds__(NT) void k_apply_bf16(Geom g, Seqs32 sq0, const Pro
                              red, partial + (long long)s * g.pmax);
 }
 
+// The BF16 image of r32 that the first preconditioner product reads: slice s at s npx npy, row j at j npx
+// (the zero-padded layout of the products' operands; the padding is zeroed once).  Element e = j n_x + k of
+// the slice goes to row j, column k (j from a float quotient, corrected to the exact one).
+__device__ __forceinline__ void put_rimg(const Geom& g, __bf16* __restrict__ rimg, long long sob, long long e,
+                                         float v) {
+    const int nx = g.nx;
+    int j = (int)((float)e * (1.0f / (float)nx));
+    int k = (int)e - j * nx;
+    if (k < 0) {
+        --j;
+        k += nx;
+    } else if (k >= nx) {
+        ++j;
+        k -= nx;
+    }
+    rimg[sob + (long long)j * (g.tiles_x[0] * 64) + k] = (__bf16)v;
+}
+
 // Start of a refinement step from the FP64 residual (np partials of ||b||^2
 // and ||r||^2 per slice): outer flag ||r|| > rtol ||b||, scale ||r||, inner
 // tolerance eta^2 = max(rtol^2 ||b||^2 / ||r||^2, eta_min^2), r32 = r / ||r||,
@@ -631,7 +649,7 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
                                                  int first, double* bb, double* scale, double* eta2, int* oact,
                                                  int* iact, int* iters, float* r32, float* d32, float* p32,
                                                  double* partial_rr32, int* host_act, int* host_iters,
-                                                 const int* trust_in, int* trust_out) {
+                                                 const int* trust_in, int* trust_out, __bf16* rimg) {
     int s, c;
     decode_block(g.nchunk, S, s, c);
     if (s < 0) return;
@@ -643,6 +661,7 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
     // the batch need (so that each slice's result does not depend on the batch)
     const bool settled = !first && trust_in[s];
     const bool active = !settled && !zero && r2 > rtol2 * b2;
+    const long long sob = (long long)s * (g.tiles_x[0] * 64) * (g.tiles_y[0] * 64);
     const long long so = (long long)s * g.stride;
     long long lo, hi;
     chunk_range(g, c, lo, hi);
@@ -659,6 +678,7 @@ __global__ __launch_bounds__(NT) void k_mx_begin(Geom g, const PropDesc* __restr
             r32[so + e] = rv;
             d32[so + e] = 0.0f;
             if (p32) p32[so + e] = rv;
+            if (rimg) put_rimg(g, rimg, sob, e, rv);
             acc += (double)rv * (double)rv;
         }
         if (p32) {
@@ -710,7 +730,8 @@ __device__ __forceinline__ Split16 split16(long long base, int len) {
 __global__ __launch_bounds__(NT) void k_mx_update(Geom g, int S, float* __restrict__ d32, float* __restrict__ r32,
                                                   const float* __restrict__ p32, const float* __restrict__ q32,
                                                   const double* partial_rho, int nrho, const double* partial_pq,
-                                                  int npq, double* partial_rr_new, const int* active) {
+                                                  int npq, double* partial_rr_new, const int* active,
+                                                  __bf16* __restrict__ rimg) {
     int s, c;
     decode_block(g.nchunk, S, s, c);
     if (s < 0 || !active[s]) return;
@@ -719,6 +740,7 @@ __global__ __launch_bounds__(NT) void k_mx_update(Geom g, int S, float* __restri
     long long lo, hi;
     chunk_range(g, c, lo, hi);
     const long long base = so + lo;
+    const long long sob = (long long)s * (g.tiles_x[0] * 64) * (g.tiles_y[0] * 64);
     const Split16 sp = split16(base, (int)(hi - lo));
     const int tid = threadIdx.x;
     float4* D = (float4*)(d32 + base + sp.head);
@@ -772,6 +794,13 @@ __global__ __launch_bounds__(NT) void k_mx_update(Geom g, int S, float* __restri
             dn.w = dv[j].w + alpha * pv[j].w;
             D[k] = dn;
             R[k] = rn;
+            if (rimg) {
+                const long long e = lo + sp.head + 4LL * k;
+                put_rimg(g, rimg, sob, e, rn.x);
+                put_rimg(g, rimg, sob, e + 1, rn.y);
+                put_rimg(g, rimg, sob, e + 2, rn.z);
+                put_rimg(g, rimg, sob, e + 3, rn.w);
+            }
             acc += (double)rn.x * (double)rn.x + (double)rn.y * (double)rn.y + (double)rn.z * (double)rn.z +
                    (double)rn.w * (double)rn.w;
         }
@@ -780,12 +809,14 @@ __global__ __launch_bounds__(NT) void k_mx_update(Geom g, int S, float* __restri
         const float rn = rh - alpha * qh;
         d32[eh] = dh + alpha * ph;
         r32[eh] = rn;
+        if (rimg) put_rimg(g, rimg, sob, lo + tid, rn);
         acc += (double)rn * (double)rn;
     }
     if (ht) {
         const float rn = rt - alpha * qt;
         d32[et] = dt + alpha * pt;
         r32[et] = rn;
+        if (rimg) put_rimg(g, rimg, sob, lo + sp.tail0 + tid, rn);
         acc += (double)rn * (double)rn;
     }
     acc = block_sum(acc, red);
@@ -2149,7 +2180,7 @@ namespace {
 // t1 = Vx^T r ; t2 = (t1 Vy) / (1 + theta (lx + ly)) ; t1 = Vx t2 ; z = t1 Vy^T (+ r.z)
 template <typename RT>
 void fdb_chain(const Geom* g, const FdMatsB* fd, const PropDesc* desc, int S, const RT* rws, RT* zws, RT* zcopy,
-               void* t1, void* t2, double* partial_rz, const int* active, hipStream_t st) {
+               void* t1, void* t2, double* partial_rz, const int* active, const void* rimg, hipStream_t st) {
     const int npx = g->tiles_x[0] * 64, npy = g->tiles_y[0] * 64;
     if (npx <= 256 && npy <= 256 && S * g->ntiles[0] < 256) {      // batches that leave compute units idle
         const dim3 grid(grid_blocks((npx / 32) * (npy / 32), S)), blk(NT);
@@ -2157,8 +2188,12 @@ void fdb_chain(const Geom* g, const FdMatsB* fd, const PropDesc* desc, int S, co
         const __bf16* Vx = (const __bf16*)fd->Vx;
         const __bf16* VyT = (const __bf16*)fd->VyT;
         const __bf16* Vy = (const __bf16*)fd->Vy;
-        hipLaunchKernelGGL((k_fdb_gemm32<true, 0, 0, RT>), grid, blk, 0, st, *g, S, VxT, (const void*)nullptr, t1,
-                           desc, fd->lx, fd->ly, rws, (RT*)nullptr, (double*)nullptr, active);
+        if (rimg)               // the first product from the BF16 image of r (same values as rounding r here)
+            hipLaunchKernelGGL((k_fdb_gemm32<true, 1, 0, RT>), grid, blk, 0, st, *g, S, VxT, rimg, t1, desc, fd->lx,
+                               fd->ly, rws, (RT*)nullptr, (double*)nullptr, active);
+        else
+            hipLaunchKernelGGL((k_fdb_gemm32<true, 0, 0, RT>), grid, blk, 0, st, *g, S, VxT, (const void*)nullptr,
+                               t1, desc, fd->lx, fd->ly, rws, (RT*)nullptr, (double*)nullptr, active);
         hipLaunchKernelGGL((k_fdb_gemm32<false, 1, 1, RT>), grid, blk, 0, st, *g, S, VyT, (const void*)t1, t2,
                            desc, fd->lx, fd->ly, rws, (RT*)nullptr, (double*)nullptr, active);
         hipLaunchKernelGGL((k_fdb_gemm32<true, 1, 0, RT>), grid, blk, 0, st, *g, S, Vx, (const void*)t2, t1,
@@ -2172,8 +2207,12 @@ void fdb_chain(const Geom* g, const FdMatsB* fd, const PropDesc* desc, int S, co
     const __bf16* Vx = (const __bf16*)fd->Vx;
     const __bf16* VyT = (const __bf16*)fd->VyT;
     const __bf16* Vy = (const __bf16*)fd->Vy;
-    hipLaunchKernelGGL((k_fdb_gemm<true, 0, 0, RT>), grid, blk, 0, st, *g, S, VxT, (const void*)nullptr, t1, desc,
-                       fd->lx, fd->ly, rws, (RT*)nullptr, (double*)nullptr, active);
+    if (rimg)
+        hipLaunchKernelGGL((k_fdb_gemm<true, 1, 0, RT>), grid, blk, 0, st, *g, S, VxT, rimg, t1, desc, fd->lx, fd->ly,
+                           rws, (RT*)nullptr, (double*)nullptr, active);
+    else
+        hipLaunchKernelGGL((k_fdb_gemm<true, 0, 0, RT>), grid, blk, 0, st, *g, S, VxT, (const void*)nullptr, t1,
+                           desc, fd->lx, fd->ly, rws, (RT*)nullptr, (double*)nullptr, active);
     hipLaunchKernelGGL((k_fdb_gemm<false, 1, 1, RT>), grid, blk, 0, st, *g, S, VyT, (const void*)t1, t2, desc,
                        fd->lx, fd->ly, rws, (RT*)nullptr, (double*)nullptr, active);
     hipLaunchKernelGGL((k_fdb_gemm<true, 1, 0, RT>), grid, blk, 0, st, *g, S, Vx, (const void*)t2, t1, desc,
@@ -2189,14 +2228,15 @@ extern "C" {
 int launch_fdb_apply(const Geom* g, const FdMatsB* fd, const PropDesc* desc, int S, const double* rws, double* zws,
                      void* t1, void* t2, double* partial_rz, const int* active, void* stream) {
     if (S <= 0) return 0;
-    fdb_chain<double>(g, fd, desc, S, rws, zws, nullptr, t1, t2, partial_rz, active, (hipStream_t)stream);
+    fdb_chain<double>(g, fd, desc, S, rws, zws, nullptr, t1, t2, partial_rz, active, nullptr, (hipStream_t)stream);
     return (int)hipGetLastError();
 }
 
 int launch_fdb_apply32(const Geom* g, const FdMatsB* fd, const PropDesc* desc, int S, const float* r32, float* z32,
-                       float* zcopy, void* t1, void* t2, double* partial_rz, const int* active, void* stream) {
+                       float* zcopy, void* t1, void* t2, double* partial_rz, const int* active, const void* rimg,
+                       void* stream) {
     if (S <= 0) return 0;
-    fdb_chain<float>(g, fd, desc, S, r32, z32, zcopy, t1, t2, partial_rz, active, (hipStream_t)stream);
+    fdb_chain<float>(g, fd, desc, S, r32, z32, zcopy, t1, t2, partial_rz, active, rimg, (hipStream_t)stream);
     return (int)hipGetLastError();
 }
 
@@ -2225,17 +2265,18 @@ int launch_mx_begin(const Geom* g, const PropDesc* desc, int S, double* xbase, c
                     const double* partial_bb, const double* partial_rr, int np, double rtol2, double eta_min2,
                     int first, double* bb, double* scale, double* eta2, int* oact, int* iact, int* iters, float* r32,
                     float* d32, float* p32, double* partial_rr32, int* host_act, int* host_iters,
-                    const int* trust_in, int* trust_out, void* stream) {
+                    const int* trust_in, int* trust_out, void* rimg, void* stream) {
     if (S <= 0) return 0;
     const dim3 grid(grid_blocks(g->nchunk, S)), blk(NT);
     if (rws)
         hipLaunchKernelGGL(k_mx_begin<double>, grid, blk, 0, (hipStream_t)stream, *g, desc, S, xbase, rws,
                            partial_bb, partial_rr, np, rtol2, eta_min2, first, bb, scale, eta2, oact, iact, iters, r32,
-                           d32, p32, partial_rr32, host_act, host_iters, trust_in, trust_out);
+                           d32, p32, partial_rr32, host_act, host_iters, trust_in, trust_out, (__bf16*)rimg);
     else
         hipLaunchKernelGGL(k_mx_begin<float>, grid, blk, 0, (hipStream_t)stream, *g, desc, S, xbase,
                            (const float*)r32, partial_bb, partial_rr, np, rtol2, eta_min2, first, bb, scale, eta2,
-                           oact, iact, iters, r32, d32, p32, partial_rr32, host_act, host_iters, trust_in, trust_out);
+                           oact, iact, iters, r32, d32, p32, partial_rr32, host_act, host_iters, trust_in, trust_out,
+                           (__bf16*)rimg);
     return (int)hipGetLastError();
 }
 
@@ -2243,11 +2284,11 @@ static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 int launch_mx_update(const Geom* g, int S, float* d32, float* r32, const float* p32, const float* q32,
                      const double* partial_rho, int nrho, const double* partial_pq, int npq, double* partial_rr_new,
-                     const int* active, void* stream) {
+                     const int* active, void* rimg, void* stream) {
     if (S <= 0) return 0;
     if (!aligned16(d32) || !aligned16(r32) || !aligned16(p32) || !aligned16(q32)) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL(k_mx_update, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, S, d32,
-                       r32, p32, q32, partial_rho, nrho, partial_pq, npq, partial_rr_new, active);
+                       r32, p32, q32, partial_rho, nrho, partial_pq, npq, partial_rr_new, active, (__bf16*)rimg);
     return (int)hipGetLastError();
 }
 

@@ -153,6 +153,7 @@ struct mgrit_handle {
     double *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *tmp = nullptr;
     double *z = nullptr, *t1 = nullptr, *t2 = nullptr;      // preconditioner workspace
     void *tb1 = nullptr, *tb2 = nullptr;                    // BF16 preconditioner workspace
+    void* rimg = nullptr;                    // mixed precision: BF16 image of r32 (zero-padded npx x npy slices)
     FdMats fd;
     FdMatsB fdb;
     double *pbb = nullptr, *prr[2] = {nullptr, nullptr}, *ppq = nullptr, *pnorm = nullptr;
@@ -834,6 +835,12 @@ int alloc_workspace(mgrit_handle* h, int S) {
         CHK(dalloc(h, &h->mx_eta2, S));
         CHK(dalloc(h, &h->mx_oact, S));
         CHK(dalloc(h, &h->mx_trust, 2 * (size_t)S));
+        if (h->opt.precond == MGRIT_PRECOND_FD_BF16) {
+            // written where r32 is (only inside n_x x n_y): the padding stays zero
+            const size_t pb = (size_t)h->geom.tiles_x[0] * 64 * h->geom.tiles_y[0] * 64 * sizeof(unsigned short);
+            CHK(dmalloc(h, &h->rimg, S * pb));
+            HIPCHK(hipMemset(h->rimg, 0, S * pb));
+        }
         CHK(dalloc(h, &h->pout, S * nt));
         if (!h->prz[0]) {
             CHK(dalloc(h, &h->prz[0], S * nt));
@@ -1212,7 +1219,7 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
                                outer == 0 ? 1 : 0, h->bb, h->mx_scale, h->mx_eta2, h->mx_oact, h->act[0], h->iters,
                                h->r32, h->d32, pc ? nullptr : h->p32, h->prr[0], h->d_start, h->d_iters,
                                h->mx_trust + (size_t)(outer & 1) * h->Smax,
-                               h->mx_trust + (size_t)((outer + 1) & 1) * h->Smax, st));
+                               h->mx_trust + (size_t)((outer + 1) & 1) * h->Smax, h->rimg, st));
         if (tv32 < 0) {
             if (h->opt.precision == MGRIT_PREC_MIXED_BF16) tv32 = 0;     // one tile size
             else CHK(tile_variant(h, &ps, S, &tv32, true));
@@ -1221,7 +1228,7 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
         if (pc) {
             if (prof) CHK(prof_record(h, MGRIT_PROF_PRECOND));
             HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, h->p32, h->tb1, h->tb2, h->prz[0],
-                                      h->act[0], st));
+                                      h->act[0], h->rimg, st));
             if (prof) CHK(prof_record(h, -1));
         }
         int cur = 0, it = 0, nact = 0;
@@ -1233,11 +1240,11 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
             HIPCHK(op_cg32(h, tv32, ps, h->p32, h->q32, h->act[c0]));
             if (prof) CHK(prof_record(h, MGRIT_PROF_UPDATE32));
             HIPCHK(launch_mx_update(g, S, h->d32, h->r32, h->p32, h->q32, prho[c0], nr, h->ppq, nop32, h->prr[nxt],
-                                    h->act[c0], st));
+                                    h->act[c0], h->rimg, st));
             if (prof && pc) CHK(prof_record(h, MGRIT_PROF_PRECOND));
             if (pc)
                 HIPCHK(launch_fdb_apply32(g, &h->fdb, ps.d, S, h->r32, h->z32, nullptr, h->tb1, h->tb2, h->prz[nxt],
-                                          h->act[c0], st));
+                                          h->act[c0], h->rimg, st));
             if (prof) CHK(prof_record(h, MGRIT_PROF_DIRECTION32));
             HIPCHK(launch_mx_direction(g, S, zws, h->p32, prho[c0], nr, prho[nxt], nrho_next, h->prr[nxt],
                                        h->mx_eta2, maxit, h->act[c0], h->act[nxt], h->iters,
@@ -2151,6 +2158,7 @@ int mgrit_footprint(const mgrit_problem* p, const mgrit_options* o, int mem, siz
     double b = 0;
     if (pc) d += 2 * nx * nx + 2 * ny * ny + nx + ny;
     if (o->precond == MGRIT_PRECOND_FD_BF16) b += 4 * npx * npx + 4 * npy * npy + 4 * (npx + npy) + 4 * smax * npx * npy;
+    if (o->precond == MGRIT_PRECOND_FD_BF16 && o->precision != MGRIT_PREC_FP64) b += 2 * smax * npx * npy;  // r image
     if (mem == MGRIT_MEM_HOST) d += (2.0 * p->Nt + 2) * st;
     const bool fft = o->op == MGRIT_OP_FFT ||
                      (o->op == MGRIT_OP_AUTO && 2 * nx - 1 <= MGRIT_FFT_LEN && 2 * ny - 1 <= MGRIT_FFT_LEN);

@@ -183,7 +183,8 @@ int launch_fdb_apply(const Geom* g, const FdMatsB* fd, const PropDesc* desc, int
 // hold slice s at s * stride) ----
 // Same preconditioner on FP32 r32 / z32; z32 is also copied to zcopy when given.
 int launch_fdb_apply32(const Geom* g, const FdMatsB* fd, const PropDesc* desc, int S, const float* r32, float* z32,
-                       float* zcopy, void* t1, void* t2, double* partial_rz, const int* active, void* stream);
+                       float* zcopy, void* t1, void* t2, double* partial_rz, const int* active, const void* rimg,
+                       void* stream);
 // q32 = M p32 + theta_lhs A p32 (FP32 matrix cores) for active slices, partial p.q.
 int launch_apply32(const Geom* g, const Seqs32* sq, int tv, const PropDesc* desc, int S, const float* p32,
                    float* q32, double* partial_pq, const int* active, void* stream);
@@ -203,11 +204,11 @@ int launch_mx_begin(const Geom* g, const PropDesc* desc, int S, double* xbase, c
                     const double* partial_bb, const double* partial_rr, int np, double rtol2, double eta_min2,
                     int first, double* bb, double* scale, double* eta2, int* oact, int* iact, int* iters, float* r32,
                     float* d32, float* p32, double* partial_rr32, int* host_act, int* host_iters,
-                    const int* trust_in, int* trust_out, void* stream);
+                    const int* trust_in, int* trust_out, void* rimg, void* stream);
 // alpha = rho / p.q; d32 += alpha p32, r32 -= alpha q32; partial r32.r32.
 int launch_mx_update(const Geom* g, int S, float* d32, float* r32, const float* p32, const float* q32,
                      const double* partial_rho, int nrho, const double* partial_pq, int npq, double* partial_rr_new,
-                     const int* active, void* stream);
+                     const int* active, void* rimg, void* stream);
 // p32 = z32 + (rho_new / rho) p32; next flags from ||r32||^2 <= eta2[s] and the total count.
 int launch_mx_direction(const Geom* g, int S, const float* z32, float* p32, const double* partial_rho, int nrho,
                         const double* partial_rho_new, int nrho_new, const double* partial_rr_new, const double* eta2,
