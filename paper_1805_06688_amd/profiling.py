@@ -8,10 +8,12 @@
         mean value per dispatch of every counter for kernels matching REGEX
     python -m paper_1805_06688_amd.profiling source-hash
         hash of the HIP kernel sources (counters are tied to one version)
-    python -m paper_1805_06688_amd.profiling traffic FETCH_CSV WRITE_CSV CLASS REGEX [REGEX2] [--ff FF --wf WF]
+    python -m paper_1805_06688_amd.profiling traffic FETCH_CSV WRITE_CSV CLASS REGEX [REGEX2 ...] [--ff FF --wf WF]
+            [--launches-of REGEX]
         HBM bytes per launch of one kernel class of the library's instrumentation (a launch of the FFT operator
         is one dispatch of each of its two passes, REGEX and REGEX2) from a FETCH_SIZE and a WRITE_SIZE run,
-        each counter scaled by its copy-kernel factor (FF, WF; default 2, 1)
+        each counter scaled by its copy-kernel factor (FF, WF; default 2, 1); with --launches-of the launches
+        are counted by that regex's dispatches (the preconditioner runs one product kernel twice)
 """
 import json
 import csv
@@ -113,7 +115,10 @@ def _kib(path, regex, counter):
     return tot, n
 
 
-def traffic(fetch_csv, write_csv, cls, regexes, ff=2.0, wf=1.0):
+def traffic(fetch_csv, write_csv, cls, regexes, ff=2.0, wf=1.0, launches_of=None):
+    """Bytes per launch of a kernel class.  A launch is one dispatch of each REGEX, or with launches_of
+    (for a class whose launch runs one kernel more than once) the number of launches is the dispatch count
+    of that regex and the REGEXes' dispatches are summed."""
     fetch, write, counts = [], [], []
     for rx in regexes:
         f, n = _kib(fetch_csv, rx, "FETCH_SIZE")
@@ -121,6 +126,10 @@ def traffic(fetch_csv, write_csv, cls, regexes, ff=2.0, wf=1.0):
         fetch.append(f)
         write.append(w)
         counts += [n, m]
+    if launches_of:
+        _, n = _kib(fetch_csv, launches_of, "FETCH_SIZE")
+        _, m = _kib(write_csv, launches_of, "WRITE_SIZE")
+        counts = [n, m]
     if not counts[0] or len(set(counts)) != 1:
         raise SystemExit(f"dispatch counts differ or are zero: {counts}")
     n = counts[0]
@@ -151,8 +160,9 @@ if __name__ == "__main__":
         ap.add_argument("regex", nargs="+")
         ap.add_argument("--ff", type=float, default=2.0)
         ap.add_argument("--wf", type=float, default=1.0)
+        ap.add_argument("--launches-of", default=None)
         a = ap.parse_args(sys.argv[2:])
-        traffic(a.fetch_csv, a.write_csv, a.cls, a.regex, a.ff, a.wf)
+        traffic(a.fetch_csv, a.write_csv, a.cls, a.regex, a.ff, a.wf, a.launches_of)
     else:
         print(__doc__)
         sys.exit(2)
