@@ -373,7 +373,8 @@ __global__ __launch_bounds__(NT) void k_apply(Geom g, Seqs sq, const ApplyDesc* 
 }
 
 // mode 0: right-hand side b = M u + theta_rhs A u (+F), partial ||b||^2
-// mode 1: initial residual r = b - (M x + theta_lhs A x), partial ||r||^2 (ubase = x base)
+// mode 1: initial residual r = b - (M x + theta_lhs A x), partial ||r||^2 (ubase = x base; slices with
+//         active[s] = 0 keep their r and partials when a mask is given)
 // mode 2: q = M p + theta_lhs A p (active slices), partial p.q
 template <int TT, int MODE>
 __global__ __launch_bounds__(NT) void k_prop_apply(Geom g, Seqs sq0, const PropDesc* __restrict__ desc, int S,
@@ -383,7 +384,7 @@ __global__ __launch_bounds__(NT) void k_prop_apply(Geom g, Seqs sq0, const PropD
     int s, tile;
     decode_block(g.ntiles[tv], S, s, tile);
     if (s < 0) return;
-    if (MODE == 2 && active && !active[s]) return;
+    if ((MODE == 1 || MODE == 2) && active && !active[s]) return;
     __shared__ double lds[TC<TT>::LDS];
     __shared__ double red[4];
     const PropDesc d = desc[s];
@@ -900,11 +901,16 @@ __global__ __launch_bounds__(NT) void k_mx_direction(Geom g, int S, const float*
 }
 
 // x += ||r|| d32 on slices whose refinement step ran.
+// need[s] = slices whose new iterate gets an FP64 check: active in this step and not settled by their own
+// inner test (trust[s]); the others keep their residual (unchanged x, or not read again).
 __global__ __launch_bounds__(NT) void k_mx_refine(Geom g, const PropDesc* __restrict__ desc, int S, double* xbase,
-                                                  const float* d32, const double* scale, const int* oact) {
+                                                  const float* d32, const double* scale, const int* oact,
+                                                  const int* trust, int* need) {
     int s, c;
     decode_block(g.nchunk, S, s, c);
-    if (s < 0 || !oact[s]) return;
+    if (s < 0) return;
+    if (c == 0 && threadIdx.x == 0) need[s] = (oact[s] && !trust[s]) ? 1 : 0;
+    if (!oact[s]) return;
     double* x = xbase + desc[s].x * g.stride;
     const float* d = d32 + (long long)s * g.stride;
     const double a = scale[s];
@@ -1797,7 +1803,7 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
     int s, blk;
     decode_block(nb, S, s, blk);
     if (s < 0) return;
-    if (MODE == 2 && active && !active[s]) return;
+    if ((MODE == 1 || MODE == 2) && active && !active[s]) return;
     constexpr int NP = FftLen<L>::NP, FPAD = FftLen<L>::PAD, FL = L;
     __shared__ __attribute__((aligned(16))) cpx<T> lds[8 * FPAD];
     __shared__ double red[8];
@@ -2119,9 +2125,9 @@ int launch_cg_init_x(const Geom* g, const PropDesc* desc, int S, const double* u
 }
 
 int launch_init_residual(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc, int S, const double* xbase,
-                         const double* bws, double* rws, double* partial_rr, void* stream) {
+                         const double* bws, double* rws, double* partial_rr, const int* mask, void* stream) {
     if (S <= 0) return 0;
-    prop_apply<1>(g, sq, tv, desc, S, xbase, nullptr, bws, rws, partial_rr, nullptr, (hipStream_t)stream);
+    prop_apply<1>(g, sq, tv, desc, S, xbase, nullptr, bws, rws, partial_rr, mask, (hipStream_t)stream);
     return (int)hipGetLastError();
 }
 
@@ -2305,10 +2311,10 @@ int launch_mx_direction(const Geom* g, int S, const float* z32, float* p32, cons
 }
 
 int launch_mx_refine(const Geom* g, const PropDesc* desc, int S, double* xbase, const float* d32,
-                     const double* scale, const int* oact, void* stream) {
+                     const double* scale, const int* oact, const int* trust, int* need, void* stream) {
     if (S <= 0) return 0;
     hipLaunchKernelGGL(k_mx_refine, dim3(grid_blocks(g->nchunk, S)), dim3(NT), 0, (hipStream_t)stream, *g, desc, S,
-                       xbase, d32, scale, oact);
+                       xbase, d32, scale, oact, trust, need);
     return (int)hipGetLastError();
 }
 
@@ -2353,9 +2359,10 @@ int launch_fft_rhs(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S
 }
 
 int launch_fft_init_residual(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const double* xbase,
-                             const double* bws, double* rws, double* partial_rr, double* pbuf, void* stream) {
+                             const double* bws, double* rws, double* partial_rr, double* pbuf, const int* mask,
+                             void* stream) {
     if (S <= 0) return 0;
-    fft_op<double, 1>(g, pl, desc, S, xbase, bws, nullptr, rws, pbuf, -1.0, 2, partial_rr, nullptr,
+    fft_op<double, 1>(g, pl, desc, S, xbase, bws, nullptr, rws, pbuf, -1.0, 2, partial_rr, mask,
                       (hipStream_t)stream);
     return (int)hipGetLastError();
 }

@@ -164,6 +164,7 @@ struct mgrit_handle {
     float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
     double *mx_scale = nullptr, *mx_eta2 = nullptr, *pout = nullptr;
     int* mx_oact = nullptr;
+    int* mx_need = nullptr;                  // slices whose iterate gets an FP64 residual after a step
     int* mx_trust = nullptr;                 // 2 x Smax: settled slices of a refinement step (parity buffers)
     long long refine_count = 0;             // refinement steps summed over slices
     int* act[2] = {nullptr, nullptr};
@@ -834,6 +835,7 @@ int alloc_workspace(mgrit_handle* h, int S) {
         CHK(dalloc(h, &h->mx_scale, S));
         CHK(dalloc(h, &h->mx_eta2, S));
         CHK(dalloc(h, &h->mx_oact, S));
+        CHK(dalloc(h, &h->mx_need, S));
         CHK(dalloc(h, &h->mx_trust, 2 * (size_t)S));
         if (h->opt.precond == MGRIT_PRECOND_FD_BF16) {
             // written where r32 is (only inside n_x x n_y): the padding stays zero
@@ -898,11 +900,13 @@ int op_rhs(mgrit_handle* h, int tv, const Pass& ps, const double* ubase, const d
     return launch_rhs(&h->geom, &h->seqs, tv, ps.d, ps.S, ubase, fbase, h->b, h->pbb, h->stream);
 }
 
-int op_resid(mgrit_handle* h, int tv, const Pass& ps, const double* xbase, double* partial) {
+// (mask: the slices to recompute, the others keep r and their partials; null: all)
+int op_resid(mgrit_handle* h, int tv, const Pass& ps, const double* xbase, double* partial,
+             const int* mask = nullptr) {
     if (h->use_fft)
-        return launch_fft_init_residual(&h->geom, &h->plan, ps.d, ps.S, xbase, h->b, h->r, partial, h->pfft,
+        return launch_fft_init_residual(&h->geom, &h->plan, ps.d, ps.S, xbase, h->b, h->r, partial, h->pfft, mask,
                                         h->stream);
-    return launch_init_residual(&h->geom, &h->seqs, tv, ps.d, ps.S, xbase, h->b, h->r, partial, h->stream);
+    return launch_init_residual(&h->geom, &h->seqs, tv, ps.d, ps.S, xbase, h->b, h->r, partial, mask, h->stream);
 }
 
 int op_cg(mgrit_handle* h, int tv, const Pass& ps, const double* pin, double* qout, const int* act) {
@@ -1269,7 +1273,8 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
             std::memcpy(h->h_iters_step + (size_t)outer * h->Smax, h->h_iters, S * sizeof(int));
             nrec = outer + 1;
         }
-        HIPCHK(launch_mx_refine(g, ps.d, S, xbase, h->d32, h->mx_scale, h->mx_oact, st));
+        int* trust_next = h->mx_trust + (size_t)((outer + 1) & 1) * h->Smax;
+        HIPCHK(launch_mx_refine(g, ps.d, S, xbase, h->d32, h->mx_scale, h->mx_oact, trust_next, h->mx_need, st));
         // An inner solve whose target was the pass tolerance itself and at least 10 x the FP32 floor
         // (inner flag 2) settles its slice by its own test: the FP32 residual it reached agrees with the
         // FP64 one to FP32 rounding (about 1e-6 of the step's starting residual, 1 % of the smallest such
@@ -1277,7 +1282,7 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
         // of the step is one of them the pass ends here.  Steps that ran to the floor (the first ones at
         // tight tolerances) are checked in FP64.
         if (untrusted == 0 || all32) break;
-        HIPCHK(op_resid(h, tv, ps, xbase, h->pout));
+        HIPCHK(op_resid(h, tv, ps, xbase, h->pout, h->mx_need));
     }
     HIPCHK(launch_add_g(g, ps.d, S, xbase, gbase, st));
     if (h->prof_on) {
@@ -2168,7 +2173,7 @@ int mgrit_footprint(const mgrit_problem* p, const mgrit_options* o, int mem, siz
     }
     if (o->precision != MGRIT_PREC_FP64) {
         b += 4.0 * (2 * (npx + 96) + 1) * 2 + 4.0 * (2 * (npy + 96) + 1) * 2;          // FP32 sequences
-        b += 4.0 * 5 * smax * st + 28.0 * smax;                                        // FP32 workspace, flags
+        b += 4.0 * 5 * smax * st + 32.0 * smax;                                        // FP32 workspace, flags
         d += smax * pmax * (pc ? 1 : 3);                                                // partials
     }
     const double total = 8 * d + b + desc + smax * 12;

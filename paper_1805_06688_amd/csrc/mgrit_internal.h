@@ -151,7 +151,7 @@ int launch_cg_init_x(const Geom* g, const PropDesc* desc, int S, const double* u
                      int warm, double* xbase, void* stream);
 // r[s] = b[s] - (M x + theta_lhs A x), partial of ||r||^2.
 int launch_init_residual(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc, int S, const double* xbase,
-                         const double* bws, double* rws, double* partial_rr, void* stream);
+                         const double* bws, double* rws, double* partial_rr, const int* mask, void* stream);
 // q = B p for active slices, partial p.q.
 int launch_cg_apply(const Geom* g, const Seqs* sq, int tv, const PropDesc* desc, int S, const double* pws,
                     double* qws, double* partial_pq, const int* active, void* stream);
@@ -216,7 +216,7 @@ int launch_mx_direction(const Geom* g, int S, const float* z32, float* p32, cons
                         void* stream);
 // x += scale[s] d32 where oact[s].
 int launch_mx_refine(const Geom* g, const PropDesc* desc, int S, double* xbase, const float* d32,
-                     const double* scale, const int* oact, void* stream);
+                     const double* scale, const int* oact, const int* trust, int* need, void* stream);
 
 // ---- operator by FFT (same results as the tiled kernels up to rounding; one
 // partial per workgroup of the y pass, nby per slice; pbuf: S slices) ----
@@ -226,7 +226,7 @@ int launch_fft_apply(const Geom* g, const FftPlan* pl, const ApplyDesc* desc, in
 int launch_fft_rhs(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const double* ubase,
                    const double* fbase, double* bws, double* partial_bb, double* pbuf, void* stream);
 int launch_fft_init_residual(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const double* xbase,
-                             const double* bws, double* rws, double* partial_rr, double* pbuf, void* stream);
+                             const double* bws, double* rws, double* partial_rr, double* pbuf, const int* mask, void* stream);
 int launch_fft_cg_apply(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const double* pws,
                         double* qws, double* partial_pq, const int* active, double* pbuf, void* stream);
 int launch_fft_apply32(const Geom* g, const FftPlan* pl, const PropDesc* desc, int S, const float* p32, float* q32,
