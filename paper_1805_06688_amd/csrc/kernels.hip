@@ -1795,6 +1795,11 @@ __device__ __forceinline__ void fft_operands(const Geom& g, const void* desc, in
 // One line pass of the FFT operator.  DIR 0: lines along x, writes
 // pbuf = M v + theta X.  DIR 1: lines along y; out = add + sign (pbuf + theta Y)
 // and, with dot_mode, the block's partial of v.out (1) or out.out (2).
+// The CG product (MODE 2: no added vector) takes v.out from the spectra: a zero-padded
+// real line v and the real output y = sum_k W_k exp(2 pi i j k / L) of its pass give
+// sum_j v_j y_j = sum_k Re(conj(V_k) W_k), V the forward transform of v.  The x pass
+// writes sign v.pbuf at partial entry nby + blk, the y pass sign theta v.Y at entry blk,
+// so the product's nbx + nby partials sum to v.out and no pass reads v twice.
 template <typename T, typename TV, typename TA, int DIR, int MODE, int L>
 __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const void* __restrict__ desc, int S,
                                          const TV* vbase, const void* wsin, const TA* addbase, T* outbase, T* pbuf,
@@ -1896,6 +1901,8 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
     // ---- spectra of the output pair (lines oa = l0 + 2 wave, ob = oa + 1) ----
     const int oa = l0 + 2 * wave, ob = oa + 1;
     const bool work = wave < 7 && oa < nl;
+    const bool sdot_on = MODE == 2 && dot_mode == 1;
+    double sdot = 0.0;                       // this lane's terms of sum_k Re(conj(V_k) W_k), both lines
     if (work) {
         const cpx<T>* Z1 = buf;              // lines oa - 1, oa
         const cpx<T>* Z2 = buf + FPAD;       // lines oa + 1, oa + 2
@@ -1915,7 +1922,9 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
         constexpr int NH = NP / 2;
         const int src = (64 - lane) & 63;
         // packed output at k (own) and at L - k (mirror) of row r
-        auto combine = [&](int r, cpx<T>& own, cpx<T>& mirror) {
+        // (wgt: how often the lane's k stands in the sum over k = 0 .. L - 1: 1 at 0 and L / 2, 2 for the
+        // pairs k, L - k, 0 for a row another lane has counted)
+        auto combine = [&](int r, cpx<T>& own, cpx<T>& mirror, int wgt) {
             const int k = lane + 64 * r, kk = (FL - k) & (FL - 1);
             const cpx<T> z1 = Z1[fpidx<L>(k)], z1c = Z1[fpidx<L>(kk)], z2 = Z2[fpidx<L>(k)], z2c = Z2[fpidx<L>(kk)];
             // unpack: first line (z + conj z(-k)) / 2, second line (z - conj z(-k)) / (2 i)
@@ -1935,19 +1944,20 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
             const cpx<T> xa = {c1 * v0.x + c2.x * sa.x - c2.y * da.y, c1 * v0.y + c2.x * sa.y + c2.y * da.x};
             const cpx<T> xb = {c1 * vp.x + c2.x * sb.x - c2.y * db.y, c1 * vp.y + c2.x * sb.y + c2.y * db.x};
             // W = xa + i xb; the inverse transform is conj(FFT(conj W)); at L - k, conj W = xa - i xb
+            if (sdot_on) sdot += (double)wgt * (double)((v0.x * xa.x + v0.y * xa.y) + (vp.x * xb.x + vp.y * xb.y));
             own = {xa.x - xb.y, -(xa.y + xb.x)};
             mirror = {xa.x + xb.y, xa.y - xb.x};
         };
 #pragma unroll
         for (int r = 0; r < NH; ++r) {
             cpx<T> m;
-            combine(r, a[r], m);
+            combine(r, a[r], m, (r == 0 && lane == 0) ? 1 : 2);
             const cpx<T> got = {__shfl(m.x, src, 64), __shfl(m.y, src, 64)};
             if (lane != 0) a[NP - 1 - r] = got;
             if (r > 0 && lane == 0) a[NP - r] = m;
         }
         cpx<T> mid, unused;
-        combine(NH, mid, unused);
+        combine(NH, mid, unused, lane == 0 ? 1 : 0);
         if (lane == 0) a[NH] = mid;
     }
     __syncthreads();
@@ -1963,6 +1973,10 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
                     if (ob < nl) P[(long long)ob * nx + pos] = -a[r].y;
                 }
             }
+        }
+        if (sdot_on) {
+            sdot = block_sum8(sdot, red);
+            if (tid == 0) partial[(long long)s * g.pmax + pl.nby + blk] = sign_d * sdot;
         }
         return;
     }
@@ -1994,7 +2008,7 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
             const long long o = (long long)j * nx + i;
             pv[q] = in ? P[o] : T(0);
             av[q] = (in && add) ? (T)add[o] : T(0);
-            cv[q] = (in && dot_mode == 1) ? (T)v[o] : T(0);
+            cv[q] = (in && dot_mode == 1 && !sdot_on) ? (T)v[o] : T(0);
         }
 #pragma unroll
         for (int q = 0; q < FG; ++q) {
@@ -2003,12 +2017,12 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
             if (e0 + q >= FE || j >= ny || i >= nx) continue;
             const T val = sign * (pv[q] + theta * stg[j * 15 + c]) + av[q];
             out[(long long)j * nx + i] = val;
-            if (dot_mode == 1) dot += (double)cv[q] * (double)val;
+            if (dot_mode == 1 && !sdot_on) dot += (double)cv[q] * (double)val;
             else if (dot_mode == 2) dot += (double)val * (double)val;
         }
     }
     if (dot_mode) {
-        dot = block_sum8(dot, red);
+        dot = block_sum8(sdot_on ? sign_d * (double)theta * sdot : dot, red);
         if (tid == 0) partial[(long long)s * g.pmax + blk] = dot;
     }
 }

@@ -145,6 +145,7 @@ struct mgrit_handle {
     double* pfft = nullptr;
     float* pfft32 = nullptr;
     int nop = 0;                             // operator partials per slice
+    int nop_pq = 0;                          // partials of the CG product's p.q (both FFT passes write them)
     std::vector<double> host_seq_x, host_seq_y;
     double cx = 0, cy = 0;
     std::vector<Level> lv;
@@ -1134,7 +1135,7 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
         if (prof) CHK(prof_record(h, tv));
         HIPCHK(op_cg(h, tv, ps, h->p, h->q, h->act[c0]));
         if (prof) CHK(prof_record(h, MGRIT_PROF_UPDATE64));
-        HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, prho[c0], nr, h->ppq, nop, h->prr[nxt],
+        HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, prho[c0], nr, h->ppq, h->nop_pq, h->prr[nxt],
                                 h->act[c0], st));
         if (prof && pc) CHK(prof_record(h, MGRIT_PROF_PRECOND));
         if (pc) HIPCHK(precondition(h->prz[nxt], h->act[c0]));
@@ -1191,9 +1192,9 @@ int run_pass_mixed(mgrit_handle* h, const Pass& ps, const double* ubase, double*
     const double eta = h->opt.inner_rtol > 0.0 ? h->opt.inner_rtol : 1e-5;
     const bool pc = h->opt.precond == MGRIT_PRECOND_FD_BF16;
     const int nop = h->nop, npc = g->ntiles[1], nc = g->nchunk;
-    // partials of the inner operator: one per 32 x 32 block from the tiled kernels (dense FP32, split
-    // BF16), one per y-pass workgroup from the FFT passes
-    const int nop32 = (h->use_fft && h->opt.precision != MGRIT_PREC_MIXED_BF16) ? h->nop : g->ntiles[1];
+    // p.q partials of the inner operator: one per 32 x 32 block from the tiled kernels (dense FP32, split
+    // BF16), one per workgroup of either pass from the FFT passes
+    const int nop32 = (h->use_fft && h->opt.precision != MGRIT_PREC_MIXED_BF16) ? h->nop_pq : g->ntiles[1];
     const int maxit = h->opt.cg_maxit;
     const bool prof = h->prof_on;
     int tv = 0, tv32 = -1, op32_class = MGRIT_PROF_OP32_T64;
@@ -1631,8 +1632,11 @@ int setup_impl(const mgrit_problem* probs, int nprob, const mgrit_options* opt, 
         }
     }
     h->use_fft = o.op == MGRIT_OP_FFT || (o.op == MGRIT_OP_AUTO && fft_fits);
-    if (h->use_fft) g.pmax = std::max(g.pmax, (int)((nx + MGRIT_FFT_LINES - 1) / MGRIT_FFT_LINES));
-    h->nop = h->use_fft ? (int)((nx + MGRIT_FFT_LINES - 1) / MGRIT_FFT_LINES) : g.ntiles[1];
+    const int fft_nby = (int)((nx + MGRIT_FFT_LINES - 1) / MGRIT_FFT_LINES);    // y-pass workgroups
+    const int fft_nbx = (int)((ny + MGRIT_FFT_LINES - 1) / MGRIT_FFT_LINES);    // x-pass workgroups
+    if (h->use_fft) g.pmax = std::max(g.pmax, fft_nby + fft_nbx);
+    h->nop = h->use_fft ? fft_nby : g.ntiles[1];
+    h->nop_pq = h->use_fft ? fft_nby + fft_nbx : g.ntiles[1];
     g.seq_off_x = g.tiles_x[0] * 64 + 64 + MGRIT_KC;
     g.seq_off_y = g.tiles_y[0] * 64 + 64 + MGRIT_KC;
     g.q1 = o.element == MGRIT_ELEMENT_Q1 ? 1 : 0;
@@ -2168,7 +2172,8 @@ int mgrit_footprint(const mgrit_problem* p, const mgrit_options* o, int mem, siz
     const bool fft = o->op == MGRIT_OP_FFT ||
                      (o->op == MGRIT_OP_AUTO && 2 * nx - 1 <= MGRIT_FFT_LEN && 2 * ny - 1 <= MGRIT_FFT_LEN);
     if (fft) {
-        d += smax * st + 14.0 * MGRIT_FFT_LEN + smax * std::ceil(nx / MGRIT_FFT_LINES) * 7;   // x-pass ws, tables
+        d += smax * st + 14.0 * MGRIT_FFT_LEN +                                       // x-pass ws, tables
+             smax * (std::ceil(nx / MGRIT_FFT_LINES) + std::ceil(ny / MGRIT_FFT_LINES)) * 7;   // partials
         if (o->precision != MGRIT_PREC_FP64) b += 4.0 * smax * st + 4.0 * 14 * MGRIT_FFT_LEN;
     }
     if (o->precision != MGRIT_PREC_FP64) {
