@@ -1795,11 +1795,13 @@ __device__ __forceinline__ void fft_operands(const Geom& g, const void* desc, in
 // One line pass of the FFT operator.  DIR 0: lines along x, writes
 // pbuf = M v + theta X.  DIR 1: lines along y; out = add + sign (pbuf + theta Y)
 // and, with dot_mode, the block's partial of v.out (1) or out.out (2).
-// The CG product (MODE 2: no added vector) takes v.out from the spectra: a zero-padded
+// The FP32 CG product (MODE 2: no added vector) takes v.out from the spectra: a zero-padded
 // real line v and the real output y = sum_k W_k exp(2 pi i j k / L) of its pass give
 // sum_j v_j y_j = sum_k Re(conj(V_k) W_k), V the forward transform of v.  The x pass
 // writes sign v.pbuf at partial entry nby + blk, the y pass sign theta v.Y at entry blk,
-// so the product's nbx + nby partials sum to v.out and no pass reads v twice.
+// so the product's nbx + nby partials sum to v.out and no pass reads v twice.  The FP64
+// product, whose CG runs to tolerances near its rounding level, sums v.out from the values
+// written (nby partials).
 template <typename T, typename TV, typename TA, int DIR, int MODE, int L>
 __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const void* __restrict__ desc, int S,
                                          const TV* vbase, const void* wsin, const TA* addbase, T* outbase, T* pbuf,
@@ -1901,7 +1903,7 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
     // ---- spectra of the output pair (lines oa = l0 + 2 wave, ob = oa + 1) ----
     const int oa = l0 + 2 * wave, ob = oa + 1;
     const bool work = wave < 7 && oa < nl;
-    const bool sdot_on = MODE == 2 && dot_mode == 1;
+    const bool sdot_on = MODE == 2 && dot_mode == 1 && sizeof(T) == 4;
     double sdot = 0.0;                       // this lane's terms of sum_k Re(conj(V_k) W_k), both lines
     if (work) {
         const cpx<T>* Z1 = buf;              // lines oa - 1, oa
@@ -1960,8 +1962,14 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
         combine(NH, mid, unused, lane == 0 ? 1 : 0);
         if (lane == 0) a[NH] = mid;
     }
+    if (sdot_on) {                           // per-wave sums, read after the barrier below
+        sdot = wave_sum(sdot);
+        if (lane == 0) red[wave] = sdot;
+    }
     __syncthreads();
     if (work) fft<T, L>(a, buf, tw, lane);      // a[r] = conj of the packed output at lane + 64 r
+    // the block's spectral sum (nothing writes red after the barrier above on this path)
+    auto sdot_blk = [&]() { return ((red[0] + red[1]) + (red[2] + red[3])) + ((red[4] + red[5]) + (red[6] + red[7])); };
 
     if (DIR == 0) {
         if (work) {
@@ -1974,10 +1982,7 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
                 }
             }
         }
-        if (sdot_on) {
-            sdot = block_sum8(sdot, red);
-            if (tid == 0) partial[(long long)s * g.pmax + pl.nby + blk] = sign_d * sdot;
-        }
+        if (sdot_on && tid == 0) partial[(long long)s * g.pmax + pl.nby + blk] = sign_d * sdot_blk();
         return;
     }
     // ---- y pass: stage Y as [row][column] and apply the epilogue with theta ----
@@ -2021,8 +2026,10 @@ __device__ __forceinline__ void fft_line(const Geom& g, const FftPlan& pl, const
             else if (dot_mode == 2) dot += (double)val * (double)val;
         }
     }
-    if (dot_mode) {
-        dot = block_sum8(sdot_on ? sign_d * (double)theta * sdot : dot, red);
+    if (sdot_on) {
+        if (tid == 0) partial[(long long)s * g.pmax + blk] = sign_d * (double)theta * sdot_blk();
+    } else if (dot_mode) {
+        dot = block_sum8(dot, red);
         if (tid == 0) partial[(long long)s * g.pmax + blk] = dot;
     }
 }

@@ -145,7 +145,7 @@ struct mgrit_handle {
     double* pfft = nullptr;
     float* pfft32 = nullptr;
     int nop = 0;                             // operator partials per slice
-    int nop_pq = 0;                          // partials of the CG product's p.q (both FFT passes write them)
+    int nop_pq = 0;                          // p.q partials of the FP32 CG product (both FFT passes write them)
     std::vector<double> host_seq_x, host_seq_y;
     double cx = 0, cy = 0;
     std::vector<Level> lv;
@@ -1135,7 +1135,7 @@ int run_pass(mgrit_handle* h, const Pass& ps, const double* ubase, double* xbase
         if (prof) CHK(prof_record(h, tv));
         HIPCHK(op_cg(h, tv, ps, h->p, h->q, h->act[c0]));
         if (prof) CHK(prof_record(h, MGRIT_PROF_UPDATE64));
-        HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, prho[c0], nr, h->ppq, h->nop_pq, h->prr[nxt],
+        HIPCHK(launch_cg_update(g, ps.d, S, xbase, h->r, h->p, h->q, prho[c0], nr, h->ppq, nop, h->prr[nxt],
                                 h->act[c0], st));
         if (prof && pc) CHK(prof_record(h, MGRIT_PROF_PRECOND));
         if (pc) HIPCHK(precondition(h->prz[nxt], h->act[c0]));
